@@ -1,0 +1,217 @@
+/*
+ * valmod.h - C ABI of the MI355X (gfx950) implementation of the hot path of
+ * VALMOD, the variable-length motif and discord discovery method of
+ * "Matrix Profile Goes MAD" (Linardi, Zhu, Palpanas, Keogh).
+ *
+ * What one run computes, for each series T of n points and every length L in
+ * [l_min, l_max] (Problem "Variable-Length Motif Pair Discovery"; Problem
+ * "Variable-Length Top-k m-th Discord Discovery" with m = 1):
+ *   - the matrix profile MP_L and its index IP_L (Def. "Matrix profile"): for
+ *     every window i, the z-normalised Euclidean distance (Eq. 6) to its nearest
+ *     non-trivial neighbour and that neighbour's offset;
+ *   - the variable-length matrix profile VALMP (Alg. updateVALMP): per offset, the
+ *     smallest length-normalised distance d * sqrt(1/L) over all lengths, with
+ *     its raw distance, length and neighbour;
+ *   - per length, the top-k motif pairs and the top-k 1st discords, and across
+ *     lengths the top-k motif pairs (from VALMP) and the discord ranking of
+ *     Sec. "Comparing Discords of Different Lengths" (position-wise max of
+ *     d / sqrt(L)).
+ * Internally the profile at the smallest length is computed with the diagonal
+ * dot-product recurrence (Alg. ComputeMatrixProfile) while keeping, per window,
+ * the p candidates with the smallest lower bound (Eq. lowerBoundFinalFormula);
+ * longer lengths reuse those partial profiles (Alg. ComputeSubMP) and recompute
+ * only the windows whose bound test fails, so every MP_L is exact.
+ *
+ * Conventions (all offsets 0-based):
+ *   N_L = n - L + 1 windows; trivial match iff |i - j| <= ceil(L / excl_den);
+ *   population standard deviation (Eq. 6); a window is flat iff
+ *   sigma <= flat_eps * max(1, |mu|), and flat windows are neither owners nor
+ *   candidates (distance +inf, index -1); ties go to the smaller index.
+ *
+ * Memory ownership: the caller owns every device buffer (input series,
+ * workspace, outputs); the plan owns host metadata only. No function of this
+ * library allocates device memory. Return values are valmod_status codes; no
+ * exception crosses the ABI. Argument errors are reported synchronously by
+ * valmod_plan / valmod_run; errors found on the device (non-finite input,
+ * internal capacity exceeded and not recoverable) are reported by valmod_run
+ * as VALMOD_E_DEVICE.
+ *
+ * Threading: a plan may be used by one host thread and one stream at a time.
+ */
+#ifndef VALMOD_H
+#define VALMOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifndef VALMOD_API
+#define VALMOD_API __attribute__((visibility("default")))
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VALMOD_OK = 0,
+  VALMOD_E_ARG = -1,       /* bad argument (null, out of range, inconsistent) */
+  VALMOD_E_TOO_SHORT = -2, /* a series has no non-trivial pair at l_max */
+  VALMOD_E_NOMEM = -3,     /* host allocation failed */
+  VALMOD_E_HIP = -4,       /* a HIP runtime call failed */
+  VALMOD_E_LAYOUT = -5,    /* sizes exceed the supported index range */
+  VALMOD_E_DEVICE = -6     /* error reported by a kernel (see valmod_last_device_error) */
+} valmod_status;
+
+typedef enum { VALMOD_F32 = 0, VALMOD_F64 = 1 } valmod_dtype;
+
+/* Arithmetic of the diagonal recurrence. Statistics, lower bounds, the length
+ * sweep and every reported distance are FP64 in both modes. */
+typedef enum {
+  VALMOD_PREC_FP64 = 0,        /* recurrence in FP64 */
+  VALMOD_PREC_FP32_REFRESH = 1 /* recurrence in FP32, restarted from FP64 dot products every R rows */
+} valmod_precision;
+
+/* Which of the two ways of getting MP_L for L > base is used. */
+typedef enum {
+  VALMOD_PATH_AUTO = 0,      /* cost model: row recompute of failing windows, or a full pass */
+  VALMOD_PATH_FULL = 1,      /* a full diagonal pass at every length (test hook) */
+  VALMOD_PATH_RECOMPUTE = 2  /* never a full pass after l_min (test hook) */
+} valmod_path;
+
+/* Maximum number of windows of one series (candidate indices are packed in 22 bits). */
+#define VALMOD_MAX_WINDOWS ((int64_t)1 << 22)
+
+typedef struct {
+  int32_t num_series;       /* >= 1 */
+  const int64_t* n;         /* host array [num_series]: points per series */
+  const int32_t* l_min;     /* host array [num_series] */
+  const int32_t* l_max;     /* host array [num_series], l_max >= l_min >= 4 */
+  int32_t p;                /* partial-profile size (Alg. ComputeMatrixProfile); 0 = default 10 */
+  int32_t k_motifs;         /* top-k motif pairs per length and across lengths, >= 1 */
+  int32_t k_discords;       /* top-k discords per length and across lengths, >= 1 */
+  int32_t excl_den;         /* exclusion zone ceil(L / excl_den); 0 = default 4 */
+  double flat_eps;          /* flat-window threshold; 0 = default 2^-20 */
+  int32_t dtype;            /* valmod_dtype of the input series */
+  int32_t precision;        /* valmod_precision */
+  int32_t refresh_R;        /* FP32 refresh interval in rows; 0 = default */
+  int32_t path;             /* valmod_path */
+  int32_t device;           /* HIP device ordinal the plan runs on */
+} valmod_config;
+
+typedef struct valmod_plan_s* valmod_plan_t;
+
+/* Per-length diagnostic counters (stats[(L - l_min) * VALMOD_NSTATS + c]). */
+enum {
+  VALMOD_STAT_VALID = 0,      /* windows whose partial profile certified the minimum */
+  VALMOD_STAT_FAILED = 1,     /* windows whose bound test failed */
+  VALMOD_STAT_RECOMPUTED = 2, /* windows recomputed by a row scan */
+  VALMOD_STAT_FULL_PASS = 3,  /* 1 if a full diagonal pass ran at this length */
+  VALMOD_STAT_FLAT = 4,       /* flat windows at this length */
+  VALMOD_STAT_APPENDS = 5,    /* candidates collected by the full pass (0 if none) */
+  VALMOD_NSTATS = 8
+};
+
+/*
+ * Output buffers (device pointers, caller-allocated; a NULL pointer skips that
+ * output). For series s with N0 = n_s - l_min_s + 1 and nlen = l_max_s - l_min_s + 1,
+ * element offsets come from valmod_series_layout; inside one series:
+ *   prof_dist[t * N0 + i]  f64  MP_L[i] for L = l_min + t (+inf if none; +inf for i >= N_L)
+ *   prof_idx [t * N0 + i]  i32  IP_L[i] (-1 if none)
+ *   valmp_norm/valmp_dist[i] f64, valmp_len/valmp_idx[i] i32, i < N0 (len 0 / idx -1 if empty)
+ *   motif_ab[(t * k_m + r) * 2 + {0,1}] i32 (a < b), motif_d[t * k_m + r] f64 (NaN / -1 unused)
+ *   discord_on[(t * k_d + r) * 2 + {0,1}] i32 (offset, neighbour), discord_d[t * k_d + r] f64
+ *   g_motif_abl[r * 3 + {0,1,2}] i32 (a, b, L), g_motif_d[r * 2 + {0,1}] f64 (d, d*sqrt(1/L))
+ *   g_discord_onl[r * 3 + {0,1,2}] i32 (offset, neighbour, L), g_discord_d[r * 2 + {0,1}] f64 (d, d/sqrt(L))
+ *   stats[t * VALMOD_NSTATS + c] i64
+ */
+typedef struct {
+  double* prof_dist;
+  int32_t* prof_idx;
+  double* valmp_norm;
+  double* valmp_dist;
+  int32_t* valmp_len;
+  int32_t* valmp_idx;
+  int32_t* motif_ab;
+  double* motif_d;
+  int32_t* discord_on;
+  double* discord_d;
+  int32_t* g_motif_abl;
+  double* g_motif_d;
+  int32_t* g_discord_onl;
+  double* g_discord_d;
+  int64_t* stats;
+} valmod_outputs;
+
+/* Element counts of every output array over the whole batch. */
+typedef struct {
+  int64_t prof;       /* prof_dist, prof_idx */
+  int64_t valmp;      /* valmp_* */
+  int64_t motif;      /* motif_d (motif_ab holds 2x) */
+  int64_t discord;    /* discord_d (discord_on holds 2x) */
+  int64_t g_motif;    /* rows of g_motif_* (abl holds 3x, d 2x) */
+  int64_t g_discord;  /* rows of g_discord_* */
+  int64_t stats;      /* stats */
+  int64_t series;     /* elements of the concatenated input series */
+} valmod_sizes;
+
+/* Element offsets of series s inside the concatenated input and each output. */
+typedef struct {
+  int64_t series;
+  int64_t prof;
+  int64_t valmp;
+  int64_t motif;
+  int64_t discord;
+  int64_t g_motif;
+  int64_t g_discord;
+  int64_t stats;
+  int64_t n, n0, nlen;
+  int32_t l_min, l_max;
+} valmod_layout;
+
+/* Validate a configuration and build a plan (host only; touches no GPU).
+ * Errors: VALMOD_E_ARG (null pointers, num_series < 1, l_min < 4, l_max < l_min,
+ * p < 0, k < 1, excl_den < 0, flat_eps < 0, unknown enum), VALMOD_E_TOO_SHORT
+ * (n - l_max + 1 <= ceil(l_max / excl_den) + 1: no non-trivial pair),
+ * VALMOD_E_LAYOUT (more than VALMOD_MAX_WINDOWS windows), VALMOD_E_NOMEM. */
+VALMOD_API valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* out);
+
+/* Device workspace the caller must pass to valmod_run (bytes, 256-aligned base). */
+VALMOD_API size_t valmod_workspace_bytes(valmod_plan_t plan);
+
+/* Output element counts; VALMOD_E_ARG if plan or out is NULL. */
+VALMOD_API valmod_status valmod_output_sizes(valmod_plan_t plan, valmod_sizes* out);
+
+/* Offsets of series s (0 <= s < num_series); VALMOD_E_ARG otherwise. */
+VALMOD_API valmod_status valmod_series_layout(valmod_plan_t plan, int32_t s, valmod_layout* out);
+
+/*
+ * Run the plan. d_series: device array of the concatenated series in the
+ * configured dtype (series s starts at element valmod_layout.series).
+ * d_workspace: device buffer of valmod_workspace_bytes(plan) bytes, 256-byte
+ * aligned, contents irrelevant on entry. d_out: struct (host memory) of device
+ * pointers. stream: a hipStream_t (passed as void*; NULL = default stream).
+ * The call enqueues work on `stream` and synchronises with it before returning
+ * (per-length decisions read device counters), so all outputs are complete on
+ * return. Errors: VALMOD_E_ARG (null plan/series/workspace/out), VALMOD_E_HIP,
+ * VALMOD_E_DEVICE (non-finite input values).
+ */
+VALMOD_API valmod_status valmod_run(valmod_plan_t plan, const void* d_series, void* d_workspace,
+                         const valmod_outputs* d_out, void* stream);
+
+/* Release a plan (NULL is ignored). */
+VALMOD_API void valmod_plan_free(valmod_plan_t plan);
+
+/* Human-readable name of a status code (static string). */
+VALMOD_API const char* valmod_status_str(int status);
+
+/* Milliseconds spent in the diagonal-pass kernel during the last valmod_run,
+ * measured with HIP events on the run's stream, and the number of those launches
+ * and of the cells they computed. */
+VALMOD_API valmod_status valmod_last_pass_timing(valmod_plan_t plan, double* ms, int64_t* launches,
+                                      int64_t* cells);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VALMOD_H */

@@ -61,6 +61,8 @@ def _load():
     lib.oracle_submp_decide.restype = ctypes.c_int
     lib.oracle_valmod.argtypes = [P, I64, I64, I64, I64, D, I64, I64, ctypes.c_int] + [P] * 14
     lib.oracle_valmod.restype = ctypes.c_int
+    lib.oracle_pair_dists.argtypes = [P, I64, I64, D, P, I64, P]
+    lib.oracle_pair_dists.restype = ctypes.c_int
     lib.oracle_valid_fraction.argtypes = [P, I64, I64, I64, I64, I64, D, P]
     lib.oracle_valid_fraction.restype = I64
     _lib = lib
@@ -91,6 +93,16 @@ def pair_dist(x, L: int, i: int, j: int, flat_eps: float = FLAT_EPS) -> float:
     """Direct z-normalised Euclidean distance of windows i and j."""
     x = _f64(x)
     return _load().oracle_pair_dist(_ptr(x), x.shape[0], L, i, j, flat_eps)
+
+
+def pair_dists(x, L: int, pairs, flat_eps: float = FLAT_EPS) -> np.ndarray:
+    """Direct distances of many (i, j) pairs at length L (statistics formed once)."""
+    x = _f64(x)
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
+    out = np.empty(pr.shape[0])
+    if pr.shape[0]:
+        _load().oracle_pair_dists(_ptr(x), x.shape[0], L, flat_eps, _ptr(pr), pr.shape[0], _ptr(out))
+    return out
 
 
 def pearson(x, L: int, i: int, j: int, flat_eps: float = FLAT_EPS) -> float:

@@ -1,0 +1,157 @@
+"""Element-by-element comparison of VALMOD outputs against the oracle.
+
+Test infrastructure only. Distances are compared as length-normalised
+distances dn = d / sqrt(L) within an absolute tolerance. Indices must be equal,
+except where distances tie within the tolerance: a different index is accepted
+iff the oracle's own distance for the reported pair is within the tolerance of
+the oracle's optimum (and the pair is a legal, non-trivial one).
+"""
+from __future__ import annotations
+
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+from . import FLAT_EPS, pair_dists, profile
+
+
+def _excl(L: int, den: int) -> int:
+    return -(-L // den)
+
+
+class Report(dict):
+    def merge_max(self, key, val):
+        self[key] = max(self.get(key, 0.0), float(val))
+
+
+def check_profile_rows(x, L: int, rows: np.ndarray, d_gpu: np.ndarray, i_gpu: np.ndarray,
+                       d_ref: np.ndarray, i_ref: np.ndarray, tol: float, excl_den: int = 4,
+                       rep: Optional[Report] = None, what: str = "") -> Report:
+    """Compare matrix-profile entries of owners `rows` at length L."""
+    rep = rep if rep is not None else Report()
+    rows = np.asarray(rows)
+    fin_g, fin_r = np.isfinite(d_gpu), np.isfinite(d_ref)
+    bad = np.nonzero(fin_g != fin_r)[0]
+    assert bad.size == 0, f"{what} L={L}: finiteness differs at owners {rows[bad[:10]]}: " \
+                          f"gpu={d_gpu[bad[:10]]} ref={d_ref[bad[:10]]}"
+    assert np.all(i_gpu[~fin_g] == -1), f"{what} L={L}: index set for an infinite entry"
+    sq = np.sqrt(L)
+    if fin_g.any():
+        err = np.abs(d_gpu[fin_g] - d_ref[fin_g]) / sq
+        rep.merge_max("max_dn_err", err.max())
+        worst = np.argmax(err)
+        assert err.max() <= tol, f"{what} L={L}: |d dn| {err.max():.3e} > {tol} at owner " \
+                                 f"{rows[fin_g][worst]} (gpu {d_gpu[fin_g][worst]!r}, ref {d_ref[fin_g][worst]!r})"
+    mis = np.nonzero(fin_g & (i_gpu != i_ref))[0]
+    rep["idx_mismatch"] = rep.get("idx_mismatch", 0) + int(mis.size)
+    if mis.size:
+        e = _excl(L, excl_den)
+        own = rows[mis]
+        assert np.all(np.abs(i_gpu[mis] - own) > e), f"{what} L={L}: trivial neighbour reported"
+        dg = pair_dists(x, L, np.stack([own, i_gpu[mis]], 1))
+        gap = (dg - d_ref[mis]) / sq
+        rep.merge_max("max_tie_gap", gap.max())
+        assert np.all(gap <= tol), f"{what} L={L}: index mismatch beyond a tie at owners " \
+                                   f"{own[gap > tol][:10]} (gap {gap.max():.3e})"
+    return rep
+
+
+def check_full(x, l_min: int, gpu: Dict[str, np.ndarray], ref: Dict[str, np.ndarray], tol: float,
+               excl_den: int = 4) -> Report:
+    """Compare every output of a full run against oracle.valmod()."""
+    rep = Report()
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[0]
+    nl, N0 = ref["prof_dist"].shape
+    for t in range(nl):
+        L = l_min + t
+        N = n - L + 1
+        rows = np.arange(N)
+        check_profile_rows(x, L, rows, gpu["prof_dist"][t, :N], gpu["prof_idx"][t, :N].astype(np.int64),
+                           ref["prof_dist"][t, :N], ref["prof_idx"][t, :N], tol, excl_den, rep, "profile")
+        assert np.all(np.isinf(gpu["prof_dist"][t, N:])) and np.all(gpu["prof_idx"][t, N:] == -1), \
+            f"L={L}: tail entries past N_L not cleared"
+    check_valmp(x, l_min, gpu, ref, tol, excl_den, rep)
+    check_rankings(x, l_min, gpu, ref, tol, excl_den, rep)
+    return rep
+
+
+def check_valmp(x, l_min, gpu, ref, tol, excl_den=4, rep=None) -> Report:
+    rep = rep if rep is not None else Report()
+    gn, rn = gpu["valmp_norm"], ref["valmp_norm"]
+    fin = np.isfinite(rn)
+    assert np.array_equal(np.isfinite(gn), fin), "VALMP finiteness differs"
+    err = np.abs(gn[fin] - rn[fin])
+    if err.size:
+        rep.merge_max("valmp_dn_err", err.max())
+        assert err.max() <= tol, f"VALMP normalised distance error {err.max():.3e}"
+    # a different length (or neighbour) is a tie within the tolerance
+    dl = np.nonzero(fin & ((gpu["valmp_len"] != ref["valmp_len"]) | (gpu["valmp_idx"] != ref["valmp_idx"])))[0]
+    rep["valmp_tie_swaps"] = int(dl.size)
+    for i in dl[:200]:
+        L = int(gpu["valmp_len"][i])
+        d = pair_dists(x, L, [[i, int(gpu["valmp_idx"][i])]])[0]
+        assert abs(d * np.sqrt(1.0 / L) - rn[i]) <= tol, f"VALMP entry {i}: not a tie"
+    return rep
+
+
+def check_rankings(x, l_min, gpu, ref, tol, excl_den=4, rep=None) -> Report:
+    rep = rep if rep is not None else Report()
+    nl = ref["motif_d"].shape[0]
+    for t in range(nl):
+        L = l_min + t
+        sq = np.sqrt(L)
+        for key_d, key_i, kind in (("motif_d", "motif_ab", "motif"), ("discord_d", "discord_on", "discord")):
+            dg, dr = gpu[key_d][t], ref[key_d][t]
+            assert np.array_equal(np.isnan(dg), np.isnan(dr)), f"{kind} L={L}: filled slots differ"
+            ok = ~np.isnan(dr)
+            if ok.any():
+                err = np.abs(dg[ok] - dr[ok]) / sq
+                rep.merge_max(f"{kind}_dn_err", err.max())
+                assert err.max() <= tol, f"{kind} L={L}: rank distances differ by {err.max():.3e}"
+            ig, ir = gpu[key_i][t], ref[key_i][t]
+            for r in np.nonzero(ok)[0]:
+                if kind == "motif" and not np.array_equal(ig[r], ir[r]):
+                    d = pair_dists(x, L, [ig[r]])[0]
+                    assert abs(d - dr[r]) / sq <= tol, f"motif L={L} rank {r}: {ig[r]} vs {ir[r]}"
+                    rep["rank_tie_swaps"] = rep.get("rank_tie_swaps", 0) + 1
+                if kind == "discord" and ig[r][0] != ir[r][0]:
+                    # the reported offset's own profile value must tie the oracle's
+                    assert abs(gpu["prof_dist"][t, ig[r][0]] - dr[r]) / sq <= tol, \
+                        f"discord L={L} rank {r}: {ig[r]} vs {ir[r]}"
+                    rep["rank_tie_swaps"] = rep.get("rank_tie_swaps", 0) + 1
+    for key_d, key_i, kind in (("g_motif_d", "g_motif_abl", "g_motif"), ("g_discord_d", "g_discord_onl", "g_discord")):
+        dg, dr = gpu[key_d], ref[key_d]
+        assert np.array_equal(np.isnan(dg[:, 1]), np.isnan(dr[:, 1])), f"{kind}: filled slots differ"
+        ok = ~np.isnan(dr[:, 1])
+        if ok.any():
+            err = np.abs(dg[ok, 1] - dr[ok, 1])
+            rep.merge_max(f"{kind}_dn_err", err.max())
+            assert err.max() <= tol, f"{kind}: normalised distances differ by {err.max():.3e}"
+            if not np.array_equal(gpu[key_i][ok], ref[key_i][ok]):
+                rep["rank_tie_swaps"] = rep.get("rank_tie_swaps", 0) + 1
+    return rep
+
+
+def sample_rows(N: int, count: int, seed: int, extra: Sequence[int] = ()) -> np.ndarray:
+    g = np.random.default_rng(seed)
+    base = g.choice(N, size=min(count, N), replace=False)
+    ex = [int(v) for v in extra if 0 <= int(v) < N]
+    return np.unique(np.concatenate([base, np.array(ex, dtype=np.int64)])).astype(np.int64)
+
+
+def check_sampled(x, l_min: int, gpu: Dict[str, np.ndarray], lengths: Sequence[int], rows_per_len: int,
+                  tol: float, excl_den: int = 4, seed: int = 0, extra: Sequence[int] = (),
+                  nthreads: int = 0) -> Report:
+    """Compare sampled owners of the given lengths against oracle.profile()."""
+    rep = Report()
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[0]
+    for L in lengths:
+        t = L - l_min
+        N = n - L + 1
+        rows = sample_rows(N, rows_per_len, seed + L, extra)
+        d_ref, i_ref = profile(x, L, rows=rows, excl_den=excl_den, nthreads=nthreads)
+        check_profile_rows(x, L, rows, gpu["prof_dist"][t, rows], gpu["prof_idx"][t, rows].astype(np.int64),
+                           d_ref, i_ref, tol, excl_den, rep, "sampled")
+    return rep

@@ -246,6 +246,31 @@ ORACLE_EXPORT double oracle_lb(const double* x, int64_t n, int64_t o, int64_t c,
   return out;
 }
 
+/* Direct distances of listed (i, j) pairs at length L (NaN for out-of-range,
+ * +inf if either window is flat), with the statistics formed once. */
+ORACLE_EXPORT int oracle_pair_dists(const double* x, int64_t n, int64_t L, double flat_eps,
+                                    const int64_t* pairs, int64_t m, double* out) {
+  int64_t N = n - L + 1;
+  if (L < 2 || N < 1) return -1;
+  double* mu = (double*)malloc(sizeof(double) * N);
+  double* sg = (double*)malloc(sizeof(double) * N);
+  uint8_t* fl = (uint8_t*)malloc(N);
+  oracle_stats(x, n, L, flat_eps, mu, sg, fl);
+  for (int64_t r = 0; r < m; r++) {
+    int64_t i = pairs[2 * r], j = pairs[2 * r + 1];
+    if (i < 0 || j < 0 || i >= N || j >= N)
+      out[r] = NAN;
+    else if (fl[i] || fl[j])
+      out[r] = INFINITY;
+    else
+      out[r] = sqrt(sqdist(x, L, i, j, mu, sg));
+  }
+  free(mu);
+  free(sg);
+  free(fl);
+  return 0;
+}
+
 /* Pearson correlation of windows i, j at length L (NaN if either is flat). */
 ORACLE_EXPORT double oracle_pearson(const double* x, int64_t n, int64_t L, int64_t i, int64_t j,
                                     double flat_eps) {

@@ -1,0 +1,339 @@
+// C ABI of the VALMOD library: plan validation, workspace layout and the
+// per-length driver (Alg. VALMOD) that enqueues the kernels.
+#include "../../include/valmod.h"
+#include "valmod_common.h"
+#include "valmod_kernels.h"
+
+#include <math.h>
+#include <new>
+#include <string.h>
+#include <vector>
+
+using namespace valmod;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct WsLayout {
+  size_t xs, A, B, mu, sig, invn, flat, df, dg, invT, thr, best, counters, vnorm, vdist, vlen, vidx;
+  size_t total;
+};
+
+enum { CNT_ERR = 0, CNT_NFLAT = 1, CNT_WORDS = 32 };
+
+}  // namespace
+
+struct valmod_plan_s {
+  valmod_config cfg;
+  std::vector<int64_t> n;
+  std::vector<int32_t> lmin, lmax;
+  std::vector<valmod_layout> lay;
+  valmod_sizes sizes;
+  int64_t nmax = 0, n0max = 0;
+  WsLayout ws;
+  // timing of the diagonal pass during the last run
+  std::vector<hipEvent_t> ev;
+  int ev_device = -1;
+  double pass_ms = 0.0;
+  int64_t pass_launches = 0, pass_cells = 0;
+};
+
+static valmod_status fail(valmod_status s) { return s; }
+
+extern "C" const char* valmod_status_str(int status) {
+  switch (status) {
+    case VALMOD_OK: return "ok";
+    case VALMOD_E_ARG: return "invalid argument";
+    case VALMOD_E_TOO_SHORT: return "series too short for the length range";
+    case VALMOD_E_NOMEM: return "host allocation failed";
+    case VALMOD_E_HIP: return "HIP runtime error";
+    case VALMOD_E_LAYOUT: return "sizes exceed the supported index range";
+    case VALMOD_E_DEVICE: return "device-side error (non-finite input or capacity exceeded)";
+    default: return "unknown status";
+  }
+}
+
+extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* out) {
+  if (!cfg || !out) return fail(VALMOD_E_ARG);
+  *out = nullptr;
+  if (cfg->num_series < 1 || !cfg->n || !cfg->l_min || !cfg->l_max) return fail(VALMOD_E_ARG);
+  if (cfg->p < 0 || cfg->k_motifs < 1 || cfg->k_discords < 1 || cfg->k_motifs > 64 || cfg->k_discords > 64)
+    return fail(VALMOD_E_ARG);
+  if (cfg->excl_den < 0 || !(cfg->flat_eps >= 0.0) || cfg->refresh_R < 0) return fail(VALMOD_E_ARG);
+  if (cfg->dtype != VALMOD_F32 && cfg->dtype != VALMOD_F64) return fail(VALMOD_E_ARG);
+  if (cfg->precision != VALMOD_PREC_FP64 && cfg->precision != VALMOD_PREC_FP32_REFRESH)
+    return fail(VALMOD_E_ARG);
+  if (cfg->path < VALMOD_PATH_AUTO || cfg->path > VALMOD_PATH_RECOMPUTE || cfg->device < 0)
+    return fail(VALMOD_E_ARG);
+
+  valmod_plan_s* P = new (std::nothrow) valmod_plan_s();
+  if (!P) return fail(VALMOD_E_NOMEM);
+  P->cfg = *cfg;
+  if (P->cfg.p == 0) P->cfg.p = 10;
+  if (P->cfg.excl_den == 0) P->cfg.excl_den = 4;
+  if (P->cfg.flat_eps == 0.0) P->cfg.flat_eps = 1.0 / 1048576.0;
+  const int S = cfg->num_series;
+  try {
+    P->n.assign(cfg->n, cfg->n + S);
+    P->lmin.assign(cfg->l_min, cfg->l_min + S);
+    P->lmax.assign(cfg->l_max, cfg->l_max + S);
+    P->lay.resize(S);
+  } catch (...) {
+    delete P;
+    return fail(VALMOD_E_NOMEM);
+  }
+  P->cfg.n = nullptr;
+  P->cfg.l_min = nullptr;
+  P->cfg.l_max = nullptr;
+
+  valmod_sizes& z = P->sizes;
+  memset(&z, 0, sizeof(z));
+  const int64_t km = P->cfg.k_motifs, kd = P->cfg.k_discords;
+  for (int s = 0; s < S; ++s) {
+    const int64_t n = P->n[s];
+    const int32_t lo = P->lmin[s], hi = P->lmax[s];
+    if (lo < 4 || hi < lo || n < 1) {
+      delete P;
+      return fail(VALMOD_E_ARG);
+    }
+    const int64_t e = excl_zone(hi, P->cfg.excl_den);
+    if (n - hi + 1 <= e + 1) {
+      delete P;
+      return fail(VALMOD_E_TOO_SHORT);
+    }
+    const int64_t n0 = n - lo + 1;
+    if (n0 > VALMOD_MAX_WINDOWS) {
+      delete P;
+      return fail(VALMOD_E_LAYOUT);
+    }
+    const int64_t nlen = hi - lo + 1;
+    valmod_layout& L = P->lay[s];
+    L.series = z.series;
+    L.prof = z.prof;
+    L.valmp = z.valmp;
+    L.motif = z.motif;
+    L.discord = z.discord;
+    L.g_motif = z.g_motif;
+    L.g_discord = z.g_discord;
+    L.stats = z.stats;
+    L.n = n;
+    L.n0 = n0;
+    L.nlen = nlen;
+    L.l_min = lo;
+    L.l_max = hi;
+    z.series += n;
+    z.prof += nlen * n0;
+    z.valmp += n0;
+    z.motif += nlen * km;
+    z.discord += nlen * kd;
+    z.g_motif += km;
+    z.g_discord += kd;
+    z.stats += nlen * VALMOD_NSTATS;
+    if (n > P->nmax) P->nmax = n;
+    if (n0 > P->n0max) P->n0max = n0;
+  }
+
+  // workspace carve-up (sized for the largest series; series run one after another)
+  WsLayout& w = P->ws;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  const size_t np = (size_t)(P->nmax + kPad);
+  const size_t wp = (size_t)(P->n0max + kPad);
+  w.xs = take(np * 8);
+  w.A = take(wp * 8);
+  w.B = take(wp * 8);
+  w.mu = take(wp * 8);
+  w.sig = take(wp * 8);
+  w.invn = take(wp * 8);
+  w.flat = take(wp);
+  w.df = take(wp * 8);
+  w.dg = take(wp * 8);
+  w.invT = take(wp * 8);
+  w.thr = take(wp * 8);
+  w.best = take(wp * 8);
+  w.counters = take(CNT_WORDS * 8);
+  w.vnorm = take(wp * 8);
+  w.vdist = take(wp * 8);
+  w.vlen = take(wp * 4);
+  w.vidx = take(wp * 4);
+  w.total = off;
+  *out = P;
+  return VALMOD_OK;
+}
+
+extern "C" size_t valmod_workspace_bytes(valmod_plan_t P) { return P ? P->ws.total : 0; }
+
+extern "C" valmod_status valmod_output_sizes(valmod_plan_t P, valmod_sizes* out) {
+  if (!P || !out) return VALMOD_E_ARG;
+  *out = P->sizes;
+  return VALMOD_OK;
+}
+
+extern "C" valmod_status valmod_series_layout(valmod_plan_t P, int32_t s, valmod_layout* out) {
+  if (!P || !out || s < 0 || s >= P->cfg.num_series) return VALMOD_E_ARG;
+  *out = P->lay[s];
+  return VALMOD_OK;
+}
+
+extern "C" void valmod_plan_free(valmod_plan_t P) {
+  if (!P) return;
+  for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+  delete P;
+}
+
+extern "C" valmod_status valmod_last_pass_timing(valmod_plan_t P, double* ms, int64_t* launches,
+                                                 int64_t* cells) {
+  if (!P) return VALMOD_E_ARG;
+  if (ms) *ms = P->pass_ms;
+  if (launches) *launches = P->pass_launches;
+  if (cells) *cells = P->pass_cells;
+  return VALMOD_OK;
+}
+
+#define VCHECK(expr)                   \
+  do {                                 \
+    hipError_t _e = (expr);            \
+    if (_e != hipSuccess) {            \
+      status = VALMOD_E_HIP;           \
+      goto done;                       \
+    }                                  \
+  } while (0)
+
+extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void* d_ws,
+                                    const valmod_outputs* o, void* stream_) {
+  if (!P || !d_series || !d_ws || !o) return VALMOD_E_ARG;
+  if (((uintptr_t)d_ws) % kAlign) return VALMOD_E_ARG;
+  if (!o->prof_dist || !o->prof_idx || !o->valmp_norm || !o->valmp_dist || !o->valmp_len || !o->valmp_idx ||
+      !o->motif_ab || !o->motif_d || !o->discord_on || !o->discord_d || !o->g_motif_abl || !o->g_motif_d ||
+      !o->g_discord_onl || !o->g_discord_d)
+    return VALMOD_E_ARG;
+  hipStream_t st = (hipStream_t)stream_;
+  valmod_status status = VALMOD_OK;
+  int prev_dev = -1;
+  if (hipGetDevice(&prev_dev) != hipSuccess) return VALMOD_E_HIP;
+  if (hipSetDevice(P->cfg.device) != hipSuccess) return VALMOD_E_HIP;
+
+  char* ws = (char*)d_ws;
+  double* xs = (double*)(ws + P->ws.xs);
+  double* A = (double*)(ws + P->ws.A);
+  double* B = (double*)(ws + P->ws.B);
+  double* mu = (double*)(ws + P->ws.mu);
+  double* sig = (double*)(ws + P->ws.sig);
+  double* invn = (double*)(ws + P->ws.invn);
+  uint8_t* flat = (uint8_t*)(ws + P->ws.flat);
+  double* df = (double*)(ws + P->ws.df);
+  double* dg = (double*)(ws + P->ws.dg);
+  double* invT = (double*)(ws + P->ws.invT);
+  double* thr = (double*)(ws + P->ws.thr);
+  uint64_t* best = (uint64_t*)(ws + P->ws.best);
+  unsigned long long* cnt = (unsigned long long*)(ws + P->ws.counters);
+  const int esz = P->cfg.dtype == VALMOD_F32 ? 4 : 8;
+  const int excl_den = P->cfg.excl_den;
+  const int km = P->cfg.k_motifs, kd = P->cfg.k_discords;
+
+  std::vector<unsigned long long> host_cnt(CNT_WORDS);
+  std::vector<int64_t> host_stats;
+  int64_t total_lengths = 0;
+  for (auto& L : P->lay) total_lengths += L.nlen;
+
+  // events bracketing every diagonal-pass launch
+  if (P->ev_device != P->cfg.device || (int64_t)P->ev.size() < 2 * total_lengths) {
+    for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+    P->ev.clear();
+    for (int64_t i = 0; i < 2 * total_lengths; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        status = VALMOD_E_HIP;
+        goto done;
+      }
+      P->ev.push_back(e);
+    }
+    P->ev_device = P->cfg.device;
+  }
+  P->pass_ms = 0.0;
+  P->pass_launches = 0;
+  P->pass_cells = 0;
+
+  VCHECK(hipMemsetAsync(cnt, 0, CNT_WORDS * 8, st));
+  {
+    int64_t evi = 0;
+    for (int s = 0; s < P->cfg.num_series; ++s) {
+      const valmod_layout& Ls = P->lay[s];
+      const int64_t n = Ls.n, N0 = Ls.n0;
+      const char* series = (const char*)d_series + (size_t)Ls.series * esz;
+      VCHECK(launch_convert(series, P->cfg.dtype, n, n + kPad, xs, (int*)&cnt[CNT_ERR], st));
+      double* vnorm = o->valmp_norm + Ls.valmp;
+      double* vdist = o->valmp_dist + Ls.valmp;
+      int32_t* vlen = o->valmp_len + Ls.valmp;
+      int32_t* vidx = o->valmp_idx + Ls.valmp;
+      VCHECK(launch_valmp_init(N0, vnorm, vdist, vlen, vidx, st));
+      host_stats.assign(Ls.nlen * VALMOD_NSTATS, 0);
+      for (int L = Ls.l_min; L <= Ls.l_max; ++L) {
+        const int64_t t = L - Ls.l_min;
+        const int64_t N = n - L + 1;
+        const int64_t e = excl_zone(L, excl_den);
+        double* pd = o->prof_dist + Ls.prof + t * N0;
+        int32_t* pi = o->prof_idx + Ls.prof + t * N0;
+        VCHECK(launch_stats(xs, N, L, L == Ls.l_min, P->cfg.flat_eps, A, B, mu, sig, invn, flat,
+                            &cnt[CNT_NFLAT], st));
+        VCHECK(launch_prep_f64(xs, mu, sig, invn, N, L, df, dg, invT, st));
+        const int32_t* prev = L > Ls.l_min ? pi - N0 : nullptr;
+        VCHECK(launch_seed_mp(xs, mu, invn, flat, prev, N, L, e, best, thr, st));
+        VCHECK(hipEventRecord(P->ev[evi], st));
+        {
+          PassLaunch pl{};
+          pl.xs = xs;
+          pl.mu = mu;
+          pl.df = df;
+          pl.dg = dg;
+          pl.sw = invT;
+          pl.invn = invn;
+          pl.thr = thr;
+          pl.best = best;
+          pl.N = N;
+          pl.e = e;
+          pl.L = L;
+          pl.append = false;
+          VCHECK(launch_pass(pl, st));
+        }
+        VCHECK(hipEventRecord(P->ev[evi + 1], st));
+        evi += 2;
+        P->pass_launches += 1;
+        P->pass_cells += pass_grid(N, e, kPassK, kPassH).cells;
+        VCHECK(launch_finalize(xs, mu, sig, best, N, L, pd, pi, vnorm, vdist, vlen, vidx, st));
+        VCHECK(launch_fill_tail(N, N0, pd, pi, st));
+        host_stats[t * VALMOD_NSTATS + VALMOD_STAT_FULL_PASS] = 1;
+      }
+      VCHECK(launch_rankings(o->prof_dist + Ls.prof, o->prof_idx + Ls.prof, N0, n, Ls.l_min, (int)Ls.nlen,
+                             excl_den, km, kd, o->motif_ab + 2 * Ls.motif, o->motif_d + Ls.motif,
+                             o->discord_on + 2 * Ls.discord, o->discord_d + Ls.discord, st));
+      VCHECK(launch_global_rank(vnorm, vdist, vlen, vidx, N0, o->discord_on + 2 * Ls.discord,
+                                o->discord_d + Ls.discord, (int)Ls.nlen, Ls.l_min, excl_den, km, kd,
+                                o->g_motif_abl + 3 * Ls.g_motif, o->g_motif_d + 2 * Ls.g_motif,
+                                o->g_discord_onl + 3 * Ls.g_discord, o->g_discord_d + 2 * Ls.g_discord, st));
+      if (o->stats) {
+        VCHECK(hipMemcpyAsync(o->stats + Ls.stats, host_stats.data(), host_stats.size() * 8,
+                              hipMemcpyHostToDevice, st));
+        VCHECK(hipStreamSynchronize(st));  // host_stats is reused by the next series
+      }
+    }
+    VCHECK(hipMemcpyAsync(host_cnt.data(), cnt, CNT_WORDS * 8, hipMemcpyDeviceToHost, st));
+    VCHECK(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < evi; i += 2) {
+      float ms = 0.f;
+      VCHECK(hipEventElapsedTime(&ms, P->ev[i], P->ev[i + 1]));
+      P->pass_ms += ms;
+    }
+    if (host_cnt[CNT_ERR]) status = VALMOD_E_DEVICE;
+  }
+done:
+  (void)hipSetDevice(prev_dev);
+  return status;
+}

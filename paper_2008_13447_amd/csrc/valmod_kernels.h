@@ -1,0 +1,57 @@
+// Launch wrappers of the VALMOD kernels (host side, no allocation, asynchronous).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace valmod {
+
+constexpr int kPassK = 8;        // diagonals per lane in the diagonal pass
+constexpr int64_t kPassH = 4096; // rows per work item of the diagonal pass
+
+struct PassLaunch {
+  const double *xs, *mu, *df, *dg, *sw, *invn;
+  double* thr;
+  uint64_t* best;
+  uint32_t* cnt;
+  int32_t* buf;
+  int64_t cap;
+  int64_t N, e;
+  int L;
+  bool append;
+};
+
+struct PassGrid {
+  int64_t bands = 0, segs = 0, cells = 0;
+};
+
+// Work decomposition of the diagonal pass over the upper triangle j - i > e.
+PassGrid pass_grid(int64_t N, int64_t e, int K, int64_t H);
+
+hipError_t launch_convert(const void* in, int dtype, int64_t n, int64_t npad, double* xs, int* err,
+                          hipStream_t st);
+hipError_t launch_stats(const double* xs, int64_t N, int L, int first, double flat_eps, double* A,
+                        double* B, double* mu, double* sig, double* invn, uint8_t* flat,
+                        unsigned long long* nflat, hipStream_t st);
+hipError_t launch_prep_f64(const double* xs, const double* mu, const double* sig, const double* invn, int64_t N,
+                           int L, double* df, double* dg, double* sw, hipStream_t st);
+hipError_t launch_seed_mp(const double* xs, const double* mu, const double* invn, const uint8_t* flat,
+                          const int32_t* prev_idx, int64_t N, int L, int64_t e, uint64_t* best,
+                          double* thr, hipStream_t st);
+hipError_t launch_pass(const PassLaunch& p, hipStream_t st);
+hipError_t launch_finalize(const double* xs, const double* mu, const double* sig, const uint64_t* best,
+                           int64_t N, int L, double* prof_dist, int32_t* prof_idx, double* valmp_norm,
+                           double* valmp_dist, int32_t* valmp_len, int32_t* valmp_idx, hipStream_t st);
+hipError_t launch_fill_tail(int64_t from, int64_t to, double* prof_dist, int32_t* prof_idx, hipStream_t st);
+hipError_t launch_valmp_init(int64_t N0, double* norm, double* dist, int32_t* len, int32_t* idx,
+                             hipStream_t st);
+hipError_t launch_rankings(const double* prof_dist, const int32_t* prof_idx, int64_t N0, int64_t n, int l_min,
+                           int nlen, int excl_den, int km, int kd, int32_t* motif_ab, double* motif_d,
+                           int32_t* discord_on, double* discord_d, hipStream_t st);
+hipError_t launch_global_rank(const double* valmp_norm, const double* valmp_dist, const int32_t* valmp_len,
+                              const int32_t* valmp_idx, int64_t N0, const int32_t* discord_on,
+                              const double* discord_d, int nlen, int l_min, int excl_den, int km, int kd,
+                              int32_t* g_motif_abl, double* g_motif_d, int32_t* g_discord_onl,
+                              double* g_discord_d, hipStream_t st);
+
+}  // namespace valmod

@@ -1,0 +1,296 @@
+"""ctypes binding of the VALMOD C ABI (include/valmod.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``libvalmod.so``. The functions keep the C names (``valmod_plan``,
+``valmod_run``, ...); ``run_valmod`` is a convenience wrapper that allocates the
+workspace and outputs as torch device tensors and calls them.
+
+The library must have been built (``__graft_entry__.build()``); importing
+this module does not build it, and a missing library raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence, Union
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvalmod.so")
+
+VALMOD_OK = 0
+STATUS = {0: "VALMOD_OK", -1: "VALMOD_E_ARG", -2: "VALMOD_E_TOO_SHORT", -3: "VALMOD_E_NOMEM",
+          -4: "VALMOD_E_HIP", -5: "VALMOD_E_LAYOUT", -6: "VALMOD_E_DEVICE"}
+DTYPE = {"f32": 0, "f64": 1}
+PRECISION = {"fp64": 0, "fp32": 1}
+PATH = {"auto": 0, "full": 1, "recompute": 2}
+NSTATS = 8
+STAT_NAMES = ["valid", "failed", "recomputed", "full_pass", "flat", "appends"]
+
+# (name, C type) of every function declared in include/valmod.h
+EXPORTS = ["valmod_plan", "valmod_workspace_bytes", "valmod_output_sizes", "valmod_series_layout",
+           "valmod_run", "valmod_plan_free", "valmod_status_str", "valmod_last_pass_timing"]
+
+
+class ValmodConfig(ctypes.Structure):
+    _fields_ = [
+        ("num_series", ctypes.c_int32),
+        ("n", ctypes.POINTER(ctypes.c_int64)),
+        ("l_min", ctypes.POINTER(ctypes.c_int32)),
+        ("l_max", ctypes.POINTER(ctypes.c_int32)),
+        ("p", ctypes.c_int32),
+        ("k_motifs", ctypes.c_int32),
+        ("k_discords", ctypes.c_int32),
+        ("excl_den", ctypes.c_int32),
+        ("flat_eps", ctypes.c_double),
+        ("dtype", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("refresh_R", ctypes.c_int32),
+        ("path", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+    ]
+
+
+OUTPUT_FIELDS = ["prof_dist", "prof_idx", "valmp_norm", "valmp_dist", "valmp_len", "valmp_idx",
+                 "motif_ab", "motif_d", "discord_on", "discord_d", "g_motif_abl", "g_motif_d",
+                 "g_discord_onl", "g_discord_d", "stats"]
+
+
+class ValmodOutputs(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in OUTPUT_FIELDS]
+
+
+class ValmodSizes(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in
+                ["prof", "valmp", "motif", "discord", "g_motif", "g_discord", "stats", "series"]]
+
+
+class ValmodLayout(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in
+                ["series", "prof", "valmp", "motif", "discord", "g_motif", "g_discord", "stats",
+                 "n", "n0", "nlen"]] + [("l_min", ctypes.c_int32), ("l_max", ctypes.c_int32)]
+
+
+_lib = None
+
+
+class ValmodError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({status_str(status)})")
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """Load libvalmod.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library missing: {LIB_PATH} (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    L.valmod_plan.argtypes = [ctypes.POINTER(ValmodConfig), ctypes.POINTER(P)]
+    L.valmod_plan.restype = ctypes.c_int
+    L.valmod_workspace_bytes.argtypes = [P]
+    L.valmod_workspace_bytes.restype = ctypes.c_size_t
+    L.valmod_output_sizes.argtypes = [P, ctypes.POINTER(ValmodSizes)]
+    L.valmod_output_sizes.restype = ctypes.c_int
+    L.valmod_series_layout.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ValmodLayout)]
+    L.valmod_series_layout.restype = ctypes.c_int
+    L.valmod_run.argtypes = [P, P, P, ctypes.POINTER(ValmodOutputs), P]
+    L.valmod_run.restype = ctypes.c_int
+    L.valmod_plan_free.argtypes = [P]
+    L.valmod_plan_free.restype = None
+    L.valmod_status_str.argtypes = [ctypes.c_int]
+    L.valmod_status_str.restype = ctypes.c_char_p
+    L.valmod_last_pass_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    L.valmod_last_pass_timing.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def status_str(status: int) -> str:
+    return lib().valmod_status_str(int(status)).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != VALMOD_OK:
+        raise ValmodError(rc, where)
+
+
+def make_config(n: Sequence[int], l_min: Sequence[int], l_max: Sequence[int], p: int = 0,
+                k_motifs: int = 1, k_discords: int = 1, excl_den: int = 4, flat_eps: float = 0.0,
+                dtype: str = "f32", precision: str = "fp64", refresh_R: int = 0, path: str = "auto",
+                device: int = 0):
+    """Build a ValmodConfig; returns (config, keepalive arrays)."""
+    S = len(n)
+    na = (ctypes.c_int64 * S)(*[int(v) for v in n])
+    lo = (ctypes.c_int32 * S)(*[int(v) for v in l_min])
+    hi = (ctypes.c_int32 * S)(*[int(v) for v in l_max])
+    cfg = ValmodConfig(S, ctypes.cast(na, ctypes.POINTER(ctypes.c_int64)),
+                       ctypes.cast(lo, ctypes.POINTER(ctypes.c_int32)),
+                       ctypes.cast(hi, ctypes.POINTER(ctypes.c_int32)), int(p), int(k_motifs),
+                       int(k_discords), int(excl_den), float(flat_eps), DTYPE[dtype], PRECISION[precision],
+                       int(refresh_R), PATH[path], int(device))
+    return cfg, (na, lo, hi)
+
+
+def valmod_plan(cfg: ValmodConfig) -> int:
+    """Validate the configuration and return a plan handle (int)."""
+    h = ctypes.c_void_p()
+    _check(lib().valmod_plan(ctypes.byref(cfg), ctypes.byref(h)), "valmod_plan")
+    return h.value
+
+
+def valmod_plan_status(cfg: ValmodConfig) -> int:
+    """Status code of valmod_plan without raising (frees a successful plan)."""
+    h = ctypes.c_void_p()
+    rc = lib().valmod_plan(ctypes.byref(cfg), ctypes.byref(h))
+    if rc == VALMOD_OK:
+        lib().valmod_plan_free(h)
+    return rc
+
+
+def valmod_workspace_bytes(plan: int) -> int:
+    return int(lib().valmod_workspace_bytes(plan))
+
+
+def valmod_output_sizes(plan: int) -> Dict[str, int]:
+    s = ValmodSizes()
+    _check(lib().valmod_output_sizes(plan, ctypes.byref(s)), "valmod_output_sizes")
+    return {f: getattr(s, f) for f, _ in ValmodSizes._fields_}
+
+
+def valmod_series_layout(plan: int, s: int) -> Dict[str, int]:
+    out = ValmodLayout()
+    _check(lib().valmod_series_layout(plan, s, ctypes.byref(out)), "valmod_series_layout")
+    return {f: getattr(out, f) for f, _ in ValmodLayout._fields_}
+
+
+def valmod_run(plan: int, series_ptr: int, workspace_ptr: int, outputs: ValmodOutputs,
+               stream: Optional[int] = None) -> None:
+    _check(lib().valmod_run(plan, series_ptr, workspace_ptr, ctypes.byref(outputs), stream),
+           "valmod_run")
+
+
+def valmod_plan_free(plan: int) -> None:
+    lib().valmod_plan_free(plan)
+
+
+def valmod_last_pass_timing(plan: int):
+    ms = ctypes.c_double()
+    launches = ctypes.c_int64()
+    cells = ctypes.c_int64()
+    _check(lib().valmod_last_pass_timing(plan, ctypes.byref(ms), ctypes.byref(launches),
+                                         ctypes.byref(cells)), "valmod_last_pass_timing")
+    return ms.value, launches.value, cells.value
+
+
+class Valmod:
+    """A plan plus its torch-allocated workspace and outputs on one GPU."""
+
+    def __init__(self, series: Union["torch.Tensor", List["torch.Tensor"]], l_min, l_max, p: int = 0,
+                 k_motifs: int = 1, k_discords: int = 1, excl_den: int = 4, flat_eps: float = 0.0,
+                 precision: str = "fp64", refresh_R: int = 0, path: str = "auto"):
+        import torch
+
+        if isinstance(series, torch.Tensor):
+            series = [series]
+        if not series or any((not s.is_cuda) for s in series):
+            raise ValueError("series must be CUDA (HIP) tensors")
+        dt = series[0].dtype
+        if dt not in (torch.float32, torch.float64) or any(s.dtype != dt for s in series):
+            raise ValueError("series must all be float32 or all float64")
+        S = len(series)
+        lo = list(l_min) if isinstance(l_min, (list, tuple)) else [l_min] * S
+        hi = list(l_max) if isinstance(l_max, (list, tuple)) else [l_max] * S
+        self.device = series[0].device
+        self.torch = torch
+        cfg, self._keep = make_config([s.numel() for s in series], lo, hi, p, k_motifs, k_discords,
+                                      excl_den, flat_eps, "f32" if dt == torch.float32 else "f64",
+                                      precision, refresh_R, path, self.device.index or 0)
+        self.plan = valmod_plan(cfg)
+        self.k_motifs, self.k_discords = k_motifs, k_discords
+        self.sizes = valmod_output_sizes(self.plan)
+        self.layouts = [valmod_series_layout(self.plan, s) for s in range(S)]
+        dev = self.device
+        self.series = torch.cat([s.reshape(-1) for s in series]).contiguous()
+        self.workspace = torch.empty(max(valmod_workspace_bytes(self.plan), 256), dtype=torch.uint8,
+                                     device=dev)
+        z = self.sizes
+        f64, i32 = torch.float64, torch.int32
+        self.out = {
+            "prof_dist": torch.empty(z["prof"], dtype=f64, device=dev),
+            "prof_idx": torch.empty(z["prof"], dtype=i32, device=dev),
+            "valmp_norm": torch.empty(z["valmp"], dtype=f64, device=dev),
+            "valmp_dist": torch.empty(z["valmp"], dtype=f64, device=dev),
+            "valmp_len": torch.empty(z["valmp"], dtype=i32, device=dev),
+            "valmp_idx": torch.empty(z["valmp"], dtype=i32, device=dev),
+            "motif_ab": torch.empty(2 * z["motif"], dtype=i32, device=dev),
+            "motif_d": torch.empty(z["motif"], dtype=f64, device=dev),
+            "discord_on": torch.empty(2 * z["discord"], dtype=i32, device=dev),
+            "discord_d": torch.empty(z["discord"], dtype=f64, device=dev),
+            "g_motif_abl": torch.empty(3 * z["g_motif"], dtype=i32, device=dev),
+            "g_motif_d": torch.empty(2 * z["g_motif"], dtype=f64, device=dev),
+            "g_discord_onl": torch.empty(3 * z["g_discord"], dtype=i32, device=dev),
+            "g_discord_d": torch.empty(2 * z["g_discord"], dtype=f64, device=dev),
+            "stats": torch.empty(z["stats"], dtype=torch.int64, device=dev),
+        }
+        self._outs = ValmodOutputs(*[self.out[f].data_ptr() for f in OUTPUT_FIELDS])
+
+    def run(self, stream=None) -> None:
+        torch = self.torch
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        valmod_run(self.plan, self.series.data_ptr(), self.workspace.data_ptr(), self._outs,
+                   st.cuda_stream)
+
+    def pass_timing(self):
+        """(ms, launches, cells) of the diagonal-pass kernels of the last run."""
+        return valmod_last_pass_timing(self.plan)
+
+    def result(self, s: int = 0) -> Dict[str, np.ndarray]:
+        """Host copy of the outputs of series s, reshaped like the oracle's."""
+        L = self.layouts[s]
+        n0, nl = L["n0"], L["nlen"]
+        km, kd = self.k_motifs, self.k_discords
+        o = {k: v.cpu().numpy() for k, v in self.out.items()}
+        return dict(
+            prof_dist=o["prof_dist"][L["prof"]:L["prof"] + nl * n0].reshape(nl, n0),
+            prof_idx=o["prof_idx"][L["prof"]:L["prof"] + nl * n0].reshape(nl, n0),
+            valmp_norm=o["valmp_norm"][L["valmp"]:L["valmp"] + n0],
+            valmp_dist=o["valmp_dist"][L["valmp"]:L["valmp"] + n0],
+            valmp_len=o["valmp_len"][L["valmp"]:L["valmp"] + n0],
+            valmp_idx=o["valmp_idx"][L["valmp"]:L["valmp"] + n0],
+            motif_ab=o["motif_ab"][2 * L["motif"]:2 * (L["motif"] + nl * km)].reshape(nl, km, 2),
+            motif_d=o["motif_d"][L["motif"]:L["motif"] + nl * km].reshape(nl, km),
+            discord_on=o["discord_on"][2 * L["discord"]:2 * (L["discord"] + nl * kd)].reshape(nl, kd, 2),
+            discord_d=o["discord_d"][L["discord"]:L["discord"] + nl * kd].reshape(nl, kd),
+            g_motif_abl=o["g_motif_abl"][3 * L["g_motif"]:3 * (L["g_motif"] + km)].reshape(km, 3),
+            g_motif_d=o["g_motif_d"][2 * L["g_motif"]:2 * (L["g_motif"] + km)].reshape(km, 2),
+            g_discord_onl=o["g_discord_onl"][3 * L["g_discord"]:3 * (L["g_discord"] + kd)].reshape(kd, 3),
+            g_discord_d=o["g_discord_d"][2 * L["g_discord"]:2 * (L["g_discord"] + kd)].reshape(kd, 2),
+            stats=o["stats"][L["stats"]:L["stats"] + nl * NSTATS].reshape(nl, NSTATS),
+        )
+
+    def close(self):
+        if getattr(self, "plan", None):
+            valmod_plan_free(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_valmod(x, l_min: int, l_max: int, **kw) -> Dict[str, np.ndarray]:
+    """One series through the HIP path; returns host numpy outputs."""
+    v = Valmod(x, l_min, l_max, **kw)
+    v.run()
+    v.torch.cuda.synchronize(v.device)
+    out = v.result(0)
+    v.close()
+    return out

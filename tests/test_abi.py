@@ -1,0 +1,119 @@
+"""CPU tests of the C ABI: the library loads, exports every declared symbol,
+validates plans and lays out outputs. No kernel is launched (valmod_plan and
+the layout queries are host-only)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2008_13447_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(native.LIB_PATH):
+        from paper_2008_13447_amd import build
+
+        build.build_native()
+    return native.lib()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "valmod.h")).read()
+    return sorted(set(re.findall(r"VALMOD_API\s+[\w\s\*]+?\b(valmod_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_exports():
+    assert declared_functions() == sorted(native.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.check_output(["nm", "-D", "--defined-only", native.LIB_PATH]).decode()
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in declared_functions():
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_status_strings(lib):
+    for code in native.STATUS:
+        assert native.status_str(code)
+    assert native.status_str(12345) == "unknown status"
+
+
+def _status(**kw):
+    base = dict(n=[1000], l_min=[20], l_max=[30], p=5, k_motifs=2, k_discords=2)
+    base.update(kw)
+    cfg, keep = native.make_config(**base)
+    return native.valmod_plan_status(cfg)
+
+
+def test_plan_validation(lib):
+    assert _status() == 0
+    assert _status(l_min=[3], l_max=[10]) == -1          # l_min < 4
+    assert _status(l_min=[30], l_max=[20]) == -1         # l_max < l_min
+    assert _status(k_motifs=0) == -1
+    assert _status(k_discords=65) == -1
+    assert _status(p=-1) == -1
+    assert _status(excl_den=-2) == -1
+    assert _status(n=[40], l_min=[30], l_max=[35]) == -2  # no non-trivial pair
+    assert _status(n=[(1 << 22) + 100], l_min=[10], l_max=[20]) == -5
+    cfg, keep = native.make_config([1000], [20], [30])
+    cfg.dtype = 7
+    assert native.valmod_plan_status(cfg) == -1
+
+
+def test_sizes_and_layout(lib):
+    cfg, keep = native.make_config([1000, 500, 2000], [20, 8, 50], [30, 8, 60], k_motifs=3, k_discords=2)
+    plan = native.valmod_plan(cfg)
+    try:
+        z = native.valmod_output_sizes(plan)
+        n0 = [981, 493, 1951]
+        nl = [11, 1, 11]
+        assert z["prof"] == sum(a * b for a, b in zip(n0, nl))
+        assert z["valmp"] == sum(n0)
+        assert z["motif"] == 3 * sum(nl) and z["discord"] == 2 * sum(nl)
+        assert z["g_motif"] == 9 and z["g_discord"] == 6
+        assert z["series"] == 3500 and z["stats"] == native.NSTATS * sum(nl)
+        L1 = native.valmod_series_layout(plan, 1)
+        assert L1["series"] == 1000 and L1["prof"] == 981 * 11 and L1["n0"] == 493 and L1["nlen"] == 1
+        assert native.valmod_workspace_bytes(plan) % 256 == 0
+        with pytest.raises(native.ValmodError):
+            native.valmod_series_layout(plan, 3)
+    finally:
+        native.valmod_plan_free(plan)
+
+
+def test_pass_tiling_covers_upper_triangle_once():
+    """Python mirror of the diagonal-pass work decomposition: every non-trivial
+    cell (i, j > i + e) belongs to exactly one (band, segment, lane, slot)."""
+    import numpy as np
+
+    K, H, W = 8, 64, 64  # smaller H than the build's, same formulas
+    for N, e in [(700, 5), (1500, 40), (513, 3)]:
+        cover = np.zeros((N, N), dtype=np.int32)
+        ndiag = N - 1 - e
+        bands = -(-ndiag // (W * K))
+        segs = -(-ndiag // H)
+        for b in range(bands):
+            d0 = e + 1 + b * W * K
+            if d0 > N - 1:
+                continue
+            row_end = N - d0
+            for s in range(segs):
+                i0 = s * H
+                if i0 >= row_end:
+                    continue
+                rows = np.arange(i0, min(i0 + H, row_end))
+                for t in range(W):
+                    for q in range(K):
+                        d = d0 + K * t + q
+                        j = rows + d
+                        ok = j < N
+                        cover[rows[ok], j[ok]] += 1
+        ii, jj = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+        want = (jj - ii > e).astype(np.int32)
+        assert np.array_equal(cover, want)

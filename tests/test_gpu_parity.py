@@ -1,0 +1,160 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+FP64 path tolerance: |d(d/sqrt(L))| <= 1e-9 on every output distance; indices
+equal except distance ties within that tolerance (then the oracle's distance
+of the reported pair must tie the optimum).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2008_13447_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-9
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(x, l_min, l_max, **kw):
+    torch = _torch()
+    from paper_2008_13447_amd import native
+
+    t = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    return native.run_valmod(t, l_min, l_max, **kw)
+
+
+@pytest.fixture(scope="module")
+def oracle_mod():
+    import oracle
+
+    oracle.build(force=False)
+    return oracle
+
+
+def test_config1_full_parity(oracle_mod):
+    """Plain FP64 case: random walk n=2048, lengths 32..40, p=5, top-1."""
+    from oracle import compare
+
+    w = gen.config1()
+    _say(f"config1 n={w.n} L={w.l_min}..{w.l_max}")
+    g = run_gpu(w.x, w.l_min, w.l_max, p=w.p, k_motifs=w.k_motifs, k_discords=w.k_discords)
+    r = oracle_mod.valmod(w.x, w.l_min, w.l_max, k_motifs=w.k_motifs, k_discords=w.k_discords)
+    rep = compare.check_full(w.x, w.l_min, g, r, TOL64)
+    _say(f"config1 report {dict(rep)}")
+
+
+@pytest.mark.parametrize("n,lo,hi,den,k,dtype,seed", [
+    (1000, 16, 24, 4, 3, np.float32, 0),
+    (1531, 9, 12, 2, 5, np.float64, 1),
+    (3001, 40, 44, 4, 4, np.float32, 2),
+    (700, 20, 20, 4, 2, np.float64, 3),     # single length: the plain matrix profile
+    (97, 8, 12, 4, 2, np.float64, 4),       # tiny, ragged against every tile size
+])
+def test_random_walk_parity(oracle_mod, n, lo, hi, den, k, dtype, seed):
+    from oracle import compare
+
+    x = gen.small_random_walk(n, 10 + seed, dtype)
+    _say(f"rw n={n} L={lo}..{hi} den={den}")
+    g = run_gpu(x, lo, hi, p=5, k_motifs=k, k_discords=k, excl_den=den)
+    r = oracle_mod.valmod(x, lo, hi, excl_den=den, k_motifs=k, k_discords=k)
+    compare.check_full(x, lo, g, r, TOL64, excl_den=den)
+
+
+def test_flat_segments_at_offset(oracle_mod):
+    """Constant stretches at a 1e4 offset: flat windows get +inf / -1 and are
+    never reported as neighbours."""
+    from oracle import compare
+
+    x = gen.small_random_walk(2500, 20) + 1.0e4
+    x[300:700] = x[300]
+    x[1500:1560] = x[1500]
+    x = x.astype(np.float32)
+    _say("flats n=2500 L=24..32")
+    g = run_gpu(x, 24, 32, p=5, k_motifs=3, k_discords=3)
+    r = oracle_mod.valmod(x, 24, 32, k_motifs=3, k_discords=3)
+    compare.check_full(x, 24, g, r, TOL64)
+    assert np.isinf(g["prof_dist"][0, 300:650]).all()
+
+
+def test_minimal_series(oracle_mod):
+    from oracle import compare
+
+    lo = hi = 16
+    e = 4
+    n = hi + e + 2  # N = e + 3 windows: exactly the smallest legal case
+    x = gen.small_random_walk(n, 30)
+    g = run_gpu(x, lo, hi, k_motifs=1, k_discords=1)
+    r = oracle_mod.valmod(x, lo, hi)
+    compare.check_full(x, lo, g, r, TOL64)
+
+
+def test_batch_equals_single():
+    torch = _torch()
+    from paper_2008_13447_amd import native
+
+    xs = [gen.small_random_walk(n, 40 + i, np.float32) for i, n in enumerate([900, 1700, 1234])]
+    lo, hi = [20, 12, 30], [26, 12, 33]
+    v = native.Valmod([torch.from_numpy(x).cuda() for x in xs], lo, hi, p=5, k_motifs=2, k_discords=2)
+    v.run()
+    torch.cuda.synchronize()
+    for s, x in enumerate(xs):
+        one = run_gpu(x, lo[s], hi[s], p=5, k_motifs=2, k_discords=2)
+        b = v.result(s)
+        for key in ("prof_dist", "prof_idx", "valmp_norm", "valmp_idx", "motif_ab", "discord_on",
+                    "g_motif_abl", "g_discord_onl"):
+            assert np.array_equal(b[key], one[key], equal_nan=True), (s, key)
+    v.close()
+
+
+def test_repeat_runs_are_bitwise_identical():
+    torch = _torch()
+    from paper_2008_13447_amd import native
+
+    x = gen.small_random_walk(5000, 50, np.float32)
+    v = native.Valmod(torch.from_numpy(x).cuda(), 30, 40, p=10, k_motifs=3, k_discords=3)
+    v.run()
+    a = v.result(0)
+    v.run()
+    b = v.result(0)
+    for key in a:
+        assert np.array_equal(a[key], b[key], equal_nan=True), key
+    v.close()
+
+
+def test_config2_sampled_parity(oracle_mod):
+    """n=65,536 FP32 random walk with planted motifs/discord, lengths 100..200:
+    full run on the GPU, sampled owners against the oracle, planted motifs
+    recovered."""
+    from oracle import compare
+
+    w = gen.config2()
+    _say(f"config2 n={w.n} L={w.l_min}..{w.l_max}")
+    g = run_gpu(w.x, w.l_min, w.l_max, p=w.p, k_motifs=w.k_motifs, k_discords=w.k_discords)
+    extra = [v for (a, b, _) in w.planted_motifs for v in (a, b)] + [c for c, _ in w.planted_discords]
+    rep = compare.check_sampled(w.x, w.l_min, g, [100, 150, 200], 96, TOL64, extra=extra)
+    _say(f"config2 sampled report {dict(rep)}")
+    t = 150 - w.l_min
+    e = -(-150 // 4)
+    for a, b, _ in w.planted_motifs:
+        assert abs(int(g["prof_idx"][t, a]) - b) <= e
+    # VALMP internal consistency: min over lengths of the per-length profiles
+    n0 = w.n - w.l_min + 1
+    nl = w.l_max - w.l_min + 1
+    L = np.arange(w.l_min, w.l_max + 1)[:, None]
+    norm = g["prof_dist"] * np.sqrt(1.0 / L)
+    np.testing.assert_allclose(g["valmp_norm"], norm.min(axis=0), rtol=0, atol=1e-15)
+    assert nl == g["prof_dist"].shape[0] and n0 == g["prof_dist"].shape[1]
