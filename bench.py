@@ -22,6 +22,22 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed)
 FLOP_PER_CELL = 6         # 2 FMA co-moment update + 2 MUL normalisation
 
 
+def profiled_traffic(precision):
+    """HBM bytes per pass launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
+    scaled by a 1 GiB device-copy calibration) for the current kernel source; None
+    when the summary is missing or was taken on a different kernel source."""
+    import glob
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_2008_13447_amd", "csrc", "valmod_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", f"k_pass_{precision}_*.md")):
+        fields = dict(line.split(": ", 1) for line in open(path) if ": " in line and not line.startswith(("-", "|")))
+        if fields.get("kernel_source_sha256_16", "").strip() == sha and "traffic_bytes_per_launch" in fields:
+            return float(fields["traffic_bytes_per_launch"])
+    return None
+
+
 def cells_total(n, lo, hi):
     return sum((n - L + 1) * (n - L) // 2 for L in range(lo, hi + 1))
 
@@ -37,9 +53,10 @@ def cpu_baseline(x, L, excl_den, gpu_prof_d, gpu_prof_i, target_s, seed=0):
     oracle.build(force=False)
     n = x.shape[0]
     N = n - L + 1
-    threads = os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count() or 1
     rows = compare.sample_rows(N, N, seed)  # a random permutation
-    probe = rows[:max(threads, 8)]
+    probe = rows[:4 * threads]
+    oracle.profile(x, L, rows=probe[:threads], excl_den=excl_den, nthreads=threads)  # warm
     t0 = time.perf_counter()
     oracle.profile(x, L, rows=probe, excl_den=excl_den, nthreads=threads)
     dt = max(time.perf_counter() - t0, 1e-6)
@@ -67,6 +84,8 @@ def main():
     ap.add_argument("--path", default="auto", choices=["auto", "full", "recompute"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; multi-GPU runs are not supported "
@@ -77,6 +96,16 @@ def main():
     import torch
 
     from paper_2008_13447_amd import gen, native
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes}))
+        return
 
     w = gen.WORKLOADS[args.config]()
     dev = torch.device("cuda:0")
@@ -105,12 +134,15 @@ def main():
         "config": {"workload": w.name, "n": w.n, "l_min": w.l_min, "l_max": w.l_max, "p": w.p,
                    "k": w.k_motifs, "precision": args.precision, "path": args.path},
         "roofline": {"bound": "alu", "kernel": "k_pass (diagonal pass)", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": profiled_traffic(args.precision),
                      "avg_launch_ms": avg_ms, "launches_per_step": launches,
                      "cells_per_launch": pass_cells / max(launches, 1)},
     }
+    res = v.result(0)
+    st = res["stats"].sum(axis=0)
+    out["diagnostics"] = {name: int(st[c]) for c, name in enumerate(native.STAT_NAMES)}
+    out["diagnostics"]["wave_steps_per_pass"] = int(pass_cells / max(launches, 1) / 512)
     if not args.no_cpu:
-        res = v.result(0)
         out["cpu_baseline"] = cpu_baseline(w.x, w.l_min, w.excl_den, res["prof_dist"][0], res["prof_idx"][0],
                                            args.cpu_seconds)
     v.close()

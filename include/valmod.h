@@ -108,6 +108,8 @@ enum {
   VALMOD_STAT_FULL_PASS = 3,  /* 1 if a full diagonal pass ran at this length */
   VALMOD_STAT_FLAT = 4,       /* flat windows at this length */
   VALMOD_STAT_APPENDS = 5,    /* candidates collected by the full pass (0 if none) */
+  VALMOD_STAT_PASS_EVENTS = 6,/* wavefront steps of the diagonal pass that took its slow path */
+  VALMOD_STAT_PASS_HITS = 7,  /* owner updates made by the diagonal pass */
   VALMOD_NSTATS = 8
 };
 

@@ -158,10 +158,10 @@ static void* profile_worker(void* arg) {
   for (;;) {
     pthread_mutex_lock(&J->lock);
     int64_t r0 = J->next;
-    J->next += 16;
+    J->next += 1;
     pthread_mutex_unlock(&J->lock);
     if (r0 >= J->nrows) break;
-    int64_t r1 = r0 + 16 < J->nrows ? r0 + 16 : J->nrows;
+    int64_t r1 = r0 + 1 < J->nrows ? r0 + 1 : J->nrows;
     for (int64_t r = r0; r < r1; r++) profile_one(J, r);
   }
   return NULL;

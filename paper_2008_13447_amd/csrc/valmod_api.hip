@@ -6,6 +6,7 @@
 
 #include <math.h>
 #include <new>
+#include <stdlib.h>
 #include <string.h>
 #include <vector>
 
@@ -18,11 +19,44 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
-  size_t xs, A, B, mu, sig, invn, flat, df, dg, invT, thr, best, counters, vnorm, vdist, vlen, vidx;
+  size_t xs, A, B, mu, sig, invn, flat, df, dg, sw32, thr, thr32, best, counters, anc;
   size_t total;
 };
 
-enum { CNT_ERR = 0, CNT_NFLAT = 1, CNT_WORDS = 32 };
+// Geometry of the diagonal pass of one series, fixed for all its lengths.
+struct PassGeom {
+  int64_t dstart = 0, H = 0, segs = 0, bands = 0, stride = 0;
+  int K = 0;
+};
+
+int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  return v && *v ? atoi(v) : dflt;
+}
+
+PassGeom pass_geom(int64_t n, int32_t l_min, int32_t excl_den) {
+  PassGeom g;
+  const int64_t N0 = n - l_min + 1;
+  const int64_t e0 = excl_zone(l_min, excl_den);
+  g.K = env_int("VALMOD_PASS_K", 8) == 4 ? 4 : 8;
+  const int64_t bw = 64 * g.K;
+  g.dstart = (e0 + 1) / 8 * 8;  // bands start on a multiple of 8 (aligned wide loads)
+  const int64_t ndiag = N0 - 1 - e0;
+  const double cells = ndiag > 0 ? 0.5 * (double)ndiag * (double)(ndiag + 1) : 0.0;
+  // segment height: enough work items to keep every SIMD busy, within [128, 4096]
+  const double items = env_int("VALMOD_PASS_ITEMS", 16384);
+  int64_t H = 4096;
+  while (H > 128 && cells / ((double)bw * (double)H) < items) H /= 2;
+  const int hforce = env_int("VALMOD_PASS_H", 0);
+  if (hforce >= 64 && hforce % 8 == 0) H = hforce;
+  g.H = H;
+  g.bands = (N0 - g.dstart + bw - 1) / bw;
+  g.segs = (N0 - g.dstart + H - 1) / H;
+  g.stride = g.bands * bw;
+  return g;
+}
+
+enum { CNT_ERR = 0, CNT_NFLAT = 1, CNT_EV_STEPS = 2, CNT_EV_HITS = 3, CNT_APPENDS = 4, CNT_WORDS = 32 };
 
 }  // namespace
 
@@ -32,7 +66,8 @@ struct valmod_plan_s {
   std::vector<int32_t> lmin, lmax;
   std::vector<valmod_layout> lay;
   valmod_sizes sizes;
-  int64_t nmax = 0, n0max = 0;
+  int64_t nmax = 0, n0max = 0, ancmax = 0;
+  std::vector<PassGeom> geom;
   WsLayout ws;
   // timing of the diagonal pass during the last run
   std::vector<hipEvent_t> ev;
@@ -134,6 +169,9 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
     z.stats += nlen * VALMOD_NSTATS;
     if (n > P->nmax) P->nmax = n;
     if (n0 > P->n0max) P->n0max = n0;
+    P->geom.push_back(pass_geom(n, lo, P->cfg.excl_den));
+    const int64_t anc = P->geom.back().segs * P->geom.back().stride;
+    if (anc > P->ancmax) P->ancmax = anc;
   }
 
   // workspace carve-up (sized for the largest series; series run one after another)
@@ -155,14 +193,12 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
   w.flat = take(wp);
   w.df = take(wp * 8);
   w.dg = take(wp * 8);
-  w.invT = take(wp * 8);
+  w.sw32 = take(wp * 4);
   w.thr = take(wp * 8);
+  w.thr32 = take(wp * 4);
   w.best = take(wp * 8);
   w.counters = take(CNT_WORDS * 8);
-  w.vnorm = take(wp * 8);
-  w.vdist = take(wp * 8);
-  w.vlen = take(wp * 4);
-  w.vidx = take(wp * 4);
+  w.anc = take((size_t)P->ancmax * 8);
   w.total = off;
   *out = P;
   return VALMOD_OK;
@@ -230,8 +266,10 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
   uint8_t* flat = (uint8_t*)(ws + P->ws.flat);
   double* df = (double*)(ws + P->ws.df);
   double* dg = (double*)(ws + P->ws.dg);
-  double* invT = (double*)(ws + P->ws.invT);
+  float* sw32 = (float*)(ws + P->ws.sw32);
   double* thr = (double*)(ws + P->ws.thr);
+  float* thr32 = (float*)(ws + P->ws.thr32);
+  double* anc = (double*)(ws + P->ws.anc);
   uint64_t* best = (uint64_t*)(ws + P->ws.best);
   unsigned long long* cnt = (unsigned long long*)(ws + P->ws.counters);
   const int esz = P->cfg.dtype == VALMOD_F32 ? 4 : 8;
@@ -239,7 +277,6 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
   const int km = P->cfg.k_motifs, kd = P->cfg.k_discords;
 
   std::vector<unsigned long long> host_cnt(CNT_WORDS);
-  std::vector<int64_t> host_stats;
   int64_t total_lengths = 0;
   for (auto& L : P->lay) total_lengths += L.nlen;
 
@@ -266,6 +303,7 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
     int64_t evi = 0;
     for (int s = 0; s < P->cfg.num_series; ++s) {
       const valmod_layout& Ls = P->lay[s];
+      const PassGeom& G = P->geom[s];
       const int64_t n = Ls.n, N0 = Ls.n0;
       const char* series = (const char*)d_series + (size_t)Ls.series * esz;
       VCHECK(launch_convert(series, P->cfg.dtype, n, n + kPad, xs, (int*)&cnt[CNT_ERR], st));
@@ -274,7 +312,6 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
       int32_t* vlen = o->valmp_len + Ls.valmp;
       int32_t* vidx = o->valmp_idx + Ls.valmp;
       VCHECK(launch_valmp_init(N0, vnorm, vdist, vlen, vidx, st));
-      host_stats.assign(Ls.nlen * VALMOD_NSTATS, 0);
       for (int L = Ls.l_min; L <= Ls.l_max; ++L) {
         const int64_t t = L - Ls.l_min;
         const int64_t N = n - L + 1;
@@ -283,9 +320,10 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
         int32_t* pi = o->prof_idx + Ls.prof + t * N0;
         VCHECK(launch_stats(xs, N, L, L == Ls.l_min, P->cfg.flat_eps, A, B, mu, sig, invn, flat,
                             &cnt[CNT_NFLAT], st));
-        VCHECK(launch_prep_f64(xs, mu, sig, invn, N, L, df, dg, invT, st));
+        VCHECK(launch_anchor(xs, n, L, L == Ls.l_min, G.H, G.dstart, G.segs, G.stride, G.stride, anc, st));
+        VCHECK(launch_prep_f64(xs, mu, sig, invn, N, L, df, dg, sw32, st));
         const int32_t* prev = L > Ls.l_min ? pi - N0 : nullptr;
-        VCHECK(launch_seed_mp(xs, mu, invn, flat, prev, N, L, e, best, thr, st));
+        VCHECK(launch_seed_mp(xs, mu, invn, flat, prev, N, L, e, best, thr, thr32, st));
         VCHECK(hipEventRecord(P->ev[evi], st));
         {
           PassLaunch pl{};
@@ -293,23 +331,32 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
           pl.mu = mu;
           pl.df = df;
           pl.dg = dg;
-          pl.sw = invT;
+          pl.sw32 = sw32;
           pl.invn = invn;
           pl.thr = thr;
+          pl.thr32 = thr32;
           pl.best = best;
+          pl.anc = anc;
+          pl.A = A;
+          pl.anc_stride = G.stride;
           pl.N = N;
           pl.e = e;
+          pl.H = G.H;
+          pl.dstart = G.dstart;
           pl.L = L;
+          pl.K = G.K;
           pl.append = false;
+          pl.events = &cnt[CNT_EV_STEPS];
           VCHECK(launch_pass(pl, st));
         }
         VCHECK(hipEventRecord(P->ev[evi + 1], st));
         evi += 2;
         P->pass_launches += 1;
-        P->pass_cells += pass_grid(N, e, kPassK, kPassH).cells;
+        P->pass_cells += pass_grid(N, e, G.dstart, G.K, G.H).cells;
         VCHECK(launch_finalize(xs, mu, sig, best, N, L, pd, pi, vnorm, vdist, vlen, vidx, st));
         VCHECK(launch_fill_tail(N, N0, pd, pi, st));
-        host_stats[t * VALMOD_NSTATS + VALMOD_STAT_FULL_PASS] = 1;
+        VCHECK(launch_record_stats(cnt, o->stats ? o->stats + Ls.stats + t * VALMOD_NSTATS : nullptr, 1, 0, 0, 0,
+                                   st));
       }
       VCHECK(launch_rankings(o->prof_dist + Ls.prof, o->prof_idx + Ls.prof, N0, n, Ls.l_min, (int)Ls.nlen,
                              excl_den, km, kd, o->motif_ab + 2 * Ls.motif, o->motif_d + Ls.motif,
@@ -318,11 +365,6 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
                                 o->discord_d + Ls.discord, (int)Ls.nlen, Ls.l_min, excl_den, km, kd,
                                 o->g_motif_abl + 3 * Ls.g_motif, o->g_motif_d + 2 * Ls.g_motif,
                                 o->g_discord_onl + 3 * Ls.g_discord, o->g_discord_d + 2 * Ls.g_discord, st));
-      if (o->stats) {
-        VCHECK(hipMemcpyAsync(o->stats + Ls.stats, host_stats.data(), host_stats.size() * 8,
-                              hipMemcpyHostToDevice, st));
-        VCHECK(hipStreamSynchronize(st));  // host_stats is reused by the next series
-      }
     }
     VCHECK(hipMemcpyAsync(host_cnt.data(), cnt, CNT_WORDS * 8, hipMemcpyDeviceToHost, st));
     VCHECK(hipStreamSynchronize(st));

@@ -6,18 +6,24 @@
 
 namespace valmod {
 
-constexpr int kPassK = 8;        // diagonals per lane in the diagonal pass
-constexpr int64_t kPassH = 4096; // rows per work item of the diagonal pass
+constexpr int kPassKMax = 8;  // largest supported diagonals-per-lane of the pass (4 or 8)
 
 struct PassLaunch {
-  const double *xs, *mu, *df, *dg, *sw, *invn;
+  const double *xs, *mu, *df, *dg, *invn;
+  const float* sw32;
   double* thr;
+  float* thr32;
   uint64_t* best;
   uint32_t* cnt;
   int32_t* buf;
   int64_t cap;
-  int64_t N, e;
+  const double* anc;
+  const double* A;
+  int64_t anc_stride;
+  unsigned long long* events;
+  int64_t N, e, H, dstart;
   int L;
+  int K;  // diagonals per lane: 4 or 8
   bool append;
 };
 
@@ -26,7 +32,9 @@ struct PassGrid {
 };
 
 // Work decomposition of the diagonal pass over the upper triangle j - i > e.
-PassGrid pass_grid(int64_t N, int64_t e, int K, int64_t H);
+PassGrid pass_grid(int64_t N, int64_t e, int64_t dstart, int K, int64_t H);
+hipError_t launch_anchor(const double* xs, int64_t n, int L, bool init, int64_t H, int64_t dstart, int64_t segs,
+                         int64_t stride, int64_t ncols, double* anc, hipStream_t st);
 
 hipError_t launch_convert(const void* in, int dtype, int64_t n, int64_t npad, double* xs, int* err,
                           hipStream_t st);
@@ -34,14 +42,18 @@ hipError_t launch_stats(const double* xs, int64_t N, int L, int first, double fl
                         double* B, double* mu, double* sig, double* invn, uint8_t* flat,
                         unsigned long long* nflat, hipStream_t st);
 hipError_t launch_prep_f64(const double* xs, const double* mu, const double* sig, const double* invn, int64_t N,
-                           int L, double* df, double* dg, double* sw, hipStream_t st);
+                           int L, double* df, double* dg, float* sw32, hipStream_t st);
 hipError_t launch_seed_mp(const double* xs, const double* mu, const double* invn, const uint8_t* flat,
                           const int32_t* prev_idx, int64_t N, int L, int64_t e, uint64_t* best,
-                          double* thr, hipStream_t st);
+                          double* thr, float* thr32, hipStream_t st);
 hipError_t launch_pass(const PassLaunch& p, hipStream_t st);
 hipError_t launch_finalize(const double* xs, const double* mu, const double* sig, const uint64_t* best,
                            int64_t N, int L, double* prof_dist, int32_t* prof_idx, double* valmp_norm,
                            double* valmp_dist, int32_t* valmp_len, int32_t* valmp_idx, hipStream_t st);
+// counters layout: [0] error flag, [1] flat windows, [2] pass slow-path steps,
+// [3] pass owner hits, [4] appended candidates
+hipError_t launch_record_stats(unsigned long long* cnt, int64_t* row, int full_pass, int64_t valid,
+                               int64_t failed, int64_t recomputed, hipStream_t st);
 hipError_t launch_fill_tail(int64_t from, int64_t to, double* prof_dist, int32_t* prof_idx, hipStream_t st);
 hipError_t launch_valmp_init(int64_t N0, double* norm, double* dist, int32_t* len, int32_t* idx,
                              hipStream_t st);

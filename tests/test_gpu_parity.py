@@ -115,7 +115,7 @@ def test_batch_equals_single():
         one = run_gpu(x, lo[s], hi[s], p=5, k_motifs=2, k_discords=2)
         b = v.result(s)
         for key in ("prof_dist", "prof_idx", "valmp_norm", "valmp_idx", "motif_ab", "discord_on",
-                    "g_motif_abl", "g_discord_onl"):
+                    "g_motif_abl", "g_discord_onl", "motif_d", "discord_d", "g_motif_d", "g_discord_d"):
             assert np.array_equal(b[key], one[key], equal_nan=True), (s, key)
     v.close()
 
@@ -131,6 +131,9 @@ def test_repeat_runs_are_bitwise_identical():
     v.run()
     b = v.result(0)
     for key in a:
+        if key == "stats":
+            # pass_events / pass_hits count concurrent threshold updates: diagnostics, not outputs
+            a[key], b[key] = a[key][:, :6], b[key][:, :6]
         assert np.array_equal(a[key], b[key], equal_nan=True), key
     v.close()
 
