@@ -29,7 +29,7 @@ def profiled_traffic(precision):
     import glob
     import hashlib
 
-    src = os.path.join(ROOT, "paper_2008_13447_amd", "csrc", "valmod_kernels.hip")
+    src = os.path.join(ROOT, "paper_2008_13447_amd", "csrc", "valmod_pass.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     for path in glob.glob(os.path.join(ROOT, "profiles", f"k_pass_{precision}_*.md")):
         fields = dict(line.split(": ", 1) for line in open(path) if ": " in line and not line.startswith(("-", "|")))

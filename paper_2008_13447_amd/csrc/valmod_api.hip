@@ -20,6 +20,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
   size_t xs, A, B, mu, sig, invn, flat, df, dg, sw32, thr, thr32, best, counters, anc;
+  size_t hc, hS, hn, hbound, hsig, acnt, abuf, fail;
   size_t total;
 };
 
@@ -56,7 +57,16 @@ PassGeom pass_geom(int64_t n, int32_t l_min, int32_t excl_den) {
   return g;
 }
 
-enum { CNT_ERR = 0, CNT_NFLAT = 1, CNT_EV_STEPS = 2, CNT_EV_HITS = 3, CNT_APPENDS = 4, CNT_WORDS = 32 };
+enum {
+  CNT_ERR = 0,
+  CNT_NFLAT = 1,
+  CNT_EV_STEPS = 2,
+  CNT_EV_HITS = 3,
+  CNT_APPENDS = 4,
+  CNT_NFAIL = 5,
+  CNT_VALID = 6,
+  CNT_WORDS = 32
+};
 
 }  // namespace
 
@@ -67,6 +77,7 @@ struct valmod_plan_s {
   std::vector<valmod_layout> lay;
   valmod_sizes sizes;
   int64_t nmax = 0, n0max = 0, ancmax = 0;
+  int64_t cap = 0;  // candidate-list capacity per owner of the collecting pass
   std::vector<PassGeom> geom;
   WsLayout ws;
   // timing of the diagonal pass during the last run
@@ -199,6 +210,16 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
   w.best = take(wp * 8);
   w.counters = take(CNT_WORDS * 8);
   w.anc = take((size_t)P->ancmax * 8);
+  const size_t pp = (size_t)P->cfg.p;
+  P->cap = 8 * (int64_t)pp < 64 ? 64 : (8 * (int64_t)pp > 512 ? 512 : 8 * (int64_t)pp);
+  w.hc = take(wp * pp * 4);
+  w.hS = take(wp * pp * 8);
+  w.hn = take(wp * 4);
+  w.hbound = take(wp * 8);
+  w.hsig = take(wp * 8);
+  w.acnt = take(wp * 4);
+  w.abuf = take((size_t)P->n0max * (size_t)P->cap * 4);
+  w.fail = take(wp * 4);
   w.total = off;
   *out = P;
   return VALMOD_OK;
@@ -281,10 +302,10 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
   for (auto& L : P->lay) total_lengths += L.nlen;
 
   // events bracketing every diagonal-pass launch
-  if (P->ev_device != P->cfg.device || (int64_t)P->ev.size() < 2 * total_lengths) {
+  if (P->ev_device != P->cfg.device || (int64_t)P->ev.size() < 4 * total_lengths) {
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     P->ev.clear();
-    for (int64_t i = 0; i < 2 * total_lengths; ++i) {
+    for (int64_t i = 0; i < 4 * total_lengths; ++i) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) {
         status = VALMOD_E_HIP;
@@ -300,6 +321,24 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
 
   VCHECK(hipMemsetAsync(cnt, 0, CNT_WORDS * 8, st));
   {
+    int32_t* hc = (int32_t*)(ws + P->ws.hc);
+    double* hS = (double*)(ws + P->ws.hS);
+    int32_t* hn = (int32_t*)(ws + P->ws.hn);
+    double* hbound = (double*)(ws + P->ws.hbound);
+    double* hsig = (double*)(ws + P->ws.hsig);
+    uint32_t* acnt = (uint32_t*)(ws + P->ws.acnt);
+    int32_t* abuf = (int32_t*)(ws + P->ws.abuf);
+    int32_t* fail = (int32_t*)(ws + P->ws.fail);
+    const int p = P->cfg.p;
+    const int D = p < 15 ? p : 15;
+    const double margin = 1.0e-11;  // pass rounding of the FP64 correlation
+    const double rec_factor = env_int("VALMOD_RECOMPUTE_FACTOR_X100", 80) / 100.0;
+    unsigned long long* hcnt = host_cnt.data();
+    auto read_counters = [&]() -> hipError_t {
+      hipError_t e1 = hipMemcpyAsync(hcnt, cnt, CNT_WORDS * 8, hipMemcpyDeviceToHost, st);
+      if (e1 != hipSuccess) return e1;
+      return hipStreamSynchronize(st);
+    };
     int64_t evi = 0;
     for (int s = 0; s < P->cfg.num_series; ++s) {
       const valmod_layout& Ls = P->lay[s];
@@ -312,20 +351,47 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
       int32_t* vlen = o->valmp_len + Ls.valmp;
       int32_t* vidx = o->valmp_idx + Ls.valmp;
       VCHECK(launch_valmp_init(N0, vnorm, vdist, vlen, vidx, st));
+      // partial profiles are used unless every length is forced through a full pass
+      bool heaps_on = P->cfg.path != VALMOD_PATH_FULL && Ls.l_max > Ls.l_min;
+      int base = 0;             // base length of the current partial profiles (0: none)
+      bool probe_next = false;  // judge the partial profiles at the first length after a rebuild
       for (int L = Ls.l_min; L <= Ls.l_max; ++L) {
         const int64_t t = L - Ls.l_min;
         const int64_t N = n - L + 1;
         const int64_t e = excl_zone(L, excl_den);
         double* pd = o->prof_dist + Ls.prof + t * N0;
         int32_t* pi = o->prof_idx + Ls.prof + t * N0;
-        VCHECK(launch_stats(xs, N, L, L == Ls.l_min, P->cfg.flat_eps, A, B, mu, sig, invn, flat,
-                            &cnt[CNT_NFLAT], st));
+        const int32_t* prev = L > Ls.l_min ? pi - N0 : nullptr;
+        VCHECK(launch_stats(xs, N, L, L == Ls.l_min, P->cfg.flat_eps, A, B, mu, sig, invn, flat, &cnt[CNT_NFLAT],
+                            st));
         VCHECK(launch_anchor(xs, n, L, L == Ls.l_min, G.H, G.dstart, G.segs, G.stride, G.stride, anc, st));
         VCHECK(launch_prep_f64(xs, mu, sig, invn, N, L, df, dg, sw32, st));
-        const int32_t* prev = L > Ls.l_min ? pi - N0 : nullptr;
-        VCHECK(launch_seed_mp(xs, mu, invn, flat, prev, N, L, e, best, thr, thr32, st));
-        VCHECK(hipEventRecord(P->ev[evi], st));
-        {
+
+        int64_t nvalid = 0, nfail = 0, nrecomp = 0, nswept_fail = 0;
+        bool full = true, rebuild = false;
+        if (L == Ls.l_min) {
+          rebuild = heaps_on;
+        } else if (heaps_on && base > 0) {
+          // Alg. ComputeSubMP: sweep the partial profiles, certify by the lower bound
+          VCHECK(hipMemsetAsync(&cnt[CNT_NFAIL], 0, 16, st));
+          VCHECK(launch_sweep(xs, A, invn, sig, flat, N, L, e, p, base, hc, hS, hn, hbound, hsig, best, fail,
+                              &cnt[CNT_NFAIL], &cnt[CNT_VALID], st));
+          VCHECK(read_counters());
+          nfail = nswept_fail = (int64_t)hcnt[CNT_NFAIL];
+          nvalid = (int64_t)hcnt[CNT_VALID];
+          // row recompute of the failing windows vs one full pass (cost model in FMA-equivalents)
+          const double cells = 0.5 * (double)N * (double)N;
+          const bool cheap = (double)nfail * (double)N * (double)L <= rec_factor * cells;
+          if (P->cfg.path == VALMOD_PATH_RECOMPUTE || cheap) {
+            full = false;
+          } else if (probe_next && (double)nfail > 0.25 * (double)N) {
+            heaps_on = false;  // the bound fails right after a rebuild: partial profiles do not pay here
+          } else {
+            rebuild = true;
+          }
+          probe_next = false;
+        }
+        if (full) {
           PassLaunch pl{};
           pl.xs = xs;
           pl.mu = mu;
@@ -345,18 +411,56 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
           pl.dstart = G.dstart;
           pl.L = L;
           pl.K = G.K;
-          pl.append = false;
           pl.events = &cnt[CNT_EV_STEPS];
-          VCHECK(launch_pass(pl, st));
+          pl.cnt = acnt;
+          pl.buf = abuf;
+          pl.cap = P->cap;
+          const int32_t* src = prev;
+          if (!rebuild || L == Ls.l_min) {
+            // matrix-profile mode: running best keys seeded from the previous length
+            VCHECK(launch_seed_mp(xs, mu, invn, flat, prev, N, L, e, best, thr, thr32, st));
+            pl.append = false;
+            VCHECK(hipEventRecord(P->ev[evi], st));
+            VCHECK(launch_pass(pl, st));
+            VCHECK(hipEventRecord(P->ev[evi + 1], st));
+            evi += 2;
+            P->pass_launches += 1;
+            P->pass_cells += pass_grid(N, e, G.dstart, G.K, G.H).cells;
+            if (rebuild) {  // first length: the exact neighbours seed the collecting pass
+              VCHECK(launch_keys_to_idx(best, N, pi, st));
+              src = pi;
+            }
+          }
+          if (rebuild) {
+            // collecting pass: every candidate above a per-owner threshold, then an
+            // exact merge into the partial profiles at base L (Alg. ComputeMatrixProfile)
+            VCHECK(hipMemsetAsync(&cnt[CNT_NFAIL], 0, 8, st));
+            const int best_exact = L == Ls.l_min ? 1 : 0;  // the matrix-profile pass just ran
+            VCHECK(launch_seed_append(xs, A, invn, flat, src, N, L, e, p, D, margin, best_exact, thr, acnt, fail,
+                                      &cnt[CNT_NFAIL], st));
+            pl.append = true;
+            VCHECK(hipEventRecord(P->ev[evi], st));
+            VCHECK(launch_pass(pl, st));
+            VCHECK(hipEventRecord(P->ev[evi + 1], st));
+            evi += 2;
+            P->pass_launches += 1;
+            P->pass_cells += pass_grid(N, e, G.dstart, G.K, G.H).cells;
+            VCHECK(launch_merge(xs, A, invn, sig, flat, thr, acnt, abuf, P->cap, N, L, p, margin, best_exact, hc, hS,
+                                hn, hbound, hsig, best, fail, &cnt[CNT_NFAIL], &cnt[CNT_APPENDS], st));
+            VCHECK(read_counters());
+            nfail = (int64_t)hcnt[CNT_NFAIL];
+            base = L;
+            probe_next = true;
+          }
         }
-        VCHECK(hipEventRecord(P->ev[evi + 1], st));
-        evi += 2;
-        P->pass_launches += 1;
-        P->pass_cells += pass_grid(N, e, G.dstart, G.K, G.H).cells;
+        if (nfail > 0 && (!full || rebuild)) {
+          VCHECK(launch_recompute(xs, A, invn, flat, fail, nfail, N, L, e, best, st));
+          nrecomp = nfail;
+        }
         VCHECK(launch_finalize(xs, mu, sig, best, N, L, pd, pi, vnorm, vdist, vlen, vidx, st));
         VCHECK(launch_fill_tail(N, N0, pd, pi, st));
-        VCHECK(launch_record_stats(cnt, o->stats ? o->stats + Ls.stats + t * VALMOD_NSTATS : nullptr, 1, 0, 0, 0,
-                                   st));
+        VCHECK(launch_record_stats(cnt, o->stats ? o->stats + Ls.stats + t * VALMOD_NSTATS : nullptr, full ? 1 : 0,
+                                   nvalid, nswept_fail, nrecomp, st));
       }
       VCHECK(launch_rankings(o->prof_dist + Ls.prof, o->prof_idx + Ls.prof, N0, n, Ls.l_min, (int)Ls.nlen,
                              excl_den, km, kd, o->motif_ab + 2 * Ls.motif, o->motif_d + Ls.motif,
@@ -366,8 +470,7 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
                                 o->g_motif_abl + 3 * Ls.g_motif, o->g_motif_d + 2 * Ls.g_motif,
                                 o->g_discord_onl + 3 * Ls.g_discord, o->g_discord_d + 2 * Ls.g_discord, st));
     }
-    VCHECK(hipMemcpyAsync(host_cnt.data(), cnt, CNT_WORDS * 8, hipMemcpyDeviceToHost, st));
-    VCHECK(hipStreamSynchronize(st));
+    VCHECK(read_counters());
     for (int64_t i = 0; i < evi; i += 2) {
       float ms = 0.f;
       VCHECK(hipEventElapsedTime(&ms, P->ev[i], P->ev[i + 1]));

@@ -66,4 +66,24 @@ hipError_t launch_global_rank(const double* valmp_norm, const double* valmp_dist
                               int32_t* g_motif_abl, double* g_motif_d, int32_t* g_discord_onl,
                               double* g_discord_d, hipStream_t st);
 
+// partial distance profiles (valmod_heap.hip)
+hipError_t launch_seed_append(const double* xs, const double* A, const double* invn, const uint8_t* flat,
+                              const int32_t* src, int64_t N, int L, int64_t e, int p, int D, double margin,
+                              int best_exact, double* thr, uint32_t* cnt, int32_t* fail, unsigned long long* nfail,
+                              hipStream_t st);
+hipError_t launch_merge(const double* xs, const double* A, const double* invn, const double* sig, const uint8_t* flat,
+                        const double* thr, const uint32_t* cnt, const int32_t* buf, int64_t cap, int64_t N, int L,
+                        int p, double margin, int best_exact, int32_t* hc, double* hS, int32_t* hn, double* hbound,
+                        double* hsig, uint64_t* best, int32_t* fail, unsigned long long* nfail,
+                        unsigned long long* nappend, hipStream_t st);
+hipError_t launch_sweep(const double* xs, const double* A, const double* invn, const double* sig, const uint8_t* flat,
+                        int64_t N, int L, int64_t e, int p, int base, const int32_t* hc, double* hS, const int32_t* hn,
+                        const double* hbound, const double* hsig, uint64_t* best, int32_t* fail,
+                        unsigned long long* nfail, unsigned long long* nvalid, hipStream_t st);
+hipError_t launch_recompute(const double* xs, const double* A, const double* invn, const uint8_t* flat,
+                            const int32_t* fail, int64_t nfail, int64_t N, int L, int64_t e, uint64_t* best,
+                            hipStream_t st);
+// copies best keys into an int32 index array (-1 for empty keys)
+hipError_t launch_keys_to_idx(const uint64_t* best, int64_t N, int32_t* idx, hipStream_t st);
+
 }  // namespace valmod

@@ -156,296 +156,6 @@ __global__ void k_seed_mp(const double* __restrict__ xs, const double* __restric
 }
 
 // --------------------------------------------------------------------------
-// Anchor table of the diagonal pass (the first-row dot products of
-// Alg. ComputeMatrixProfile, one per work item and diagonal):
-//   S(i0, i0 + d) = sum_{k<L} (x_{i0+k} - x_{i0}) (x_{i0+d+k} - x_{i0+d})
-// for every segment start row i0 = seg * H and diagonal d >= dstart. Values
-// are excursions from each window's first point (no large-offset
-// cancellation); the pass turns them into co-moments with C = S - A_i A_j / L.
-// k_anchor_init forms them directly (L FMAs each); when the length grows by one
-// k_anchor_grow adds the single new term, so later lengths cost O(1) per anchor.
-__global__ void k_anchor_init(const double* __restrict__ xs, int64_t n, int L, int64_t H, int64_t dstart,
-                              int64_t stride, int64_t ncols, double* __restrict__ anc) {
-  const int64_t seg = blockIdx.y;
-  const int64_t dd = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (dd >= ncols) return;
-  const int64_t i0 = seg * H;
-  const int64_t j0 = i0 + dstart + dd;
-  double acc = 0.0;
-  if (j0 + L <= n) {
-    const double xi = xs[i0], xj = xs[j0];
-    for (int k = 1; k < L; ++k) acc = fma(xs[i0 + k] - xi, xs[j0 + k] - xj, acc);
-  }
-  anc[seg * stride + dd] = acc;
-}
-
-__global__ void k_anchor_grow(const double* __restrict__ xs, int64_t n, int L, int64_t H, int64_t dstart,
-                              int64_t stride, int64_t ncols, double* __restrict__ anc) {
-  // L is the new length: adds the term k = L - 1
-  const int64_t seg = blockIdx.y;
-  const int64_t dd = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (dd >= ncols) return;
-  const int64_t i0 = seg * H;
-  const int64_t j0 = i0 + dstart + dd;
-  if (j0 + L > n) return;
-  anc[seg * stride + dd] = fma(xs[i0 + L - 1] - xs[i0], xs[j0 + L - 1] - xs[j0], anc[seg * stride + dd]);
-}
-
-// --------------------------------------------------------------------------
-// Diagonal pass (Alg. ComputeMatrixProfile).
-//
-// One wavefront owns a band of 64*K adjacent diagonals d = j - i (K per lane)
-// and a segment of H rows. Each lane runs the co-moment recurrence of its K
-// diagonals in registers, from an FP64 anchor computed directly at the
-// segment's first row. Every cell (i, j) is seen once and serves two owners by
-// symmetry: row owner i (candidate j) and column owner j (candidate i).
-//
-// The per-cell work is two FMAs and one compare. The compare is a filter in
-// co-moment space: for owner thresholds thr (in correlation units) the cell can
-// matter only if rho = C / (sw_i sw_j) >= min(thr_i, thr_j), with
-// sw = sigma * sqrt(L). Over a block of K rows the filter uses
-//   tau_j = min(thr_j, min_rows thr_i) * sw_j * min_rows sw_i   (times 1 - 1e-12),
-// which is never larger than the exact per-cell bound, so no qualifying cell is
-// skipped. Cells that pass go to a slow path that evaluates rho exactly and
-// applies the mode's action:
-//   MODE_MP     : running best of each owner as a packed (distance, index) key
-//                 updated by 64-bit atomic min; thr = the running best's bound.
-//   MODE_APPEND : thr is a fixed per-owner threshold; every candidate with
-//                 rho >= thr is appended to the owner's list (the partial
-//                 distance profile of Alg. ComputeMatrixProfile, collected as all
-//                 candidates above a threshold instead of a heap insert per cell).
-// Column data slide through a per-lane register window of K columns (one new
-// column per row, 32-bit offsets off a uniform base); row data are wave-uniform
-// scalar loads, once per K rows.
-enum { MODE_MP = 0, MODE_APPEND = 1 };
-
-struct PassArgs {
-  double* thr;         // per-owner threshold (correlation units)
-  uint64_t* best;      // MODE_MP: packed best key per owner
-  uint32_t* cnt;       // MODE_APPEND: candidates appended per owner
-  int32_t* buf;        // MODE_APPEND: owner-major candidate lists
-  int64_t cap;         // MODE_APPEND: list capacity per owner
-  unsigned long long* events;  // [0] wave-steps that took the slow path, [1] owner hits
-  int64_t anc_stride;  // anchor-table row length (diagonals per segment row)
-  int64_t N, e, H, dstart;
-  int L;
-};
-
-template <typename T>
-__device__ __forceinline__ T ldo(const T* base, uint32_t off) {
-  return *(const T*)((const char*)base + off);
-}
-
-// Wide per-lane loads of `n` consecutive doubles (lanes read adjacent ranges,
-// so a wavefront reads one contiguous block).
-template <int n>
-__device__ __forceinline__ void load_run(const double* p, double* dst) {
-#pragma unroll
-  for (int u = 0; u < n; u += 2) {
-    const double2 v = *(const double2*)(p + u);
-    dst[u] = v.x;
-    dst[u + 1] = v.y;
-  }
-}
-
-// Per-wavefront LDS queue of slow-path results. The step loop issues no global
-// writes or atomics (on gfx9 they share the load counter with the prefetch
-// loads, and a write inside a data-dependent branch makes every later wait
-// drain all prefetches); the queue is flushed to global memory when it could
-// overflow at the next step and at the end of the work item.
-constexpr int kQueue = 1024;
-
-// min of two thresholds (never NaN) without the IEEE quieting of the operands
-// that fmin() implies.
-__device__ __forceinline__ double vmin_f64(double a, double b) {
-  double r;
-  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
-
-template <int K, int MODE>
-__global__ __launch_bounds__(kWave) void k_pass(const double* __restrict__ g_df, const double* __restrict__ g_dg,
-                                                const double* __restrict__ g_invn, const double* __restrict__ g_thr,
-                                                const double* __restrict__ g_anc, const double* __restrict__ g_A,
-                                                PassArgs a) {
-  // g_thr aliases a.thr: threshold reads through it may return values older than
-  // this kernel's own updates, which only makes the filter looser (never unsound).
-  static_assert(K % 4 == 0, "K must be a multiple of 4");
-  constexpr int64_t BW = (int64_t)kWave * K;  // diagonals per band
-  constexpr int HK = K / 2;
-  __shared__ int32_t q_owner[kQueue];
-  __shared__ uint64_t q_val[kQueue];  // MODE_MP: packed key; MODE_APPEND: candidate index
-  const int t = threadIdx.x;
-  const int64_t N = a.N;
-  const int64_t d0 = a.dstart + (int64_t)blockIdx.y * BW;
-  if (d0 > N - 1) return;
-  const int64_t i0 = (int64_t)blockIdx.x * a.H;
-  const int64_t rowEnd = N - d0;
-  if (i0 >= rowEnd) return;
-  const int rows = (int)((i0 + a.H < rowEnd ? i0 + a.H : rowEnd) - i0);
-  const int64_t dl = d0 + (int64_t)K * t;
-
-  // co-moments at row i0 from the FP64 anchor table: C = S - A_i A_j / L
-  double C[K];
-  {
-    double S[K], Aj[K];
-    load_run<K>(g_anc + (int64_t)blockIdx.x * a.anc_stride + (dl - a.dstart), S);
-    load_run<K>(g_A + i0 + dl, Aj);
-    const double Ai = g_A[i0] / (double)a.L;
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-      const int64_t j = i0 + dl + q;
-      C[q] = (dl + q > a.e && j < N) ? S[q] - Ai * Aj[q] : -INFINITY;  // trivial or past the end
-    }
-  }
-
-  // Column window: at step u of a block, slot s holds column i + dl + ((s - u) mod K).
-  // Two register sets X and Y alternate by block: during a block whose slots
-  // start in set P, slot s moves to set Q (holding the column that enters) at
-  // step s, and the freed entries of P receive the next block's entering
-  // columns, a half block at a time. No register copies are needed.
-  double Xdf[K], Xdg[K], Xinv[K], Xthr[K];
-  double Ydf[K], Ydg[K], Yinv[K], Ythr[K];
-  {
-    const int64_t c0 = i0 + dl;
-    load_run<K>(g_df + c0, Xdf);
-    load_run<K>(g_dg + c0, Xdg);
-    load_run<K>(g_invn + c0, Xinv);
-    load_run<K>(g_thr + c0, Xthr);
-    load_run<K>(g_df + c0 + K, Ydf);
-    load_run<K>(g_dg + c0 + K, Ydg);
-    load_run<K>(g_invn + c0 + K, Yinv);
-    load_run<K>(g_thr + c0 + K, Ythr);
-  }
-  int qn = 0;  // queue fill (wave-uniform)
-  unsigned long long ev_steps = 0;
-
-  auto flush = [&]() {
-    __syncthreads();
-    for (int b = 0; b < qn; b += kWave) {
-      if (b + t < qn) {
-        const int32_t own = q_owner[b + t];
-        const uint64_t v = q_val[b + t];
-        if (MODE == MODE_MP) {
-          atomicMin((unsigned long long*)&a.best[own], (unsigned long long)v);
-          const double nt = key_threshold(v);
-          if (nt > a.thr[own]) a.thr[own] = nt;  // racy but every stored value is a real candidate's bound
-        } else {
-          const uint32_t pos = atomicAdd(&a.cnt[own], 1u);
-          if ((int64_t)pos < a.cap) a.buf[(int64_t)own * a.cap + pos] = (int32_t)v;
-        }
-      }
-    }
-    if (a.events && t == 0) atomicAdd(&a.events[1], (unsigned long long)qn);
-    __syncthreads();
-    qn = 0;
-  };
-  auto push = [&](bool want, int32_t owner, uint64_t val) {
-    const uint64_t m = __ballot(want);
-    if (!m) return;
-    if (want) {
-      const int pos = qn + __popcll(m & ((uint64_t(1) << t) - 1));
-      q_owner[pos] = owner;
-      q_val[pos] = val;
-    }
-    qn += __popcll(m);
-  };
-
-  // one block of K rows starting at row ib; slots start in P and move to Q
-  auto block = [&](int64_t ib, double* Pdf, double* Pdg, double* Pinv, double* Pthr, double* Qdf, double* Qdg,
-                   double* Qinv, double* Qthr) {
-    double rdf[K], rdg[K], rinv[K], rthr[K];
-#pragma unroll
-    for (int u = 0; u < K; ++u) {
-      rdf[u] = g_df[ib + u];
-      rdg[u] = g_dg[ib + u];
-      rinv[u] = g_invn[ib + u];
-      rthr[u] = g_thr[ib + u];
-    }
-    const int64_t cn = ib + dl + 2 * K;  // first column entering during the next block
-    // Every block runs all K steps: rows past the segment or the series only meet
-    // columns past the end (zero inverse norm, padded thresholds), so they never
-    // produce a queue entry, and all their reads stay inside the zero padding.
-#pragma unroll
-    for (int u = 0; u < K; ++u) {
-      const int64_t i = ib + u;
-      // exact correlation of every cell and the test against both owners' thresholds
-      bool pass = false;
-#pragma unroll
-      for (int q = 0; q < K; ++q) {
-        const int s = (q + u) % K;
-        const double inv = s < u ? Qinv[s] : Pinv[s];
-        const double th = s < u ? Qthr[s] : Pthr[s];
-        pass |= (C[q] * inv) * rinv[u] >= vmin_f64(th, rthr[u]);
-      }
-      if (__any(pass)) {
-        ++ev_steps;
-        if (qn + kWave * K + 1 > kQueue) flush();
-        uint64_t rowkey = kEmptyKey;
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-          const int s = (q + u) % K;
-          const int64_t j = i + dl + q;
-          const double inv = s < u ? Qinv[s] : Pinv[s];
-          double& th = s < u ? Qthr[s] : Pthr[s];
-          const double rho = (C[q] * inv) * rinv[u];
-          const bool ok = j < N && rinv[u] > 0.0 && inv > 0.0;
-          const bool col = ok && rho >= th;
-          if (MODE == MODE_MP) {
-            const uint64_t key = col ? make_key(rho, i) : kEmptyKey;
-            push(col, (int32_t)j, key);
-            if (col) {
-              const double nt = key_threshold(key);
-              th = nt > th ? nt : th;
-            }
-            if (ok && rho >= rthr[u]) {
-              const uint64_t k2 = make_key(rho, j);
-              rowkey = k2 < rowkey ? k2 : rowkey;
-            }
-          } else {
-            push(col, (int32_t)j, (uint64_t)i);
-            push(ok && rho >= rthr[u], (int32_t)i, (uint64_t)j);
-          }
-        }
-        if (MODE == MODE_MP && __any(rowkey != kEmptyKey)) {
-          rowkey = wave_min_u64(rowkey);
-          push(t == 0, (int32_t)i, rowkey);
-        }
-      }
-      // advance every diagonal one row: C(i+1, j+1) = C(i, j) + df_i dg_j + df_j dg_i
-#pragma unroll
-      for (int q = 0; q < K; ++q) {
-        const int s = (q + u) % K;
-        const double cdf = s < u ? Qdf[s] : Pdf[s];
-        const double cdg = s < u ? Qdg[s] : Pdg[s];
-        C[q] = fma(rdf[u], cdg, C[q]);
-        C[q] = fma(cdf, rdg[u], C[q]);
-      }
-      // slot u now moves to Q (column i + dl + K). Freed P entries take the
-      // next block's entering columns, half a block at a time.
-      if (u == HK - 1) {
-        load_run<HK>(g_df + cn, Pdf);
-        load_run<HK>(g_dg + cn, Pdg);
-        load_run<HK>(g_invn + cn, Pinv);
-        load_run<HK>(g_thr + cn, Pthr);
-      } else if (u == K - 1) {
-        load_run<HK>(g_df + cn + HK, Pdf + HK);
-        load_run<HK>(g_dg + cn + HK, Pdg + HK);
-        load_run<HK>(g_invn + cn + HK, Pinv + HK);
-        load_run<HK>(g_thr + cn + HK, Pthr + HK);
-      }
-    }
-  };
-
-  for (int sb = 0; sb < rows; sb += 2 * K) {
-    block(i0 + sb, Xdf, Xdg, Xinv, Xthr, Ydf, Ydg, Yinv, Ythr);
-    if (sb + K < rows) block(i0 + sb + K, Ydf, Ydg, Yinv, Ythr, Xdf, Xdg, Xinv, Xthr);
-  }
-  if (qn > 0) flush();
-  if (a.events && t == 0 && ev_steps) atomicAdd(&a.events[0], ev_steps);
-}
-
-// --------------------------------------------------------------------------
 // Matrix-profile entries at L from the best keys: the FP64 distance of every
 // chosen pair is evaluated directly from the z-normalised windows (no closed
 // form, exact near d = 0), in a canonical (min, max) order so d(i, j) = d(j, i)
@@ -797,59 +507,6 @@ hipError_t launch_seed_mp(const double* xs, const double* mu, const double* invn
   return hipGetLastError();
 }
 
-PassGrid pass_grid(int64_t N, int64_t e, int64_t dstart, int K, int64_t H) {
-  PassGrid g;
-  const int64_t ndiag = N - 1 - e;    // non-trivial diagonals e+1 .. N-1
-  const int64_t nband = N - dstart;   // diagonals covered by the bands: dstart .. N-1
-  const int64_t bw = (int64_t)kWave * K;
-  g.bands = ndiag > 0 ? (nband + bw - 1) / bw : 0;
-  g.segs = ndiag > 0 ? (N - dstart + H - 1) / H : 0;  // the first band has N - dstart rows
-  g.cells = ndiag > 0 ? ndiag * (ndiag + 1) / 2 : 0;
-  return g;
-}
-
-hipError_t launch_anchor(const double* xs, int64_t n, int L, bool init, int64_t H, int64_t dstart, int64_t segs,
-                         int64_t stride, int64_t ncols, double* anc, hipStream_t st) {
-  if (segs <= 0 || ncols <= 0) return hipSuccess;
-  dim3 grid(blocks_for(ncols, 256), (unsigned)segs);
-  if (init)
-    k_anchor_init<<<grid, 256, 0, st>>>(xs, n, L, H, dstart, stride, ncols, anc);
-  else
-    k_anchor_grow<<<grid, 256, 0, st>>>(xs, n, L, H, dstart, stride, ncols, anc);
-  return hipGetLastError();
-}
-
-template <int K>
-static hipError_t launch_pass_k(const PassLaunch& p, hipStream_t st) {
-  const PassGrid g = pass_grid(p.N, p.e, p.dstart, K, p.H);
-  if (g.bands == 0) return hipSuccess;
-  PassArgs a;
-  a.thr = p.thr;
-  a.events = p.events;
-  a.best = p.best;
-  a.cnt = p.cnt;
-  a.buf = p.buf;
-  a.cap = p.cap;
-  a.N = p.N;
-  a.e = p.e;
-  a.H = p.H;
-  a.dstart = p.dstart;
-  a.anc_stride = p.anc_stride;
-  a.L = p.L;
-  dim3 grid((unsigned)g.segs, (unsigned)g.bands);
-  if (p.append)
-    k_pass<K, MODE_APPEND><<<grid, kWave, 0, st>>>(p.df, p.dg, p.invn, p.thr, p.anc, p.A, a);
-  else
-    k_pass<K, MODE_MP><<<grid, kWave, 0, st>>>(p.df, p.dg, p.invn, p.thr, p.anc, p.A, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_pass(const PassLaunch& p, hipStream_t st) {
-  if (p.K == 8) return launch_pass_k<8>(p, st);
-  if (p.K == 4) return launch_pass_k<4>(p, st);
-  return hipErrorInvalidValue;
-}
-
 hipError_t launch_finalize(const double* xs, const double* mu, const double* sig, const uint64_t* best,
                            int64_t N, int L, double* prof_dist, int32_t* prof_idx, double* valmp_norm,
                            double* valmp_dist, int32_t* valmp_len, int32_t* valmp_idx, hipStream_t st) {
@@ -861,6 +518,19 @@ hipError_t launch_finalize(const double* xs, const double* mu, const double* sig
 hipError_t launch_record_stats(unsigned long long* cnt, int64_t* row, int full_pass, int64_t valid,
                                int64_t failed, int64_t recomputed, hipStream_t st) {
   k_record_stats<<<1, 64, 0, st>>>(cnt, row, full_pass, valid, failed, recomputed);
+  return hipGetLastError();
+}
+
+__global__ void k_keys_to_idx(const uint64_t* __restrict__ best, int64_t N, int32_t* __restrict__ idx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const uint64_t k = best[i];
+  idx[i] = k == kEmptyKey ? -1 : (int32_t)key_cand(k);
+}
+
+hipError_t launch_keys_to_idx(const uint64_t* best, int64_t N, int32_t* idx, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  k_keys_to_idx<<<blocks_for(N, 256), 256, 0, st>>>(best, N, idx);
   return hipGetLastError();
 }
 

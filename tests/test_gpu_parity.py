@@ -161,3 +161,52 @@ def test_config2_sampled_parity(oracle_mod):
     norm = g["prof_dist"] * np.sqrt(1.0 / L)
     np.testing.assert_allclose(g["valmp_norm"], norm.min(axis=0), rtol=0, atol=1e-15)
     assert nl == g["prof_dist"].shape[0] and n0 == g["prof_dist"].shape[1]
+
+
+@pytest.mark.parametrize("path", ["full", "recompute", "auto"])
+@pytest.mark.parametrize("p", [1, 5, 20])
+def test_paths_and_p_give_the_exact_profiles(oracle_mod, path, p):
+    """Exact mode: the outputs do not depend on the path (full passes, sweep +
+    recompute, cost model) nor on the partial-profile size p."""
+    from oracle import compare
+
+    x = gen.small_random_walk(1800, 60, np.float32)
+    lo, hi = 30, 45
+    _say(f"path={path} p={p}")
+    g = run_gpu(x, lo, hi, p=p, k_motifs=3, k_discords=3, path=path)
+    r = oracle_mod.valmod(x, lo, hi, k_motifs=3, k_discords=3)
+    compare.check_full(x, lo, g, r, TOL64)
+    st = g["stats"]
+    if path == "recompute":
+        assert st[0, 3] == 1 and (st[1:, 3] == 0).all()  # full pass only at l_min
+        N = x.shape[0] - np.arange(lo + 1, hi + 1) + 1
+        assert ((st[1:, 0] + st[1:, 1]) == N).all()         # every owner is valid or failing
+        assert (st[1:, 2] == st[1:, 1]).all()               # every failing owner is recomputed
+    if path == "full":
+        assert (st[:, 3] == 1).all()
+
+
+def test_large_p_certifies_every_window(oracle_mod):
+    """P6: with p >= N - 1 no candidate is left out of a partial profile, so the
+    bound test passes for every window that still has a stored candidate."""
+    from oracle import compare
+
+    x = gen.small_random_walk(420, 61)
+    lo, hi = 16, 22
+    g = run_gpu(x, lo, hi, p=500, k_motifs=2, k_discords=2, path="recompute")
+    r = oracle_mod.valmod(x, lo, hi, k_motifs=2, k_discords=2)
+    compare.check_full(x, lo, g, r, TOL64)
+    assert (g["stats"][1:, 1] == 0).all(), g["stats"]
+
+
+def test_partial_profiles_on_flat_segments(oracle_mod):
+    """Windows that are flat at the base length but not at a longer one have a
+    zero lower bound and must be recomputed."""
+    from oracle import compare
+
+    x = gen.small_random_walk(2000, 62) + 1.0e4
+    x[500:800] = x[500]
+    x = x.astype(np.float32)
+    g = run_gpu(x, 20, 34, p=10, k_motifs=3, k_discords=3, path="recompute")
+    r = oracle_mod.valmod(x, 20, 34, k_motifs=3, k_discords=3)
+    compare.check_full(x, 20, g, r, TOL64)
