@@ -65,7 +65,12 @@ typedef enum {
 typedef enum { VALMOD_F32 = 0, VALMOD_F64 = 1 } valmod_dtype;
 
 /* Arithmetic of the diagonal recurrence. Statistics, lower bounds, the length
- * sweep and every reported distance are FP64 in both modes. */
+ * sweep and every reported distance are FP64 in both modes, and both modes
+ * return the same exact results: the FP32 recurrence only selects candidates,
+ * with a threshold widened by a rigorous bound of its rounding error per work
+ * item; work items whose bound exceeds a limit run in FP64, and every selected
+ * candidate is re-evaluated in FP64. The first length of each series is an FP64
+ * matrix-profile pass in both modes. */
 typedef enum {
   VALMOD_PREC_FP64 = 0,        /* recurrence in FP64 */
   VALMOD_PREC_FP32_REFRESH = 1 /* recurrence in FP32, restarted from FP64 dot products every R rows */
@@ -93,7 +98,8 @@ typedef struct {
   double flat_eps;          /* flat-window threshold; 0 = default 2^-20 */
   int32_t dtype;            /* valmod_dtype of the input series */
   int32_t precision;        /* valmod_precision */
-  int32_t refresh_R;        /* FP32 refresh interval in rows; 0 = default */
+  int32_t refresh_R;        /* FP32 refresh interval R in rows: 0 = default 512, else a multiple
+                               of 16 in [64, 8192]; the rounding bound grows linearly with R */
   int32_t path;             /* valmod_path */
   int32_t device;           /* HIP device ordinal the plan runs on */
 } valmod_config;
@@ -110,7 +116,9 @@ enum {
   VALMOD_STAT_APPENDS = 5,    /* candidates collected by the full pass (0 if none) */
   VALMOD_STAT_PASS_EVENTS = 6,/* wavefront steps of the diagonal pass that took its slow path */
   VALMOD_STAT_PASS_HITS = 7,  /* owner updates made by the diagonal pass */
-  VALMOD_NSTATS = 8
+  VALMOD_STAT_FP64_ITEMS = 8, /* FP32 path: work items whose rounding bound sent them to the FP64 kernel */
+  VALMOD_STAT_PASSES = 9,     /* diagonal-pass launches at this length */
+  VALMOD_NSTATS = 10
 };
 
 /*
@@ -206,9 +214,11 @@ VALMOD_API void valmod_plan_free(valmod_plan_t plan);
 /* Human-readable name of a status code (static string). */
 VALMOD_API const char* valmod_status_str(int status);
 
-/* Milliseconds spent in the diagonal-pass kernel during the last valmod_run,
- * measured with HIP events on the run's stream, and the number of those launches
- * and of the cells they computed. */
+/* Milliseconds spent in the diagonal-pass kernel of the plan's precision during
+ * the last valmod_run (full-grid launches only: FP64 mode, every pass; FP32
+ * mode, the FP32 collecting passes, not the FP64 pass of the first length nor
+ * the FP64 re-runs of listed work items), measured with HIP events on the run's
+ * stream, and the number of those launches and of the cells they covered. */
 VALMOD_API valmod_status valmod_last_pass_timing(valmod_plan_t plan, double* ms, int64_t* launches,
                                       int64_t* cells);
 

@@ -21,6 +21,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct WsLayout {
   size_t xs, A, B, mu, sig, invn, flat, df, dg, sw32, thr, thr32, best, counters, anc;
   size_t hc, hS, hn, hbound, hsig, acnt, abuf, fail;
+  size_t df32, dg32, inv32, bsw_max, bsw_min, bdf_max, bdg_max, delta, hard;
   size_t total;
 };
 
@@ -28,6 +29,7 @@ struct WsLayout {
 struct PassGeom {
   int64_t dstart = 0, H = 0, segs = 0, bands = 0, stride = 0;
   int K = 0;
+  bool table = true;  // FP64 anchor table (FP64 recurrence); FP32 items compute their anchors directly
 };
 
 int env_int(const char* name, int dflt) {
@@ -35,11 +37,24 @@ int env_int(const char* name, int dflt) {
   return v && *v ? atoi(v) : dflt;
 }
 
-PassGeom pass_geom(int64_t n, int32_t l_min, int32_t excl_den) {
+PassGeom pass_geom(int64_t n, int32_t l_min, int32_t excl_den, bool fp32, int32_t refresh_R) {
   PassGeom g;
   const int64_t N0 = n - l_min + 1;
   const int64_t e0 = excl_zone(l_min, excl_den);
   g.K = env_int("VALMOD_PASS_K", 8) == 4 ? 4 : 8;
+  if (fp32) {
+    // FP32 recurrence: segments of R rows restart from FP64 anchors (the refresh
+    // interval), computed directly by each work item; R bounds the rounding error.
+    g.K = 8;
+    g.table = false;
+    const int64_t bw = 64 * g.K;
+    g.dstart = (e0 + 1) / 8 * 8;
+    g.H = refresh_R > 0 ? refresh_R : 512;
+    g.bands = (N0 - g.dstart + bw - 1) / bw;
+    g.segs = (N0 - g.dstart + g.H - 1) / g.H;
+    g.stride = g.bands * bw;
+    return g;
+  }
   const int64_t bw = 64 * g.K;
   g.dstart = (e0 + 1) / 8 * 8;  // bands start on a multiple of 8 (aligned wide loads)
   const int64_t ndiag = N0 - 1 - e0;
@@ -65,6 +80,7 @@ enum {
   CNT_APPENDS = 4,
   CNT_NFAIL = 5,
   CNT_VALID = 6,
+  CNT_HARD = 7,
   CNT_WORDS = 32
 };
 
@@ -78,6 +94,7 @@ struct valmod_plan_s {
   valmod_sizes sizes;
   int64_t nmax = 0, n0max = 0, ancmax = 0;
   int64_t cap = 0;  // candidate-list capacity per owner of the collecting pass
+  int64_t itemmax = 0;  // work items of the largest pass grid
   std::vector<PassGeom> geom;
   WsLayout ws;
   // timing of the diagonal pass during the last run
@@ -108,7 +125,9 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
   if (cfg->num_series < 1 || !cfg->n || !cfg->l_min || !cfg->l_max) return fail(VALMOD_E_ARG);
   if (cfg->p < 0 || cfg->k_motifs < 1 || cfg->k_discords < 1 || cfg->k_motifs > 64 || cfg->k_discords > 64)
     return fail(VALMOD_E_ARG);
-  if (cfg->excl_den < 0 || !(cfg->flat_eps >= 0.0) || cfg->refresh_R < 0) return fail(VALMOD_E_ARG);
+  if (cfg->excl_den < 0 || !(cfg->flat_eps >= 0.0)) return fail(VALMOD_E_ARG);
+  if (cfg->refresh_R != 0 && (cfg->refresh_R < 64 || cfg->refresh_R > 8192 || cfg->refresh_R % 16))
+    return fail(VALMOD_E_ARG);
   if (cfg->dtype != VALMOD_F32 && cfg->dtype != VALMOD_F64) return fail(VALMOD_E_ARG);
   if (cfg->precision != VALMOD_PREC_FP64 && cfg->precision != VALMOD_PREC_FP32_REFRESH)
     return fail(VALMOD_E_ARG);
@@ -180,9 +199,12 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
     z.stats += nlen * VALMOD_NSTATS;
     if (n > P->nmax) P->nmax = n;
     if (n0 > P->n0max) P->n0max = n0;
-    P->geom.push_back(pass_geom(n, lo, P->cfg.excl_den));
-    const int64_t anc = P->geom.back().segs * P->geom.back().stride;
+    P->geom.push_back(pass_geom(n, lo, P->cfg.excl_den, P->cfg.precision == VALMOD_PREC_FP32_REFRESH,
+                               P->cfg.refresh_R));
+    const PassGeom& gg = P->geom.back();
+    const int64_t anc = gg.table ? gg.segs * gg.stride : 0;
     if (anc > P->ancmax) P->ancmax = anc;
+    if (gg.segs * gg.bands > P->itemmax) P->itemmax = gg.segs * gg.bands;
   }
 
   // workspace carve-up (sized for the largest series; series run one after another)
@@ -220,6 +242,18 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
   w.acnt = take(wp * 4);
   w.abuf = take((size_t)P->n0max * (size_t)P->cap * 4);
   w.fail = take(wp * 4);
+  if (P->cfg.precision == VALMOD_PREC_FP32_REFRESH) {
+    w.df32 = take(wp * 4);
+    w.dg32 = take(wp * 4);
+    w.inv32 = take(wp * 4);
+    const size_t nb = wp / 64 + 2;
+    w.bsw_max = take(nb * 4);
+    w.bsw_min = take(nb * 4);
+    w.bdf_max = take(nb * 4);
+    w.bdg_max = take(nb * 4);
+    w.delta = take((size_t)P->itemmax * 4);
+    w.hard = take((size_t)P->itemmax * 4);
+  }
   w.total = off;
   *out = P;
   return VALMOD_OK;
@@ -329,6 +363,18 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
     uint32_t* acnt = (uint32_t*)(ws + P->ws.acnt);
     int32_t* abuf = (int32_t*)(ws + P->ws.abuf);
     int32_t* fail = (int32_t*)(ws + P->ws.fail);
+    const bool fp32 = P->cfg.precision == VALMOD_PREC_FP32_REFRESH;
+    float* df32 = fp32 ? (float*)(ws + P->ws.df32) : nullptr;
+    float* dg32 = fp32 ? (float*)(ws + P->ws.dg32) : nullptr;
+    float* inv32 = fp32 ? (float*)(ws + P->ws.inv32) : nullptr;
+    float* bsw_max = fp32 ? (float*)(ws + P->ws.bsw_max) : nullptr;
+    float* bsw_min = fp32 ? (float*)(ws + P->ws.bsw_min) : nullptr;
+    float* bdf_max = fp32 ? (float*)(ws + P->ws.bdf_max) : nullptr;
+    float* bdg_max = fp32 ? (float*)(ws + P->ws.bdg_max) : nullptr;
+    float* delta = fp32 ? (float*)(ws + P->ws.delta) : nullptr;
+    int32_t* hard = fp32 ? (int32_t*)(ws + P->ws.hard) : nullptr;
+    // FP32 work items whose rounding bound exceeds this go to the FP64 kernel
+    const float delta_max = (float)(env_int("VALMOD_FP32_DELTA_MAX_E6", 2000) * 1.0e-6);
     const int p = P->cfg.p;
     const int D = p < 15 ? p : 15;
     const double margin = 1.0e-11;  // pass rounding of the FP64 correlation
@@ -359,15 +405,104 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
         const int64_t t = L - Ls.l_min;
         const int64_t N = n - L + 1;
         const int64_t e = excl_zone(L, excl_den);
+        const PassGrid grid = pass_grid(N, e, G.dstart, G.K, G.H);
         double* pd = o->prof_dist + Ls.prof + t * N0;
         int32_t* pi = o->prof_idx + Ls.prof + t * N0;
         const int32_t* prev = L > Ls.l_min ? pi - N0 : nullptr;
         VCHECK(launch_stats(xs, N, L, L == Ls.l_min, P->cfg.flat_eps, A, B, mu, sig, invn, flat, &cnt[CNT_NFLAT],
                             st));
-        VCHECK(launch_anchor(xs, n, L, L == Ls.l_min, G.H, G.dstart, G.segs, G.stride, G.stride, anc, st));
+        if (G.table) VCHECK(launch_anchor(xs, n, L, L == Ls.l_min, G.H, G.dstart, G.segs, G.stride, G.stride, anc, st));
         VCHECK(launch_prep_f64(xs, mu, sig, invn, N, L, df, dg, sw32, st));
 
-        int64_t nvalid = 0, nfail = 0, nrecomp = 0, nswept_fail = 0;
+        PassLaunch pl{};
+        pl.xs = xs;
+        pl.mu = mu;
+        pl.df = df;
+        pl.dg = dg;
+        pl.sw32 = sw32;
+        pl.invn = invn;
+        pl.df32 = df32;
+        pl.dg32 = dg32;
+        pl.inv32 = inv32;
+        pl.thr = thr;
+        pl.thr32 = thr32;
+        pl.best = best;
+        pl.anc = G.table ? anc : nullptr;
+        pl.A = A;
+        pl.anc_stride = G.stride;
+        pl.N = N;
+        pl.e = e;
+        pl.H = G.H;
+        pl.dstart = G.dstart;
+        pl.L = L;
+        pl.K = G.K;
+        pl.events = &cnt[CNT_EV_STEPS];
+        pl.cnt = acnt;
+        pl.buf = abuf;
+        pl.cap = P->cap;
+        int64_t passes = 0;
+        // full-grid launch of the plan's own pass kernel: bracketed by events
+        auto timed_pass = [&](const PassLaunch& q) -> hipError_t {
+          const bool tm = evi + 2 <= (int64_t)P->ev.size();
+          hipError_t e1 = tm ? hipEventRecord(P->ev[evi], st) : hipSuccess;
+          if (e1 == hipSuccess) e1 = launch_pass(q, st);
+          if (e1 == hipSuccess && tm) e1 = hipEventRecord(P->ev[evi + 1], st);
+          if (tm) evi += 2;
+          P->pass_launches += 1;
+          P->pass_cells += grid.cells;
+          ++passes;
+          return e1;
+        };
+        bool fp32_ready = false;
+        // FP32 inputs and the per-item rounding bounds at this length; items over
+        // the limit are listed for the FP64 kernel
+        auto fp32_setup = [&]() -> hipError_t {
+          if (fp32_ready) return hipSuccess;
+          fp32_ready = true;
+          hipError_t e1 = launch_fp32_prep(sig, invn, df, dg, N, L, df32, dg32, inv32, bsw_max, bsw_min, bdf_max,
+                                           bdg_max, st);
+          if (e1 == hipSuccess) e1 = hipMemsetAsync(&cnt[CNT_HARD], 0, 8, st);
+          if (e1 == hipSuccess)
+            e1 = launch_fp32_items(bsw_max, bsw_min, bdf_max, bdg_max, N, e, G.dstart, G.K, G.H, delta_max, delta,
+                                   hard, &cnt[CNT_HARD], st);
+          return e1;
+        };
+        int64_t listed = 0;  // owners in the recompute list
+        // collecting pass above per-owner thresholds from the candidates of `src`,
+        // then the exact merge (top-`keep` partial profiles and best keys)
+        auto collect = [&](const int32_t* src, int p_eff, int keep, int best_exact) -> hipError_t {
+          hipError_t e1 = hipMemsetAsync(&cnt[CNT_NFAIL], 0, 8, st);
+          if (e1 == hipSuccess)
+            e1 = launch_seed_append(xs, A, invn, flat, src, N, L, e, p_eff, D, margin, best_exact, thr, acnt, fail,
+                                    &cnt[CNT_NFAIL], st);
+          PassLaunch q = pl;
+          q.append = true;
+          if (fp32) {
+            if (e1 == hipSuccess) e1 = fp32_setup();
+            if (e1 == hipSuccess) e1 = launch_thr_to_f32(thr, N + kPad, thr32, st);
+            q.fp32 = true;
+            q.delta = delta;
+            q.delta_max = delta_max;
+            if (e1 == hipSuccess) e1 = timed_pass(q);
+            PassLaunch h = pl;
+            h.append = true;
+            h.items = hard;
+            h.nitems = grid.segs * grid.bands;
+            h.nitems_dev = &cnt[CNT_HARD];
+            if (e1 == hipSuccess) e1 = launch_pass(h, st);
+            ++passes;
+          } else if (e1 == hipSuccess) {
+            e1 = timed_pass(q);
+          }
+          if (e1 == hipSuccess)
+            e1 = launch_merge(xs, A, invn, sig, flat, thr, acnt, abuf, P->cap, N, L, p, keep, margin, best_exact, hc,
+                              hS, hn, hbound, hsig, best, fail, &cnt[CNT_NFAIL], &cnt[CNT_APPENDS], st);
+          if (e1 == hipSuccess) e1 = read_counters();
+          if (e1 == hipSuccess) listed = (int64_t)hcnt[CNT_NFAIL];
+          return e1;
+        };
+
+        int64_t nvalid = 0, nswept_fail = 0, nrecomp = 0;
         bool full = true, rebuild = false;
         if (L == Ls.l_min) {
           rebuild = heaps_on;
@@ -377,14 +512,15 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
           VCHECK(launch_sweep(xs, A, invn, sig, flat, N, L, e, p, base, hc, hS, hn, hbound, hsig, best, fail,
                               &cnt[CNT_NFAIL], &cnt[CNT_VALID], st));
           VCHECK(read_counters());
-          nfail = nswept_fail = (int64_t)hcnt[CNT_NFAIL];
+          nswept_fail = (int64_t)hcnt[CNT_NFAIL];
           nvalid = (int64_t)hcnt[CNT_VALID];
           // row recompute of the failing windows vs one full pass (cost model in FMA-equivalents)
           const double cells = 0.5 * (double)N * (double)N;
-          const bool cheap = (double)nfail * (double)N * (double)L <= rec_factor * cells;
+          const bool cheap = (double)nswept_fail * (double)N * (double)L <= rec_factor * cells;
           if (P->cfg.path == VALMOD_PATH_RECOMPUTE || cheap) {
             full = false;
-          } else if (probe_next && (double)nfail > 0.25 * (double)N) {
+            listed = nswept_fail;
+          } else if (probe_next && (double)nswept_fail > 0.25 * (double)N) {
             heaps_on = false;  // the bound fails right after a rebuild: partial profiles do not pay here
           } else {
             rebuild = true;
@@ -392,75 +528,41 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
           probe_next = false;
         }
         if (full) {
-          PassLaunch pl{};
-          pl.xs = xs;
-          pl.mu = mu;
-          pl.df = df;
-          pl.dg = dg;
-          pl.sw32 = sw32;
-          pl.invn = invn;
-          pl.thr = thr;
-          pl.thr32 = thr32;
-          pl.best = best;
-          pl.anc = anc;
-          pl.A = A;
-          pl.anc_stride = G.stride;
-          pl.N = N;
-          pl.e = e;
-          pl.H = G.H;
-          pl.dstart = G.dstart;
-          pl.L = L;
-          pl.K = G.K;
-          pl.events = &cnt[CNT_EV_STEPS];
-          pl.cnt = acnt;
-          pl.buf = abuf;
-          pl.cap = P->cap;
           const int32_t* src = prev;
-          if (!rebuild || L == Ls.l_min) {
-            // matrix-profile mode: running best keys seeded from the previous length
+          if (L == Ls.l_min || (!fp32 && !rebuild)) {
+            // exact FP64 matrix-profile pass: running best keys seeded from the previous length
             VCHECK(launch_seed_mp(xs, mu, invn, flat, prev, N, L, e, best, thr, thr32, st));
-            pl.append = false;
-            VCHECK(hipEventRecord(P->ev[evi], st));
-            VCHECK(launch_pass(pl, st));
-            VCHECK(hipEventRecord(P->ev[evi + 1], st));
-            evi += 2;
-            P->pass_launches += 1;
-            P->pass_cells += pass_grid(N, e, G.dstart, G.K, G.H).cells;
+            PassLaunch q = pl;
+            q.append = false;
+            if (fp32) {
+              VCHECK(launch_pass(q, st));
+              ++passes;
+            } else {
+              VCHECK(timed_pass(q));
+            }
             if (rebuild) {  // first length: the exact neighbours seed the collecting pass
               VCHECK(launch_keys_to_idx(best, N, pi, st));
               src = pi;
             }
           }
           if (rebuild) {
-            // collecting pass: every candidate above a per-owner threshold, then an
-            // exact merge into the partial profiles at base L (Alg. ComputeMatrixProfile)
-            VCHECK(hipMemsetAsync(&cnt[CNT_NFAIL], 0, 8, st));
-            const int best_exact = L == Ls.l_min ? 1 : 0;  // the matrix-profile pass just ran
-            VCHECK(launch_seed_append(xs, A, invn, flat, src, N, L, e, p, D, margin, best_exact, thr, acnt, fail,
-                                      &cnt[CNT_NFAIL], st));
-            pl.append = true;
-            VCHECK(hipEventRecord(P->ev[evi], st));
-            VCHECK(launch_pass(pl, st));
-            VCHECK(hipEventRecord(P->ev[evi + 1], st));
-            evi += 2;
-            P->pass_launches += 1;
-            P->pass_cells += pass_grid(N, e, G.dstart, G.K, G.H).cells;
-            VCHECK(launch_merge(xs, A, invn, sig, flat, thr, acnt, abuf, P->cap, N, L, p, margin, best_exact, hc, hS,
-                                hn, hbound, hsig, best, fail, &cnt[CNT_NFAIL], &cnt[CNT_APPENDS], st));
-            VCHECK(read_counters());
-            nfail = (int64_t)hcnt[CNT_NFAIL];
+            // new partial profiles at base L (Alg. ComputeMatrixProfile)
+            VCHECK(collect(src, p, p, L == Ls.l_min ? 1 : 0));
             base = L;
             probe_next = true;
+          } else if (fp32 && L > Ls.l_min) {
+            // exact neighbours from an FP32 collecting pass seeded by the previous length
+            VCHECK(collect(src, 1, 0, 0));
           }
         }
-        if (nfail > 0 && (!full || rebuild)) {
-          VCHECK(launch_recompute(xs, A, invn, flat, fail, nfail, N, L, e, best, st));
-          nrecomp = nfail;
+        if (listed > 0) {
+          VCHECK(launch_recompute(xs, A, invn, flat, fail, listed, N, L, e, best, st));
+          nrecomp = listed;
         }
         VCHECK(launch_finalize(xs, mu, sig, best, N, L, pd, pi, vnorm, vdist, vlen, vidx, st));
         VCHECK(launch_fill_tail(N, N0, pd, pi, st));
         VCHECK(launch_record_stats(cnt, o->stats ? o->stats + Ls.stats + t * VALMOD_NSTATS : nullptr, full ? 1 : 0,
-                                   nvalid, nswept_fail, nrecomp, st));
+                                   nvalid, nswept_fail, nrecomp, passes, st));
       }
       VCHECK(launch_rankings(o->prof_dist + Ls.prof, o->prof_idx + Ls.prof, N0, n, Ls.l_min, (int)Ls.nlen,
                              excl_den, km, kd, o->motif_ab + 2 * Ls.motif, o->motif_d + Ls.motif,

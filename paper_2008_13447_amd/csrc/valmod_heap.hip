@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kWave) void k_merge(
     const double* __restrict__ xs, const double* __restrict__ A, const double* __restrict__ invn,
     const double* __restrict__ sig, const uint8_t* __restrict__ flat, const double* __restrict__ thr,
     const uint32_t* __restrict__ cnt, const int32_t* __restrict__ buf, int64_t cap, int64_t N, int L, int p,
-    double margin, int best_exact, int32_t* __restrict__ hc, double* __restrict__ hS, int32_t* __restrict__ hn,
+    int keep, double margin, int best_exact, int32_t* __restrict__ hc, double* __restrict__ hS, int32_t* __restrict__ hn,
     double* __restrict__ hbound, double* __restrict__ hsig, uint64_t* __restrict__ best, int32_t* __restrict__ fail,
     unsigned long long* __restrict__ nfail, unsigned long long* __restrict__ nappend) {
   // best_exact: `best` already holds every owner's exact neighbour (a
@@ -176,16 +176,16 @@ __global__ __launch_bounds__(kWave) void k_merge(
     const uint64_t k = skey[r];
     int64_t rank = 0;
     for (int64_t s2 = 0; s2 < m; ++s2) rank += skey[s2] < k ? 1 : 0;
-    if (rank < p) {
+    if (rank < keep) {
       hc[o * p + rank] = (int32_t)key_cand(k);
       hS[o * p + rank] = ssum[r];
     }
     if (rank == 0) best[o] = k;
-    if (rank == p && srho[r] > sbound) sbound = srho[r];  // the best collected candidate not kept
+    if (rank == keep && srho[r] > sbound) sbound = srho[r];  // the best collected candidate not kept
   }
   __syncthreads();
   if (t == 0) {
-    hn[o] = (int32_t)(m < p ? m : p);
+    hn[o] = (int32_t)(m < keep ? m : keep);
     hbound[o] = sbound;
     hsig[o] = sig[o];
   }
@@ -288,12 +288,12 @@ hipError_t launch_seed_append(const double* xs, const double* A, const double* i
 
 hipError_t launch_merge(const double* xs, const double* A, const double* invn, const double* sig, const uint8_t* flat,
                         const double* thr, const uint32_t* cnt, const int32_t* buf, int64_t cap, int64_t N, int L,
-                        int p, double margin, int best_exact, int32_t* hc, double* hS, int32_t* hn, double* hbound,
-                        double* hsig, uint64_t* best, int32_t* fail, unsigned long long* nfail,
+                        int p, int keep, double margin, int best_exact, int32_t* hc, double* hS, int32_t* hn,
+                        double* hbound, double* hsig, uint64_t* best, int32_t* fail, unsigned long long* nfail,
                         unsigned long long* nappend, hipStream_t st) {
   if (N <= 0) return hipSuccess;
-  k_merge<<<(unsigned)N, kWave, 0, st>>>(xs, A, invn, sig, flat, thr, cnt, buf, cap, N, L, p, margin, best_exact, hc,
-                                        hS, hn, hbound, hsig, best, fail, nfail, nappend);
+  k_merge<<<(unsigned)N, kWave, 0, st>>>(xs, A, invn, sig, flat, thr, cnt, buf, cap, N, L, p, keep, margin,
+                                        best_exact, hc, hS, hn, hbound, hsig, best, fail, nfail, nappend);
   return hipGetLastError();
 }
 

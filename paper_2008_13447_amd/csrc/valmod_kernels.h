@@ -11,8 +11,15 @@ constexpr int kPassKMax = 8;  // largest supported diagonals-per-lane of the pas
 struct PassLaunch {
   const double *xs, *mu, *df, *dg, *invn;
   const float* sw32;
+  const float *df32, *dg32, *inv32;  // FP32 recurrence inputs
   double* thr;
   float* thr32;
+  const int32_t* items;  // optional work-item list (FP64 re-run of items the FP32 bound rejects)
+  int64_t nitems;        // grid size for the list (upper bound of the count)
+  const unsigned long long* nitems_dev;  // device count of listed items
+  const float* delta;    // FP32: rounding bound per work item
+  float delta_max;
+  bool fp32;
   uint64_t* best;
   uint32_t* cnt;
   int32_t* buf;
@@ -23,7 +30,7 @@ struct PassLaunch {
   unsigned long long* events;
   int64_t N, e, H, dstart;
   int L;
-  int K;  // diagonals per lane: 4 or 8
+  int K;  // diagonals per lane: 8 (FP64 also 4)
   bool append;
 };
 
@@ -47,13 +54,21 @@ hipError_t launch_seed_mp(const double* xs, const double* mu, const double* invn
                           const int32_t* prev_idx, int64_t N, int L, int64_t e, uint64_t* best,
                           double* thr, float* thr32, hipStream_t st);
 hipError_t launch_pass(const PassLaunch& p, hipStream_t st);
+hipError_t launch_fp32_prep(const double* sig, const double* invn, const double* df, const double* dg, int64_t N,
+                            int L, float* df32, float* dg32, float* inv32, float* bsw_max, float* bsw_min,
+                            float* bdf_max, float* bdg_max, hipStream_t st);
+hipError_t launch_fp32_items(const float* bsw_max, const float* bsw_min, const float* bdf_max, const float* bdg_max,
+                             int64_t N, int64_t e, int64_t dstart, int K, int64_t H, float delta_max, float* delta,
+                             int32_t* hard, unsigned long long* nhard, hipStream_t st);
+hipError_t launch_thr_to_f32(const double* thr, int64_t n, float* thr32, hipStream_t st);
 hipError_t launch_finalize(const double* xs, const double* mu, const double* sig, const uint64_t* best,
                            int64_t N, int L, double* prof_dist, int32_t* prof_idx, double* valmp_norm,
                            double* valmp_dist, int32_t* valmp_len, int32_t* valmp_idx, hipStream_t st);
 // counters layout: [0] error flag, [1] flat windows, [2] pass slow-path steps,
-// [3] pass owner hits, [4] appended candidates
+// [3] pass owner hits, [4] appended candidates, [7] FP64 fallback work items;
+// the per-length ones are reset after recording
 hipError_t launch_record_stats(unsigned long long* cnt, int64_t* row, int full_pass, int64_t valid,
-                               int64_t failed, int64_t recomputed, hipStream_t st);
+                               int64_t failed, int64_t recomputed, int64_t passes, hipStream_t st);
 hipError_t launch_fill_tail(int64_t from, int64_t to, double* prof_dist, int32_t* prof_idx, hipStream_t st);
 hipError_t launch_valmp_init(int64_t N0, double* norm, double* dist, int32_t* len, int32_t* idx,
                              hipStream_t st);
@@ -73,8 +88,8 @@ hipError_t launch_seed_append(const double* xs, const double* A, const double* i
                               hipStream_t st);
 hipError_t launch_merge(const double* xs, const double* A, const double* invn, const double* sig, const uint8_t* flat,
                         const double* thr, const uint32_t* cnt, const int32_t* buf, int64_t cap, int64_t N, int L,
-                        int p, double margin, int best_exact, int32_t* hc, double* hS, int32_t* hn, double* hbound,
-                        double* hsig, uint64_t* best, int32_t* fail, unsigned long long* nfail,
+                        int p, int keep, double margin, int best_exact, int32_t* hc, double* hS, int32_t* hn,
+                        double* hbound, double* hsig, uint64_t* best, int32_t* fail, unsigned long long* nfail,
                         unsigned long long* nappend, hipStream_t st);
 hipError_t launch_sweep(const double* xs, const double* A, const double* invn, const double* sig, const uint8_t* flat,
                         int64_t N, int L, int64_t e, int p, int base, const int32_t* hc, double* hS, const int32_t* hn,

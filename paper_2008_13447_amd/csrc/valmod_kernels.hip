@@ -201,7 +201,7 @@ __global__ void k_finalize(const double* __restrict__ xs, const double* __restri
 // Per-length diagnostic counters: copies the running device counters into the
 // stats row of length t and clears them.
 __global__ void k_record_stats(unsigned long long* __restrict__ cnt, int64_t* __restrict__ row, int full_pass,
-                               int64_t valid, int64_t failed, int64_t recomputed) {
+                               int64_t valid, int64_t failed, int64_t recomputed, int64_t passes) {
   if (threadIdx.x != 0) return;
   if (row) {
     row[0] = valid;
@@ -212,8 +212,10 @@ __global__ void k_record_stats(unsigned long long* __restrict__ cnt, int64_t* __
     row[5] = (int64_t)cnt[4];
     row[6] = (int64_t)cnt[2];
     row[7] = (int64_t)cnt[3];
+    row[8] = (int64_t)cnt[7];
+    row[9] = passes;
   }
-  cnt[1] = cnt[2] = cnt[3] = cnt[4] = 0;
+  cnt[1] = cnt[2] = cnt[3] = cnt[4] = cnt[7] = 0;
 }
 
 __global__ void k_fill_tail(int64_t from, int64_t to, double* __restrict__ prof_dist,
@@ -516,8 +518,8 @@ hipError_t launch_finalize(const double* xs, const double* mu, const double* sig
 }
 
 hipError_t launch_record_stats(unsigned long long* cnt, int64_t* row, int full_pass, int64_t valid,
-                               int64_t failed, int64_t recomputed, hipStream_t st) {
-  k_record_stats<<<1, 64, 0, st>>>(cnt, row, full_pass, valid, failed, recomputed);
+                               int64_t failed, int64_t recomputed, int64_t passes, hipStream_t st) {
+  k_record_stats<<<1, 64, 0, st>>>(cnt, row, full_pass, valid, failed, recomputed, passes);
   return hipGetLastError();
 }
 

@@ -74,13 +74,18 @@ __global__ void k_anchor_grow(const double* __restrict__ xs, int64_t n, int L, i
 enum { MODE_MP = 0, MODE_APPEND = 1 };
 
 struct PassArgs {
-  double* thr;         // per-owner threshold (correlation units)
+  double* thr;         // per-owner threshold (correlation units); MODE_MP updates it
   uint64_t* best;      // MODE_MP: packed best key per owner
   uint32_t* cnt;       // MODE_APPEND: candidates appended per owner
   int32_t* buf;        // MODE_APPEND: owner-major candidate lists
   int64_t cap;         // MODE_APPEND: list capacity per owner
-  unsigned long long* events;  // [0] wave-steps that took the slow path, [1] owner hits
+  unsigned long long* events;  // [0] wave-steps that took the slow path, [1] queue entries
+  const int32_t* items;        // optional list of work items (seg * bands + band); null: the whole grid
+  const unsigned long long* nitems;  // number of listed items (device count; the grid may be larger)
+  const float* delta;          // FP32 recurrence: bound of |rho32 - rho| per work item (null: none)
+  float delta_max;             // FP32 recurrence: items with a larger bound are left to the FP64 kernel
   int64_t anc_stride;  // anchor-table row length (diagonals per segment row)
+  int64_t bands;       // bands of the grid (decodes item ids)
   int64_t N, e, H, dstart;
   int L;
 };
@@ -90,7 +95,7 @@ __device__ __forceinline__ T ldo(const T* base, uint32_t off) {
   return *(const T*)((const char*)base + off);
 }
 
-// Wide per-lane loads of `n` consecutive doubles (lanes read adjacent ranges,
+// Wide per-lane loads of `n` consecutive elements (lanes read adjacent ranges,
 // so a wavefront reads one contiguous block).
 template <int n>
 __device__ __forceinline__ void load_run(const double* p, double* dst) {
@@ -99,6 +104,18 @@ __device__ __forceinline__ void load_run(const double* p, double* dst) {
     const double2 v = *(const double2*)(p + u);
     dst[u] = v.x;
     dst[u + 1] = v.y;
+  }
+}
+template <int n>
+__device__ __forceinline__ void load_run(const float* p, float* dst) {
+  static_assert(n % 4 == 0, "float runs are loaded 4 at a time");
+#pragma unroll
+  for (int u = 0; u < n; u += 4) {
+    const float4 v = *(const float4*)(p + u);
+    dst[u] = v.x;
+    dst[u + 1] = v.y;
+    dst[u + 2] = v.z;
+    dst[u + 3] = v.w;
   }
 }
 
@@ -111,45 +128,96 @@ constexpr int kQueue = 1024;
 
 // min of two thresholds (never NaN) without the IEEE quieting of the operands
 // that fmin() implies.
-__device__ __forceinline__ double vmin_f64(double a, double b) {
+__device__ __forceinline__ double vmin(double a, double b) {
   double r;
   asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
   return r;
 }
+__device__ __forceinline__ float vmin(float a, float b) {
+  float r;
+  asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
 
-template <int K, int MODE>
-__global__ __launch_bounds__(kWave) void k_pass(const double* __restrict__ g_df, const double* __restrict__ g_dg,
-                                                const double* __restrict__ g_invn, const double* __restrict__ g_thr,
-                                                const double* __restrict__ g_anc, const double* __restrict__ g_A,
-                                                PassArgs a) {
-  // g_thr aliases a.thr: threshold reads through it may return values older than
-  // this kernel's own updates, which only makes the filter looser (never unsound).
-  static_assert(K % 4 == 0, "K must be a multiple of 4");
+// FP64 anchors computed directly: S[q] = sum_{k<L} (x_{i0+k} - x_{i0}) (x_{j+k} - x_j)
+// for the K diagonals j = i0 + dl + q. The lane's K consecutive windows share a
+// register window of K values that slides by one element per k.
+template <int K>
+__device__ __forceinline__ void direct_anchors(const double* __restrict__ xs, int64_t i0, int64_t dl, int L,
+                                               double* S) {
+  const double xi = xs[i0];
+  const double* xc = xs + i0 + dl;
+  double base[K], w[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    base[q] = xc[q];
+    w[q] = base[q];
+    S[q] = 0.0;
+  }
+  // at step k, slot (q + k) mod K holds x_{j0 + q + k}
+  for (int kb = 0; kb < L; kb += K) {
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      const int k = kb + u;
+      if (k >= L) break;
+      const double r = xs[i0 + k] - xi;
+#pragma unroll
+      for (int q = 0; q < K; ++q) S[q] = fma(r, w[(q + u) % K] - base[q], S[q]);
+      w[u] = xc[K + k];  // the slot of x_{j0 + k} takes x_{j0 + K + k}
+    }
+  }
+}
+
+template <typename T, int K, int MODE>
+__global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, const T* __restrict__ g_dg,
+                                                const T* __restrict__ g_invn, const T* __restrict__ g_thr,
+                                                const double* __restrict__ g_xs, const double* __restrict__ g_anc,
+                                                const double* __restrict__ g_A, PassArgs a) {
+  // g_thr aliases the threshold array this kernel updates in MODE_MP: reads
+  // through it may return older values, which only loosens the filter.
+  static_assert(K % 8 == 0 || (sizeof(T) == 8 && K % 4 == 0), "run loads need K multiple of 8 (4 for double)");
   constexpr int64_t BW = (int64_t)kWave * K;  // diagonals per band
   constexpr int HK = K / 2;
   __shared__ int32_t q_owner[kQueue];
   __shared__ uint64_t q_val[kQueue];  // MODE_MP: packed key; MODE_APPEND: candidate index
   const int t = threadIdx.x;
   const int64_t N = a.N;
-  const int64_t d0 = a.dstart + (int64_t)blockIdx.y * BW;
+  int64_t seg = blockIdx.x, band = blockIdx.y;
+  if (a.items) {
+    if ((unsigned long long)blockIdx.x >= *a.nitems) return;
+    const int64_t id = a.items[blockIdx.x];
+    seg = id / a.bands;
+    band = id % a.bands;
+  }
+  const int64_t d0 = a.dstart + band * BW;
   if (d0 > N - 1) return;
-  const int64_t i0 = (int64_t)blockIdx.x * a.H;
+  const int64_t i0 = seg * a.H;
   const int64_t rowEnd = N - d0;
   if (i0 >= rowEnd) return;
+  // FP32 recurrence: rigorous bound of the rounding of rho over this item
+  T delta = (T)0;
+  if (a.delta) {
+    const float dl_ = a.delta[seg * a.bands + band];
+    if (!(dl_ <= a.delta_max)) return;  // left to the FP64 kernel
+    delta = (T)dl_;
+  }
   const int rows = (int)((i0 + a.H < rowEnd ? i0 + a.H : rowEnd) - i0);
   const int64_t dl = d0 + (int64_t)K * t;
 
-  // co-moments at row i0 from the FP64 anchor table: C = S - A_i A_j / L
-  double C[K];
+  // co-moments at row i0 from FP64 anchors: C = S - A_i A_j / L
+  T C[K];
   {
     double S[K], Aj[K];
-    load_run<K>(g_anc + (int64_t)blockIdx.x * a.anc_stride + (dl - a.dstart), S);
+    if (g_anc)
+      load_run<K>(g_anc + seg * a.anc_stride + (dl - a.dstart), S);
+    else
+      direct_anchors<K>(g_xs, i0, dl, a.L, S);
     load_run<K>(g_A + i0 + dl, Aj);
     const double Ai = g_A[i0] / (double)a.L;
 #pragma unroll
     for (int q = 0; q < K; ++q) {
       const int64_t j = i0 + dl + q;
-      C[q] = (dl + q > a.e && j < N) ? S[q] - Ai * Aj[q] : -INFINITY;  // trivial or past the end
+      C[q] = (dl + q > a.e && j < N) ? (T)(S[q] - Ai * Aj[q]) : (T)-INFINITY;  // trivial or past the end
     }
   }
 
@@ -158,8 +226,8 @@ __global__ __launch_bounds__(kWave) void k_pass(const double* __restrict__ g_df,
   // start in set P, slot s moves to set Q (holding the column that enters) at
   // step s, and the freed entries of P receive the next block's entering
   // columns, a half block at a time. No register copies are needed.
-  double Xdf[K], Xdg[K], Xinv[K], Xthr[K];
-  double Ydf[K], Ydg[K], Yinv[K], Ythr[K];
+  T Xdf[K], Xdg[K], Xinv[K], Xthr[K];
+  T Ydf[K], Ydg[K], Yinv[K], Ythr[K];
   {
     const int64_t c0 = i0 + dl;
     load_run<K>(g_df + c0, Xdf);
@@ -206,15 +274,14 @@ __global__ __launch_bounds__(kWave) void k_pass(const double* __restrict__ g_df,
   };
 
   // one block of K rows starting at row ib; slots start in P and move to Q
-  auto block = [&](int64_t ib, double* Pdf, double* Pdg, double* Pinv, double* Pthr, double* Qdf, double* Qdg,
-                   double* Qinv, double* Qthr) {
-    double rdf[K], rdg[K], rinv[K], rthr[K];
+  auto block = [&](int64_t ib, T* Pdf, T* Pdg, T* Pinv, T* Pthr, T* Qdf, T* Qdg, T* Qinv, T* Qthr) {
+    T rdf[K], rdg[K], rinv[K], rthr[K];
 #pragma unroll
     for (int u = 0; u < K; ++u) {
       rdf[u] = g_df[ib + u];
       rdg[u] = g_dg[ib + u];
       rinv[u] = g_invn[ib + u];
-      rthr[u] = g_thr[ib + u];
+      rthr[u] = g_thr[ib + u] - delta;
     }
     const int64_t cn = ib + dl + 2 * K;  // first column entering during the next block
     // Every block runs all K steps: rows past the segment or the series only meet
@@ -223,14 +290,14 @@ __global__ __launch_bounds__(kWave) void k_pass(const double* __restrict__ g_df,
 #pragma unroll
     for (int u = 0; u < K; ++u) {
       const int64_t i = ib + u;
-      // exact correlation of every cell and the test against both owners' thresholds
+      // correlation of every cell and the test against both owners' thresholds
       bool pass = false;
 #pragma unroll
       for (int q = 0; q < K; ++q) {
         const int s = (q + u) % K;
-        const double inv = s < u ? Qinv[s] : Pinv[s];
-        const double th = s < u ? Qthr[s] : Pthr[s];
-        pass |= (C[q] * inv) * rinv[u] >= vmin_f64(th, rthr[u]);
+        const T inv = s < u ? Qinv[s] : Pinv[s];
+        const T th = (s < u ? Qthr[s] : Pthr[s]) - delta;
+        pass |= (C[q] * inv) * rinv[u] >= vmin(th, rthr[u]);
       }
       if (__any(pass)) {
         ++ev_steps;
@@ -240,20 +307,20 @@ __global__ __launch_bounds__(kWave) void k_pass(const double* __restrict__ g_df,
         for (int q = 0; q < K; ++q) {
           const int s = (q + u) % K;
           const int64_t j = i + dl + q;
-          const double inv = s < u ? Qinv[s] : Pinv[s];
-          double& th = s < u ? Qthr[s] : Pthr[s];
-          const double rho = (C[q] * inv) * rinv[u];
-          const bool ok = j < N && rinv[u] > 0.0 && inv > 0.0;
-          const bool col = ok && rho >= th;
+          const T inv = s < u ? Qinv[s] : Pinv[s];
+          T& th = s < u ? Qthr[s] : Pthr[s];
+          const T rho = (C[q] * inv) * rinv[u];
+          const bool ok = j < N && rinv[u] > (T)0 && inv > (T)0;
+          const bool col = ok && rho >= th - delta;
           if (MODE == MODE_MP) {
-            const uint64_t key = col ? make_key(rho, i) : kEmptyKey;
+            const uint64_t key = col ? make_key((double)rho, i) : kEmptyKey;
             push(col, (int32_t)j, key);
             if (col) {
-              const double nt = key_threshold(key);
+              const T nt = (T)key_threshold(key);
               th = nt > th ? nt : th;
             }
             if (ok && rho >= rthr[u]) {
-              const uint64_t k2 = make_key(rho, j);
+              const uint64_t k2 = make_key((double)rho, j);
               rowkey = k2 < rowkey ? k2 : rowkey;
             }
           } else {
@@ -270,8 +337,8 @@ __global__ __launch_bounds__(kWave) void k_pass(const double* __restrict__ g_df,
 #pragma unroll
       for (int q = 0; q < K; ++q) {
         const int s = (q + u) % K;
-        const double cdf = s < u ? Qdf[s] : Pdf[s];
-        const double cdg = s < u ? Qdg[s] : Pdg[s];
+        const T cdf = s < u ? Qdf[s] : Pdf[s];
+        const T cdg = s < u ? Qdg[s] : Pdg[s];
         C[q] = fma(rdf[u], cdg, C[q]);
         C[q] = fma(cdf, rdg[u], C[q]);
       }
@@ -299,6 +366,109 @@ __global__ __launch_bounds__(kWave) void k_pass(const double* __restrict__ g_df,
   if (a.events && t == 0 && ev_steps) atomicAdd(&a.events[0], ev_steps);
 }
 
+// --------------------------------------------------------------------------
+// Rounding bound of the FP32 recurrence per work item. With eps = 2^-24, a
+// segment of R rows, Phi = (max sw / min sw)_rows (max sw / min sw)_cols and
+// Psi = (max|df|_rows max|dg|_cols + max|dg|_rows max|df|_cols) / (min sw_rows min sw_cols)
+// over the item's windows (sw = sigma sqrt L, flat windows excluded), the
+// first-order error of rho = C / (sw_i sw_j) after r <= R steps is at most
+//   eps [(2R + 1) Phi + 4R Psi + 4]
+// (two rounded FMAs per step on |C| <= sw_i sw_j, rounded FP32 inputs, the
+// anchor conversion and the normalisation). The bound is doubled for the
+// second-order terms, and one FP32 ulp at magnitude 2..4 is added for the
+// rounding of the test's own threshold difference.
+__global__ void k_delta(const float* __restrict__ bsw_max, const float* __restrict__ bsw_min,
+                        const float* __restrict__ bdf_max, const float* __restrict__ bdg_max, int64_t nblk,
+                        int64_t segs, int64_t bands, int64_t H, int64_t dstart, int64_t BW, int64_t N,
+                        float* __restrict__ delta) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= segs * bands) return;
+  const int64_t seg = id / bands, band = id % bands;
+  const int64_t i0 = seg * H, d0 = dstart + band * BW;
+  if (d0 > N - 1 || i0 >= N - d0) {
+    delta[id] = 0.0f;
+    return;
+  }
+  auto range = [&](int64_t lo, int64_t hi, float& smax, float& smin, float& fmax_, float& gmax) {
+    smax = 0.0f;
+    smin = INFINITY;
+    fmax_ = 0.0f;
+    gmax = 0.0f;
+    const int64_t b0 = lo / 64, b1 = (hi - 1) / 64 < nblk - 1 ? (hi - 1) / 64 : nblk - 1;
+    for (int64_t b = b0; b <= b1; ++b) {
+      smax = fmaxf(smax, bsw_max[b]);
+      smin = fminf(smin, bsw_min[b]);
+      fmax_ = fmaxf(fmax_, bdf_max[b]);
+      gmax = fmaxf(gmax, bdg_max[b]);
+    }
+  };
+  float rsx, rsn, rfx, rgx, csx, csn, cfx, cgx;
+  range(i0, i0 + H + 1, rsx, rsn, rfx, rgx);
+  range(i0 + d0, i0 + d0 + H + BW + 1, csx, csn, cfx, cgx);
+  if (!(rsn < INFINITY) || !(csn < INFINITY)) {
+    delta[id] = 0.0f;  // no non-flat window on one side: nothing can pass
+    return;
+  }
+  const double R = (double)H;
+  const double phi = ((double)rsx / rsn) * ((double)csx / csn);
+  const double psi = ((double)rfx * cgx + (double)rgx * cfx) / ((double)rsn * csn);
+  const double eps = 5.9604644775390625e-08;  // 2^-24
+  // + 2^-22: the rounding of the FP32 difference threshold - delta (|.| < 4)
+  const double d = 2.0 * eps * ((2.0 * R + 1.0) * phi + 4.0 * R * psi + 4.0) + 2.384185791015625e-07;
+  delta[id] = d < 1.0 ? (float)d * 1.0000002f : 1.0f;
+}
+
+// Per-block (64 windows) extrema feeding k_delta.
+__global__ void k_block_extrema(const double* __restrict__ sig, const double* __restrict__ invn,
+                                const double* __restrict__ df, const double* __restrict__ dg, int64_t N, int L,
+                                float* __restrict__ bsw_max, float* __restrict__ bsw_min,
+                                float* __restrict__ bdf_max, float* __restrict__ bdg_max, int64_t nblk) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblk) return;
+  double smax = 0.0, smin = INFINITY, fmx = 0.0, gmx = 0.0;
+  const double sl = sqrt((double)L);
+  for (int64_t i = b * 64; i < b * 64 + 64 && i < N; ++i) {
+    if (invn[i] > 0.0) {
+      const double w = sig[i] * sl;
+      smax = w > smax ? w : smax;
+      smin = w < smin ? w : smin;
+    }
+    fmx = fmax(fmx, fabs(df[i]));
+    gmx = fmax(gmx, fabs(dg[i]));
+  }
+  // rounded outward so that the item bound stays an upper bound
+  bsw_max[b] = smax > 0.0 ? __double2float_ru(smax) : 0.0f;
+  bsw_min[b] = smin < INFINITY ? __double2float_rd(smin) : INFINITY;
+  bdf_max[b] = __double2float_ru(fmx);
+  bdg_max[b] = __double2float_ru(gmx);
+}
+
+// FP32 copies of the recurrence inputs (nearest rounding; their error is part
+// of the item bound) and of the thresholds (rounded down).
+__global__ void k_to_f32(const double* __restrict__ df, const double* __restrict__ dg,
+                         const double* __restrict__ invn, int64_t n, float* __restrict__ df32,
+                         float* __restrict__ dg32, float* __restrict__ inv32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  df32[i] = (float)df[i];
+  dg32[i] = (float)dg[i];
+  inv32[i] = (float)invn[i];
+}
+
+__global__ void k_thr_to_f32(const double* __restrict__ thr, int64_t n, float* __restrict__ thr32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  thr32[i] = __double2float_rd(thr[i]);
+}
+
+// Items whose FP32 bound exceeds the limit, for the FP64 kernel.
+__global__ void k_hard_items(const float* __restrict__ delta, int64_t nitems, float delta_max,
+                             int32_t* __restrict__ items, unsigned long long* __restrict__ count) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nitems) return;
+  if (delta[id] > delta_max) items[atomicAdd(count, 1ull)] = (int32_t)id;
+}
+
 PassGrid pass_grid(int64_t N, int64_t e, int64_t dstart, int K, int64_t H) {
   PassGrid g;
   const int64_t ndiag = N - 1 - e;    // non-trivial diagonals e+1 .. N-1
@@ -321,7 +491,7 @@ hipError_t launch_anchor(const double* xs, int64_t n, int L, bool init, int64_t 
   return hipGetLastError();
 }
 
-template <int K>
+template <typename T, int K>
 static hipError_t launch_pass_k(const PassLaunch& p, hipStream_t st) {
   const PassGrid g = pass_grid(p.N, p.e, p.dstart, K, p.H);
   if (g.bands == 0) return hipSuccess;
@@ -332,24 +502,67 @@ static hipError_t launch_pass_k(const PassLaunch& p, hipStream_t st) {
   a.cnt = p.cnt;
   a.buf = p.buf;
   a.cap = p.cap;
+  a.items = p.items;
+  a.nitems = p.nitems_dev;
+  a.delta = p.delta;
+  a.delta_max = p.delta_max;
   a.N = p.N;
   a.e = p.e;
   a.H = p.H;
   a.dstart = p.dstart;
   a.anc_stride = p.anc_stride;
+  a.bands = g.bands;
   a.L = p.L;
-  dim3 grid((unsigned)g.segs, (unsigned)g.bands);
+  if (p.items && (p.nitems <= 0 || !p.nitems_dev)) return p.nitems < 0 ? hipErrorInvalidValue : hipSuccess;
+  dim3 grid = p.items ? dim3((unsigned)p.nitems, 1) : dim3((unsigned)g.segs, (unsigned)g.bands);
+  const T* df = (const T*)(sizeof(T) == 8 ? (const void*)p.df : (const void*)p.df32);
+  const T* dg = (const T*)(sizeof(T) == 8 ? (const void*)p.dg : (const void*)p.dg32);
+  const T* inv = (const T*)(sizeof(T) == 8 ? (const void*)p.invn : (const void*)p.inv32);
+  const T* thr = (const T*)(sizeof(T) == 8 ? (const void*)p.thr : (const void*)p.thr32);
   if (p.append)
-    k_pass<K, MODE_APPEND><<<grid, kWave, 0, st>>>(p.df, p.dg, p.invn, p.thr, p.anc, p.A, a);
+    k_pass<T, K, MODE_APPEND><<<grid, kWave, 0, st>>>(df, dg, inv, thr, p.xs, p.anc, p.A, a);
   else
-    k_pass<K, MODE_MP><<<grid, kWave, 0, st>>>(p.df, p.dg, p.invn, p.thr, p.anc, p.A, a);
+    k_pass<T, K, MODE_MP><<<grid, kWave, 0, st>>>(df, dg, inv, thr, p.xs, p.anc, p.A, a);
   return hipGetLastError();
 }
 
 hipError_t launch_pass(const PassLaunch& p, hipStream_t st) {
-  if (p.K == 8) return launch_pass_k<8>(p, st);
-  if (p.K == 4) return launch_pass_k<4>(p, st);
+  if (p.fp32) {
+    if (p.K == 8) return launch_pass_k<float, 8>(p, st);
+    return hipErrorInvalidValue;
+  }
+  if (p.K == 8) return launch_pass_k<double, 8>(p, st);
+  if (p.K == 4) return launch_pass_k<double, 4>(p, st);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_fp32_prep(const double* sig, const double* invn, const double* df, const double* dg, int64_t N,
+                            int L, float* df32, float* dg32, float* inv32, float* bsw_max, float* bsw_min,
+                            float* bdf_max, float* bdg_max, hipStream_t st) {
+  const int64_t n = N + kPad;
+  k_to_f32<<<blocks_for(n, 256), 256, 0, st>>>(df, dg, invn, n, df32, dg32, inv32);
+  const int64_t nblk = (N + 63) / 64;
+  k_block_extrema<<<blocks_for(nblk, 128), 128, 0, st>>>(sig, invn, df, dg, N, L, bsw_max, bsw_min, bdf_max,
+                                                         bdg_max, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_fp32_items(const float* bsw_max, const float* bsw_min, const float* bdf_max, const float* bdg_max,
+                             int64_t N, int64_t e, int64_t dstart, int K, int64_t H, float delta_max, float* delta,
+                             int32_t* hard, unsigned long long* nhard, hipStream_t st) {
+  const PassGrid g = pass_grid(N, e, dstart, K, H);
+  const int64_t nitems = g.segs * g.bands;
+  if (nitems == 0) return hipSuccess;
+  const int64_t nblk = (N + 63) / 64;
+  k_delta<<<blocks_for(nitems, 256), 256, 0, st>>>(bsw_max, bsw_min, bdf_max, bdg_max, nblk, g.segs, g.bands, H,
+                                                   dstart, (int64_t)kWave * K, N, delta);
+  k_hard_items<<<blocks_for(nitems, 256), 256, 0, st>>>(delta, nitems, delta_max, hard, nhard);
+  return hipGetLastError();
+}
+
+hipError_t launch_thr_to_f32(const double* thr, int64_t n, float* thr32, hipStream_t st) {
+  k_thr_to_f32<<<blocks_for(n, 256), 256, 0, st>>>(thr, n, thr32);
+  return hipGetLastError();
 }
 
 }  // namespace valmod

@@ -25,8 +25,9 @@ STATUS = {0: "VALMOD_OK", -1: "VALMOD_E_ARG", -2: "VALMOD_E_TOO_SHORT", -3: "VAL
 DTYPE = {"f32": 0, "f64": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 PATH = {"auto": 0, "full": 1, "recompute": 2}
-NSTATS = 8
-STAT_NAMES = ["valid", "failed", "recomputed", "full_pass", "flat", "appends", "pass_events", "pass_hits"]
+NSTATS = 10
+STAT_NAMES = ["valid", "failed", "recomputed", "full_pass", "flat", "appends", "pass_events", "pass_hits",
+              "fp64_items", "passes"]
 
 # (name, C type) of every function declared in include/valmod.h
 EXPORTS = ["valmod_plan", "valmod_workspace_bytes", "valmod_output_sizes", "valmod_series_layout",

@@ -64,6 +64,12 @@ def test_plan_validation(lib):
     cfg, keep = native.make_config([1000], [20], [30])
     cfg.dtype = 7
     assert native.valmod_plan_status(cfg) == -1
+    # FP32 refresh interval: 0 (default) or a multiple of 16 in [64, 8192]
+    assert _status(precision="fp32") == 0
+    assert _status(precision="fp32", refresh_R=64) == 0
+    assert _status(precision="fp32", refresh_R=8192) == 0
+    for bad in (-16, 48, 100, 8208):
+        assert _status(precision="fp32", refresh_R=bad) == -1, bad
 
 
 def test_sizes_and_layout(lib):

@@ -210,3 +210,85 @@ def test_partial_profiles_on_flat_segments(oracle_mod):
     g = run_gpu(x, 20, 34, p=10, k_motifs=3, k_discords=3, path="recompute")
     r = oracle_mod.valmod(x, 20, 34, k_motifs=3, k_discords=3)
     compare.check_full(x, 20, g, r, TOL64)
+
+
+# --------------------------------------------------------------------------
+# FP32 recurrence with FP64 refresh: the FP32 pass only selects candidates
+# (threshold widened by its per-item rounding bound) and every reported value
+# is re-evaluated in FP64, so the FP64 tolerance applies unchanged.
+
+@pytest.mark.parametrize("n,lo,hi,den,k,dtype,seed,R", [
+    (1000, 16, 24, 4, 3, np.float32, 0, 0),
+    (1531, 9, 12, 2, 5, np.float64, 1, 64),
+    (3001, 40, 44, 4, 4, np.float32, 2, 128),
+    (97, 8, 12, 4, 2, np.float64, 4, 0),
+])
+def test_fp32_refresh_parity(oracle_mod, n, lo, hi, den, k, dtype, seed, R):
+    from oracle import compare
+
+    x = gen.small_random_walk(n, 10 + seed, dtype)
+    _say(f"fp32 rw n={n} L={lo}..{hi} den={den} R={R}")
+    g = run_gpu(x, lo, hi, p=5, k_motifs=k, k_discords=k, excl_den=den, precision="fp32", refresh_R=R)
+    r = oracle_mod.valmod(x, lo, hi, excl_den=den, k_motifs=k, k_discords=k)
+    compare.check_full(x, lo, g, r, TOL64, excl_den=den)
+
+
+@pytest.mark.parametrize("path", ["full", "auto", "recompute"])
+def test_fp32_refresh_paths(oracle_mod, path):
+    from oracle import compare
+
+    x = gen.small_random_walk(2200, 70, np.float32)
+    lo, hi = 30, 42
+    _say(f"fp32 path={path}")
+    g = run_gpu(x, lo, hi, p=10, k_motifs=3, k_discords=3, path=path, precision="fp32")
+    r = oracle_mod.valmod(x, lo, hi, k_motifs=3, k_discords=3)
+    compare.check_full(x, lo, g, r, TOL64)
+
+
+def test_fp32_refresh_all_items_in_fp64(oracle_mod, monkeypatch):
+    """A zero bound limit sends every work item to the FP64 kernel through the
+    item list: same exact results, and the stats count the items."""
+    from oracle import compare
+
+    monkeypatch.setenv("VALMOD_FP32_DELTA_MAX_E6", "0")
+    x = gen.small_random_walk(1500, 71, np.float32)
+    _say("fp32 all items fp64")
+    g = run_gpu(x, 20, 26, p=5, k_motifs=3, k_discords=3, path="full", precision="fp32")
+    r = oracle_mod.valmod(x, 20, 26, k_motifs=3, k_discords=3)
+    compare.check_full(x, 20, g, r, TOL64)
+    assert (g["stats"][1:, 8] > 0).all(), g["stats"]
+
+
+def test_fp32_refresh_flats(oracle_mod):
+    from oracle import compare
+
+    x = gen.small_random_walk(2500, 72) + 1.0e4
+    x[300:700] = x[300]
+    x[1500:1560] = x[1500]
+    x = x.astype(np.float32)
+    _say("fp32 flats")
+    g = run_gpu(x, 24, 32, p=5, k_motifs=3, k_discords=3, precision="fp32", path="full")
+    r = oracle_mod.valmod(x, 24, 32, k_motifs=3, k_discords=3)
+    compare.check_full(x, 24, g, r, TOL64)
+
+
+def test_fp32_refresh_equals_fp64():
+    """Both precisions return identical outputs (bitwise for indices and
+    distances, which are FP64 in both)."""
+    x = gen.small_random_walk(6000, 73, np.float32)
+    a = run_gpu(x, 50, 60, p=10, k_motifs=4, k_discords=4, path="full")
+    b = run_gpu(x, 50, 60, p=10, k_motifs=4, k_discords=4, path="full", precision="fp32")
+    for key in ("prof_dist", "prof_idx", "valmp_norm", "valmp_idx", "motif_ab", "discord_on",
+                "g_motif_abl", "g_discord_onl"):
+        assert np.array_equal(a[key], b[key], equal_nan=True), key
+
+
+def test_config2_fp32_sampled_parity(oracle_mod):
+    from oracle import compare
+
+    w = gen.config2()
+    _say(f"config2 fp32 n={w.n} L={w.l_min}..{w.l_max}")
+    g = run_gpu(w.x, w.l_min, w.l_max, p=w.p, k_motifs=w.k_motifs, k_discords=w.k_discords, precision="fp32")
+    extra = [v for (a, b, _) in w.planted_motifs for v in (a, b)] + [c for c, _ in w.planted_discords]
+    rep = compare.check_sampled(w.x, w.l_min, g, [100, 101, 150, 200], 96, TOL64, extra=extra)
+    _say(f"config2 fp32 sampled report {dict(rep)} stats sums {g['stats'].sum(axis=0).tolist()}")
