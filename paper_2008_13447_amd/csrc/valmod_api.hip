@@ -20,7 +20,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
   size_t xs, A, B, mu, sig, invn, flat, df, dg, sw32, thr, thr32, best, counters, anc;
-  size_t hc, hS, hn, hbound, hsig, acnt, abuf, fail;
+  size_t hc, hS, hn, hbound, hsig, acnt, abuf, fail, big;
   size_t df32, dg32, inv32, bsw_max, bsw_min, bdf_max, bdg_max, delta, hard;
   size_t total;
 };
@@ -41,48 +41,39 @@ PassGeom pass_geom(int64_t n, int32_t l_min, int32_t excl_den, bool fp32, int32_
   PassGeom g;
   const int64_t N0 = n - l_min + 1;
   const int64_t e0 = excl_zone(l_min, excl_den);
-  g.K = env_int("VALMOD_PASS_K", 8) == 4 ? 4 : 8;
-  if (fp32) {
-    // FP32 recurrence: segments of R rows restart from FP64 anchors (the refresh
-    // interval), computed directly by each work item; R bounds the rounding error.
-    g.K = 8;
-    g.table = false;
-    const int64_t bw = 64 * g.K;
-    g.dstart = (e0 + 1) / 8 * 8;
-    g.H = refresh_R > 0 ? refresh_R : 512;
-    g.bands = (N0 - g.dstart + bw - 1) / bw;
-    g.segs = (N0 - g.dstart + g.H - 1) / g.H;
-    g.stride = g.bands * bw;
-    return g;
-  }
+  g.K = fp32 ? 8 : (env_int("VALMOD_PASS_K", 8) == 4 ? 4 : 8);
   const int64_t bw = 64 * g.K;
   g.dstart = (e0 + 1) / 8 * 8;  // bands start on a multiple of 8 (aligned wide loads)
-  const int64_t ndiag = N0 - 1 - e0;
-  const double cells = ndiag > 0 ? 0.5 * (double)ndiag * (double)(ndiag + 1) : 0.0;
-  // segment height: enough work items to keep every SIMD busy, within [128, 4096]
-  const double items = env_int("VALMOD_PASS_ITEMS", 16384);
-  int64_t H = 4096;
-  while (H > 128 && cells / ((double)bw * (double)H) < items) H /= 2;
-  const int hforce = env_int("VALMOD_PASS_H", 0);
-  if (hforce >= 64 && hforce % 8 == 0) H = hforce;
-  g.H = H;
   g.bands = (N0 - g.dstart + bw - 1) / bw;
-  g.segs = (N0 - g.dstart + H - 1) / H;
   g.stride = g.bands * bw;
+  // FP64 anchor table (one anchor per segment start and diagonal, grown by one
+  // term per length) while it fits this budget; beyond it anchors are formed directly
+  const double budget = (double)env_int("VALMOD_ANCHOR_BUDGET_MIB", 32768) * 1048576.0;
+  auto table_bytes = [&](int64_t H) { return (double)((N0 - g.dstart + H - 1) / H) * (double)g.stride * 8.0; };
+  int64_t H;
+  if (fp32) {
+    // FP32 recurrence: segments of R rows restart from FP64 anchors (the refresh
+    // interval); the rounding bound grows linearly with R
+    H = refresh_R;
+    if (H <= 0) {
+      H = 256;
+      while (H < 1024 && table_bytes(H) > budget) H *= 2;
+    }
+  } else {
+    const int64_t ndiag = N0 - 1 - e0;
+    const double cells = ndiag > 0 ? 0.5 * (double)ndiag * (double)(ndiag + 1) : 0.0;
+    // segment height: enough work items to keep every SIMD busy, within [128, 4096]
+    const double items = env_int("VALMOD_PASS_ITEMS", 16384);
+    H = 4096;
+    while (H > 128 && cells / ((double)bw * (double)H) < items) H /= 2;
+    const int hforce = env_int("VALMOD_PASS_H", 0);
+    if (hforce >= 64 && hforce % 8 == 0) H = hforce;
+  }
+  g.H = H;
+  g.segs = (N0 - g.dstart + H - 1) / H;
+  g.table = table_bytes(H) <= budget;
   return g;
 }
-
-enum {
-  CNT_ERR = 0,
-  CNT_NFLAT = 1,
-  CNT_EV_STEPS = 2,
-  CNT_EV_HITS = 3,
-  CNT_APPENDS = 4,
-  CNT_NFAIL = 5,
-  CNT_VALID = 6,
-  CNT_HARD = 7,
-  CNT_WORDS = 32
-};
 
 }  // namespace
 
@@ -100,6 +91,10 @@ struct valmod_plan_s {
   // timing of the diagonal pass during the last run
   std::vector<hipEvent_t> ev;
   int ev_device = -1;
+  // second stream (default priority) for the FP64 re-run of listed FP32 work
+  // items, overlapped with the FP32 pass; fork/join events
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   double pass_ms = 0.0;
   int64_t pass_launches = 0, pass_cells = 0;
 };
@@ -242,6 +237,7 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
   w.acnt = take(wp * 4);
   w.abuf = take((size_t)P->n0max * (size_t)P->cap * 4);
   w.fail = take(wp * 4);
+  w.big = take(wp * 4);
   if (P->cfg.precision == VALMOD_PREC_FP32_REFRESH) {
     w.df32 = take(wp * 4);
     w.dg32 = take(wp * 4);
@@ -276,6 +272,9 @@ extern "C" valmod_status valmod_series_layout(valmod_plan_t P, int32_t s, valmod
 extern "C" void valmod_plan_free(valmod_plan_t P) {
   if (!P) return;
   for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+  if (P->fork) (void)hipEventDestroy(P->fork);
+  if (P->join) (void)hipEventDestroy(P->join);
+  if (P->aux) (void)hipStreamDestroy(P->aux);
   delete P;
 }
 
@@ -339,6 +338,17 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
   if (P->ev_device != P->cfg.device || (int64_t)P->ev.size() < 4 * total_lengths) {
     for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
     P->ev.clear();
+    if (P->fork) (void)hipEventDestroy(P->fork);
+    if (P->join) (void)hipEventDestroy(P->join);
+    if (P->aux) (void)hipStreamDestroy(P->aux);
+    P->fork = P->join = nullptr;
+    P->aux = nullptr;
+    if (hipEventCreateWithFlags(&P->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&P->join, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking) != hipSuccess) {
+      status = VALMOD_E_HIP;
+      goto done;
+    }
     for (int64_t i = 0; i < 4 * total_lengths; ++i) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) {
@@ -363,6 +373,7 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
     uint32_t* acnt = (uint32_t*)(ws + P->ws.acnt);
     int32_t* abuf = (int32_t*)(ws + P->ws.abuf);
     int32_t* fail = (int32_t*)(ws + P->ws.fail);
+    int32_t* big = (int32_t*)(ws + P->ws.big);
     const bool fp32 = P->cfg.precision == VALMOD_PREC_FP32_REFRESH;
     float* df32 = fp32 ? (float*)(ws + P->ws.df32) : nullptr;
     float* dg32 = fp32 ? (float*)(ws + P->ws.dg32) : nullptr;
@@ -374,7 +385,7 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
     float* delta = fp32 ? (float*)(ws + P->ws.delta) : nullptr;
     int32_t* hard = fp32 ? (int32_t*)(ws + P->ws.hard) : nullptr;
     // FP32 work items whose rounding bound exceeds this go to the FP64 kernel
-    const float delta_max = (float)(env_int("VALMOD_FP32_DELTA_MAX_E6", 2000) * 1.0e-6);
+    const float delta_max = (float)(env_int("VALMOD_FP32_DELTA_MAX_E6", 5000) * 1.0e-6);
     const int p = P->cfg.p;
     const int D = p < 15 ? p : 15;
     const double margin = 1.0e-11;  // pass rounding of the FP64 correlation
@@ -461,57 +472,62 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
           fp32_ready = true;
           hipError_t e1 = launch_fp32_prep(sig, invn, df, dg, N, L, df32, dg32, inv32, bsw_max, bsw_min, bdf_max,
                                            bdg_max, st);
-          if (e1 == hipSuccess) e1 = hipMemsetAsync(&cnt[CNT_HARD], 0, 8, st);
           if (e1 == hipSuccess)
             e1 = launch_fp32_items(bsw_max, bsw_min, bdf_max, bdg_max, N, e, G.dstart, G.K, G.H, delta_max, delta,
                                    hard, &cnt[CNT_HARD], st);
           return e1;
         };
-        int64_t listed = 0;  // owners in the recompute list
+        bool recompute = false;  // process the recompute list (its length is a device counter)
+        bool swept = false;      // the sweep filled the recompute list at this length
         // collecting pass above per-owner thresholds from the candidates of `src`,
         // then the exact merge (top-`keep` partial profiles and best keys)
         auto collect = [&](const int32_t* src, int p_eff, int keep, int best_exact) -> hipError_t {
-          hipError_t e1 = hipMemsetAsync(&cnt[CNT_NFAIL], 0, 8, st);
+          hipError_t e1 = swept ? launch_zero_counters(&cnt[CNT_NFAIL], 1, st) : hipSuccess;
           if (e1 == hipSuccess)
-            e1 = launch_seed_append(xs, A, invn, flat, src, N, L, e, p_eff, D, margin, best_exact, thr, acnt, fail,
-                                    &cnt[CNT_NFAIL], st);
+            e1 = launch_seed_append(xs, A, invn, flat, src, N, L, e, p_eff, p_eff == 1 ? 0 : D, margin, best_exact,
+                                    thr, acnt, fail, &cnt[CNT_NFAIL], st);
           PassLaunch q = pl;
           q.append = true;
           if (fp32) {
             if (e1 == hipSuccess) e1 = fp32_setup();
             if (e1 == hipSuccess) e1 = launch_thr_to_f32(thr, N + kPad, thr32, st);
-            q.fp32 = true;
-            q.delta = delta;
-            q.delta_max = delta_max;
-            if (e1 == hipSuccess) e1 = timed_pass(q);
+            // listed items run in FP64 on the second stream, beside the FP32 pass
             PassLaunch h = pl;
             h.append = true;
             h.items = hard;
             h.nitems = grid.segs * grid.bands;
             h.nitems_dev = &cnt[CNT_HARD];
-            if (e1 == hipSuccess) e1 = launch_pass(h, st);
+            if (e1 == hipSuccess) e1 = hipEventRecord(P->fork, st);
+            if (e1 == hipSuccess) e1 = hipStreamWaitEvent(P->aux, P->fork, 0);
+            if (e1 == hipSuccess) e1 = launch_pass(h, P->aux);
+            if (e1 == hipSuccess) e1 = hipEventRecord(P->join, P->aux);
             ++passes;
+            q.fp32 = true;
+            q.delta = delta;
+            q.delta_max = delta_max;
+            if (e1 == hipSuccess) e1 = timed_pass(q);
+            if (e1 == hipSuccess) e1 = hipStreamWaitEvent(st, P->join, 0);
           } else if (e1 == hipSuccess) {
             e1 = timed_pass(q);
           }
           if (e1 == hipSuccess)
             e1 = launch_merge(xs, A, invn, sig, flat, thr, acnt, abuf, P->cap, N, L, p, keep, margin, best_exact, hc,
-                              hS, hn, hbound, hsig, best, fail, &cnt[CNT_NFAIL], &cnt[CNT_APPENDS], st);
-          if (e1 == hipSuccess) e1 = read_counters();
-          if (e1 == hipSuccess) listed = (int64_t)hcnt[CNT_NFAIL];
+                              hS, hn, hbound, hsig, best, fail, &cnt[CNT_NFAIL], big, &cnt[CNT_BIG],
+                              &cnt[CNT_APPENDS], st);
+          recompute = true;
           return e1;
         };
 
-        int64_t nvalid = 0, nswept_fail = 0, nrecomp = 0;
+        int64_t nvalid = 0, nswept_fail = 0;
         bool full = true, rebuild = false;
         if (L == Ls.l_min) {
           rebuild = heaps_on;
         } else if (heaps_on && base > 0) {
           // Alg. ComputeSubMP: sweep the partial profiles, certify by the lower bound
-          VCHECK(hipMemsetAsync(&cnt[CNT_NFAIL], 0, 16, st));
           VCHECK(launch_sweep(xs, A, invn, sig, flat, N, L, e, p, base, hc, hS, hn, hbound, hsig, best, fail,
                               &cnt[CNT_NFAIL], &cnt[CNT_VALID], st));
           VCHECK(read_counters());
+          swept = true;
           nswept_fail = (int64_t)hcnt[CNT_NFAIL];
           nvalid = (int64_t)hcnt[CNT_VALID];
           // row recompute of the failing windows vs one full pass (cost model in FMA-equivalents)
@@ -519,7 +535,7 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
           const bool cheap = (double)nswept_fail * (double)N * (double)L <= rec_factor * cells;
           if (P->cfg.path == VALMOD_PATH_RECOMPUTE || cheap) {
             full = false;
-            listed = nswept_fail;
+            recompute = nswept_fail > 0;
           } else if (probe_next && (double)nswept_fail > 0.25 * (double)N) {
             heaps_on = false;  // the bound fails right after a rebuild: partial profiles do not pay here
           } else {
@@ -555,14 +571,11 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
             VCHECK(collect(src, 1, 0, 0));
           }
         }
-        if (listed > 0) {
-          VCHECK(launch_recompute(xs, A, invn, flat, fail, listed, N, L, e, best, st));
-          nrecomp = listed;
-        }
+        if (recompute) VCHECK(launch_recompute(xs, A, invn, flat, fail, &cnt[CNT_NFAIL], N, N, L, e, best, st));
         VCHECK(launch_finalize(xs, mu, sig, best, N, L, pd, pi, vnorm, vdist, vlen, vidx, st));
         VCHECK(launch_fill_tail(N, N0, pd, pi, st));
         VCHECK(launch_record_stats(cnt, o->stats ? o->stats + Ls.stats + t * VALMOD_NSTATS : nullptr, full ? 1 : 0,
-                                   nvalid, nswept_fail, nrecomp, passes, st));
+                                   nvalid, nswept_fail, recompute ? 1 : 0, passes, st));
       }
       VCHECK(launch_rankings(o->prof_dist + Ls.prof, o->prof_idx + Ls.prof, N0, n, Ls.l_min, (int)Ls.nlen,
                              excl_den, km, kd, o->motif_ab + 2 * Ls.motif, o->motif_d + Ls.motif,

@@ -66,4 +66,33 @@ __host__ __device__ __forceinline__ int64_t excl_zone(int64_t L, int64_t den) {
   return (L + den - 1) / den;
 }
 
+// Anchored cross sums formed directly: S[q] = sum_{k<L} (x_{i0+k} - x_{i0}) (x_{j+k} - x_j)
+// for the K consecutive windows j = i0 + dl + q (dl may be negative). The lane's K consecutive windows share a
+// register window of K values that slides by one element per k.
+template <int K>
+__device__ __forceinline__ void direct_anchors(const double* __restrict__ xs, int64_t i0, int64_t dl, int L,
+                                               double* S) {
+  const double xi = xs[i0];
+  const double* xc = xs + i0 + dl;
+  double base[K], w[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    base[q] = xc[q];
+    w[q] = base[q];
+    S[q] = 0.0;
+  }
+  // at step k, slot (q + k) mod K holds x_{j0 + q + k}
+  for (int kb = 0; kb < L; kb += K) {
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      const int k = kb + u;
+      if (k >= L) break;
+      const double r = xs[i0 + k] - xi;
+#pragma unroll
+      for (int q = 0; q < K; ++q) S[q] = fma(r, w[(q + u) % K] - base[q], S[q]);
+      w[u] = xc[K + k];  // the slot of x_{j0 + k} takes x_{j0 + K + k}
+    }
+  }
+}
+
 }  // namespace valmod

@@ -21,11 +21,23 @@ namespace valmod {
 
 static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
-// anchored cross sum of windows o and c at length L (direct, L - 1 FMAs)
+// anchored cross sum of windows o and c at length L (direct, L - 1 FMAs in
+// order of k; the loads of 8 terms are issued before their FMAs)
 __device__ __forceinline__ double cross_sum(const double* __restrict__ xs, int L, int64_t o, int64_t c) {
   const double xo = xs[o], xc = xs[c];
   double s = 0.0;
-  for (int k = 1; k < L; ++k) s = fma(xs[o + k] - xo, xs[c + k] - xc, s);
+  int k = 1;
+  for (; k + 8 <= L; k += 8) {
+    double a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = xs[o + k + u];
+      b[u] = xs[c + k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s = fma(a[u] - xo, b[u] - xc, s);
+  }
+  for (; k < L; ++k) s = fma(xs[o + k] - xo, xs[c + k] - xc, s);
   return s;
 }
 
@@ -36,6 +48,24 @@ __device__ __forceinline__ double rho_from_sum(double S, double Ao, double Ac, i
 __device__ __forceinline__ void push_fail(int32_t* fail, unsigned long long* nfail, int64_t o) {
   const unsigned long long pos = atomicAdd(nfail, 1ull);
   fail[pos] = (int32_t)o;
+}
+
+// wavefront-aggregated push: one atomic per wavefront for every lane with `want`
+__device__ __forceinline__ void push_fail_wave(bool want, int32_t* fail, unsigned long long* nfail, int64_t o) {
+  const uint64_t m = __ballot(want);
+  if (!m) return;
+  const int lane = (int)__lane_id();
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(nfail, (unsigned long long)__popcll(m));
+  base = shfl_u64(base, leader);
+  if (want) fail[base + __popcll(m & ((uint64_t(1) << lane) - 1))] = (int32_t)o;
+}
+
+__device__ __forceinline__ void count_wave(bool want, unsigned long long* counter) {
+  const uint64_t m = __ballot(want);
+  if (!m) return;
+  if ((int)__lane_id() == __ffsll((unsigned long long)m) - 1) atomicAdd(counter, (unsigned long long)__popcll(m));
 }
 
 // number of active lanes whose 64-bit key is smaller than `key`
@@ -57,7 +87,9 @@ __device__ __forceinline__ int wave_rank(uint64_t key, bool valid) {
 // the min(p, m)-th largest correlation, which is at most the true p-th largest
 // (and at most the true largest), lowered by a margin covering the rounding of
 // the pass. Owners with no eligible candidate collect nothing and go to the
-// recompute list. One wavefront per owner.
+// recompute list. A group of G >= 4D + 2 lanes per owner (one lane for D = 0,
+// the single candidate src[o]).
+template <int G>
 __global__ __launch_bounds__(kWave) void k_seed_append(const double* __restrict__ xs, const double* __restrict__ A,
                                                        const double* __restrict__ invn,
                                                        const uint8_t* __restrict__ flat,
@@ -66,28 +98,27 @@ __global__ __launch_bounds__(kWave) void k_seed_append(const double* __restrict_
                                                        double* __restrict__ thr,
                                                        uint32_t* __restrict__ cnt, int32_t* __restrict__ fail,
                                                        unsigned long long* __restrict__ nfail) {
-  const int64_t o = blockIdx.x;
-  const int t = threadIdx.x;
-  if (o >= N) return;
-  if (t == 0) cnt[o] = 0;
-  if (flat[o]) {
-    if (t == 0) thr[o] = 3.0;  // not an owner
-    return;
-  }
+  constexpr int OPW = kWave / G;  // owners per wavefront
+  const int t = threadIdx.x, l = t % G, gb = t - l;
+  const int64_t o = (int64_t)blockIdx.x * OPW + t / G;
+  const bool live = o < N;
+  const bool fl = live ? flat[o] != 0 : true;
   int64_t c = -1;
-  if (t <= 2 * D) {
-    const int64_t d = t - D, w = o + d;
-    if (w >= 0 && w < N && src[w] >= 0) c = (int64_t)src[w] - d;
-  } else if (t <= 4 * D + 1) {
-    const int64_t d = t - (3 * D + 1);
-    if (src[o] >= 0) c = (int64_t)src[o] + d;
+  if (!fl) {
+    if (l <= 2 * D) {
+      const int64_t d = l - D, w = o + d;
+      if (w >= 0 && w < N && src[w] >= 0) c = (int64_t)src[w] - d;
+    } else if (l <= 4 * D + 1) {
+      const int64_t d = l - (3 * D + 1);
+      if (src[o] >= 0) c = (int64_t)src[o] + d;
+    }
   }
   bool ok = c >= 0 && c < N && iabs64(c - o) > e && !flat[c];
-  // drop duplicates: keep the lowest lane holding each candidate
-  for (int m = 0; m < kWave; ++m) {
-    const int64_t oc = (int64_t)__shfl((int)c, m, kWave);
-    const int ov = __shfl((int)ok, m, kWave);
-    if (m < t && ov && oc == c) ok = false;
+  // drop duplicates: keep the lowest lane of the group holding each candidate
+  for (int m = 0; m < G; ++m) {
+    const int64_t oc = (int64_t)__shfl((int)c, gb + m, kWave);
+    const int ov = __shfl((int)ok, gb + m, kWave);
+    if (m < l && ov && oc == c) ok = false;
   }
   uint64_t key = kEmptyKey;
   double rho = -2.0;
@@ -95,61 +126,99 @@ __global__ __launch_bounds__(kWave) void k_seed_append(const double* __restrict_
     rho = rho_from_sum(cross_sum(xs, L, o, c), A[o], A[c], L, invn[o], invn[c]);
     key = make_key(rho, c);
   }
-  const int m = __popcll(__ballot(ok));
-  const int rank = wave_rank(key, ok);
-  if (m == 0) {
-    if (t == 0) {
+  int mg = 0, rank = 0;  // eligible candidates of the group, and this lane's rank among them
+  for (int m = 0; m < G; ++m) {
+    const uint64_t other = shfl_u64(key, gb + m);
+    const int ov = __shfl((int)ok, gb + m, kWave);
+    mg += ov;
+    rank += (ov && other < key) ? 1 : 0;
+  }
+  if (!live) return;
+  if (l == 0) cnt[o] = 0;
+  if (fl) {
+    if (l == 0) thr[o] = 3.0;  // not an owner
+    return;
+  }
+  if (mg == 0) {
+    if (l == 0) {
       thr[o] = 3.0;
       if (!best_exact) push_fail(fail, nfail, o);
     }
     return;
   }
   if ((int64_t)p >= N - 1) {
-    if (t == 0) thr[o] = -2.0 - margin;  // a profile can hold every candidate: collect them all
+    if (l == 0) thr[o] = -2.0 - margin;  // a profile can hold every candidate: collect them all
     return;
   }
-  const int want = (p < m ? p : m) - 1;
+  const int want = (p < mg ? p : mg) - 1;
   if (ok && rank == want) thr[o] = rho - margin;
 }
 
 // --------------------------------------------------------------------------
 // Merge of the collected candidates into the partial profile of each owner at
 // the new base length L: exact correlation of every candidate the pass
-// appended, top-p by (correlation desc, index asc), the bound correlation of
-// the ones not kept, and the owner's best key. Owners whose list overflowed
+// appended, top-`keep` by (correlation desc, index asc), the bound correlation
+// of the ones not kept, and the owner's best key. Owners whose list overflowed
 // (incomplete) or that collected nothing go to the recompute list with an empty
-// profile. One wavefront per owner.
+// profile.
+//
+// best_exact: `best` already holds every owner's exact neighbour (a
+// matrix-profile pass ran at this length), so an owner whose profile cannot be
+// built keeps it instead of going to the recompute list.
+//
+// k_merge_small takes a group of kSmallG lanes per owner and one candidate per
+// lane; owners with more candidates are listed for k_merge_big (one wavefront
+// per owner, candidates in LDS).
 constexpr int kMergeCap = 512;
+constexpr int kSmallG = 8;
 
-__global__ __launch_bounds__(kWave) void k_merge(
+// every candidate not collected is below the threshold (up to the pass rounding);
+// below -1 every candidate was collected, and -3 marks a complete profile
+__device__ __forceinline__ double collect_bound(double thr, double margin) {
+  return thr < -1.5 ? -3.0 : thr + 2.0 * margin;
+}
+
+__global__ __launch_bounds__(kWave) void k_merge_small(
     const double* __restrict__ xs, const double* __restrict__ A, const double* __restrict__ invn,
     const double* __restrict__ sig, const uint8_t* __restrict__ flat, const double* __restrict__ thr,
     const uint32_t* __restrict__ cnt, const int32_t* __restrict__ buf, int64_t cap, int64_t N, int L, int p,
     int keep, double margin, int best_exact, int32_t* __restrict__ hc, double* __restrict__ hS, int32_t* __restrict__ hn,
     double* __restrict__ hbound, double* __restrict__ hsig, uint64_t* __restrict__ best, int32_t* __restrict__ fail,
-    unsigned long long* __restrict__ nfail, unsigned long long* __restrict__ nappend) {
-  // best_exact: `best` already holds every owner's exact neighbour (a
-  // matrix-profile pass ran at this length), so an owner whose profile cannot be
-  // built keeps it instead of going to the recompute list.
-  __shared__ uint64_t skey[kMergeCap];
-  __shared__ double srho[kMergeCap];
-  __shared__ double ssum[kMergeCap];
-  __shared__ double sbound;
-  const int64_t o = blockIdx.x;
-  const int t = threadIdx.x;
-  if (o >= N) return;
-  const uint32_t total = cnt[o];
-  if (t == 0 && total) atomicAdd(nappend, (unsigned long long)total);
-  if (flat[o] || thr[o] >= 2.0) {  // not an owner, or already queued for recompute by the seeding
-    if (t == 0) {
+    unsigned long long* __restrict__ nfail, int32_t* __restrict__ big, unsigned long long* __restrict__ nbig) {
+  const int t = threadIdx.x, l = t % kSmallG, gb = t - l;
+  const int64_t o = (int64_t)blockIdx.x * (kWave / kSmallG) + t / kSmallG;
+  const bool live = o < N;
+  int64_t m = 0;
+  bool skip = true;
+  if (live) {
+    m = cnt[o];
+    skip = flat[o] || thr[o] >= 2.0;  // not an owner, or already queued for recompute by the seeding
+  }
+  const bool ok = live && !skip && m <= kSmallG && l < m;
+  int64_t c = -1;
+  double rho = -2.0, S = 0.0;
+  uint64_t key = kEmptyKey;
+  if (ok) {
+    c = buf[o * cap + l];
+    S = cross_sum(xs, L, o, c);
+    rho = rho_from_sum(S, A[o], A[c], L, invn[o], invn[c]);
+    key = make_key(rho, c);
+  }
+  int rank = 0;  // keys of the group are distinct; empty keys sort last
+  for (int mm = 0; mm < kSmallG; ++mm) rank += shfl_u64(key, gb + mm) < key ? 1 : 0;
+  double nb = (ok && rank == keep) ? rho : -4.0;  // the best collected candidate not kept
+#pragma unroll
+  for (int msk = kSmallG / 2; msk >= 1; msk >>= 1) nb = fmax(nb, __shfl_xor(nb, msk, kWave));
+  if (!live) return;
+  if (skip) {
+    if (l == 0) {
       hn[o] = 0;
       if (!best_exact || flat[o]) best[o] = kEmptyKey;
     }
     return;
   }
-  const int64_t m = total;
   if (m == 0 || m > cap || m > kMergeCap) {
-    if (t == 0) {
+    if (l == 0) {
       hn[o] = 0;
       if (!best_exact) {
         best[o] = kEmptyKey;
@@ -158,36 +227,70 @@ __global__ __launch_bounds__(kWave) void k_merge(
     }
     return;
   }
-  const double Ao = A[o], io = invn[o];
-  const int32_t* list = buf + o * cap;
-  for (int64_t r = t; r < m; r += kWave) {
-    const int64_t c = list[r];
-    const double S = cross_sum(xs, L, o, c);
-    const double rho = rho_from_sum(S, Ao, A[c], L, io, invn[c]);
-    skey[r] = make_key(rho, c);
-    srho[r] = rho;
-    ssum[r] = S;
+  if (m > kSmallG) {
+    if (l == 0) push_fail(big, nbig, o);
+    return;
   }
-  // every candidate not collected is below the threshold (up to the pass rounding);
-  // below -1 every candidate was collected, and -3 marks a complete profile
-  if (t == 0) sbound = thr[o] < -1.5 ? -3.0 : thr[o] + 2.0 * margin;
-  __syncthreads();
-  for (int64_t r = t; r < m; r += kWave) {
-    const uint64_t k = skey[r];
-    int64_t rank = 0;
-    for (int64_t s2 = 0; s2 < m; ++s2) rank += skey[s2] < k ? 1 : 0;
-    if (rank < keep) {
-      hc[o * p + rank] = (int32_t)key_cand(k);
-      hS[o * p + rank] = ssum[r];
-    }
-    if (rank == 0) best[o] = k;
-    if (rank == keep && srho[r] > sbound) sbound = srho[r];  // the best collected candidate not kept
+  if (ok && rank < keep) {
+    hc[o * p + rank] = (int32_t)c;
+    hS[o * p + rank] = S;
   }
-  __syncthreads();
-  if (t == 0) {
+  if (ok && rank == 0) best[o] = key;
+  if (l == 0) {
+    const double sb = collect_bound(thr[o], margin);
     hn[o] = (int32_t)(m < keep ? m : keep);
-    hbound[o] = sbound;
+    hbound[o] = nb > sb ? nb : sb;
     hsig[o] = sig[o];
+  }
+}
+
+__global__ __launch_bounds__(kWave) void k_merge_big(
+    const double* __restrict__ xs, const double* __restrict__ A, const double* __restrict__ invn,
+    const double* __restrict__ sig, const double* __restrict__ thr, const uint32_t* __restrict__ cnt,
+    const int32_t* __restrict__ buf, int64_t cap, int L, int p, int keep, double margin,
+    int32_t* __restrict__ hc, double* __restrict__ hS, int32_t* __restrict__ hn, double* __restrict__ hbound,
+    double* __restrict__ hsig, uint64_t* __restrict__ best, const int32_t* __restrict__ big,
+    const unsigned long long* __restrict__ nbig) {
+  extern __shared__ double merge_lds[];  // cap entries each of key, correlation and cross sum
+  uint64_t* skey = (uint64_t*)merge_lds;
+  double* srho = merge_lds + cap;
+  double* ssum = merge_lds + 2 * cap;
+  __shared__ double sbound;
+  const int t = threadIdx.x;
+  const int64_t count = (int64_t)*nbig;
+  for (int64_t w = blockIdx.x; w < count; w += gridDim.x) {
+    const int64_t o = big[w];
+    const int64_t m = cnt[o];  // kSmallG < m <= cap
+    const double Ao = A[o], io = invn[o];
+    const int32_t* list = buf + o * cap;
+    for (int64_t r = t; r < m; r += kWave) {
+      const int64_t c = list[r];
+      const double S = cross_sum(xs, L, o, c);
+      const double rho = rho_from_sum(S, Ao, A[c], L, io, invn[c]);
+      skey[r] = make_key(rho, c);
+      srho[r] = rho;
+      ssum[r] = S;
+    }
+    if (t == 0) sbound = collect_bound(thr[o], margin);
+    __syncthreads();
+    for (int64_t r = t; r < m; r += kWave) {
+      const uint64_t k = skey[r];
+      int64_t rank = 0;
+      for (int64_t s2 = 0; s2 < m; ++s2) rank += skey[s2] < k ? 1 : 0;
+      if (rank < keep) {
+        hc[o * p + rank] = (int32_t)key_cand(k);
+        hS[o * p + rank] = ssum[r];
+      }
+      if (rank == 0) best[o] = k;
+      if (rank == keep && srho[r] > sbound) sbound = srho[r];  // a single lane has this rank
+    }
+    __syncthreads();
+    if (t == 0) {
+      hn[o] = (int32_t)(m < keep ? m : keep);
+      hbound[o] = sbound;
+      hsig[o] = sig[o];
+    }
+    __syncthreads();  // the LDS lists are reused by the next owner
   }
 }
 
@@ -240,40 +343,65 @@ __global__ void k_sweep(const double* __restrict__ xs, const double* __restrict_
       valid = min_dist < max_lb * (1.0 - 1.0e-9);
     }
   }
-  if (valid) {
-    best[o] = kb;
-    atomicAdd(nvalid, 1ull);
-  } else {
-    best[o] = kEmptyKey;
-    push_fail(fail, nfail, o);
-  }
+  best[o] = valid ? kb : kEmptyKey;
+  count_wave(valid, nvalid);
+  push_fail_wave(!valid, fail, nfail, o);
 }
 
 // --------------------------------------------------------------------------
 // Exact row recompute of the listed owners: the whole distance profile at L
 // (every eligible candidate, anchored cross sums formed directly), reduced to
-// the best key. One wavefront per listed owner.
+// the best key. The candidates of one owner are spread over gridDim.x
+// workgroups, kRecK consecutive candidates per lane sharing one sliding
+// register window; the partial minima meet in a 64-bit atomic min on a key
+// that the listing kernel has set to empty.
+constexpr int kRecK = 8;
+
 __global__ __launch_bounds__(kWave) void k_recompute(const double* __restrict__ xs, const double* __restrict__ A,
                                                      const double* __restrict__ invn,
                                                      const uint8_t* __restrict__ flat,
-                                                     const int32_t* __restrict__ fail, int64_t nfail, int64_t N,
-                                                     int L, int64_t e, uint64_t* __restrict__ best) {
-  const int64_t w = blockIdx.x;
-  if (w >= nfail) return;
+                                                     const int32_t* __restrict__ fail,
+                                                     const unsigned long long* __restrict__ nfail, int64_t N, int L,
+                                                     int64_t e, uint64_t* __restrict__ best) {
+  const int64_t count = (int64_t)*nfail;
   const int t = threadIdx.x;
-  const int64_t o = fail[w];
-  const double Ao = A[o], io = invn[o];
-  uint64_t kb = kEmptyKey;
-  if (!flat[o]) {
-    for (int64_t c = t; c < N; c += kWave) {
-      if (iabs64(c - o) <= e || flat[c]) continue;
-      const double rho = rho_from_sum(cross_sum(xs, L, o, c), Ao, A[c], L, io, invn[c]);
-      const uint64_t k = make_key(rho, c);
-      kb = k < kb ? k : kb;
+  const int64_t c0 = ((int64_t)blockIdx.x * kWave + t) * kRecK;
+  for (int64_t w = blockIdx.y; w < count; w += gridDim.y) {
+    const int64_t o = fail[w];
+    uint64_t kb = kEmptyKey;
+    if (c0 < N && !flat[o]) {
+      double S[kRecK];
+      direct_anchors<kRecK>(xs, o, c0 - o, L, S);
+      const double Ao = A[o], io = invn[o];
+#pragma unroll
+      for (int q = 0; q < kRecK; ++q) {
+        const int64_t c = c0 + q;
+        if (c >= N || iabs64(c - o) <= e || flat[c]) continue;
+        const uint64_t k = make_key(rho_from_sum(S[q], Ao, A[c], L, io, invn[c]), c);
+        kb = k < kb ? k : kb;
+      }
     }
+    kb = wave_min_u64(kb);
+    if (t == 0 && kb != kEmptyKey) atomicMin((unsigned long long*)&best[o], (unsigned long long)kb);
   }
-  kb = wave_min_u64(kb);
-  if (t == 0) best[o] = kb;
+}
+
+// total of per-owner counts (one atomic per workgroup)
+__global__ __launch_bounds__(1024) void k_sum_counts(const uint32_t* __restrict__ v, int64_t n,
+                                                     unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long part[1024 / kWave];
+  unsigned long long acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc += v[i];
+#pragma unroll
+  for (int m = kWave / 2; m >= 1; m >>= 1) acc += shfl_xor_u64(acc, m);
+  if (__lane_id() == 0) part[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) s += part[w];
+    if (s) atomicAdd(out, s);
+  }
 }
 
 hipError_t launch_seed_append(const double* xs, const double* A, const double* invn, const uint8_t* flat,
@@ -281,8 +409,22 @@ hipError_t launch_seed_append(const double* xs, const double* A, const double* i
                               int best_exact, double* thr, uint32_t* cnt, int32_t* fail, unsigned long long* nfail,
                               hipStream_t st) {
   if (N <= 0) return hipSuccess;
-  k_seed_append<<<(unsigned)N, kWave, 0, st>>>(xs, A, invn, flat, src, N, L, e, p, D, margin, best_exact, thr, cnt,
-                                               fail, nfail);
+  if (D < 0 || 4 * D + 2 > kWave) return hipErrorInvalidValue;
+  const int seeds = 4 * D + 2;  // D = 0: the single candidate src[o], one lane per owner
+#define SEED_LAUNCH(G)                                                                                     \
+  k_seed_append<G><<<blocks_for(N, kWave / (G)), kWave, 0, st>>>(xs, A, invn, flat, src, N, L, e, p, D, margin, \
+                                                                 best_exact, thr, cnt, fail, nfail)
+  if (D == 0)
+    SEED_LAUNCH(1);
+  else if (seeds <= 8)
+    SEED_LAUNCH(8);
+  else if (seeds <= 16)
+    SEED_LAUNCH(16);
+  else if (seeds <= 32)
+    SEED_LAUNCH(32);
+  else
+    SEED_LAUNCH(64);
+#undef SEED_LAUNCH
   return hipGetLastError();
 }
 
@@ -290,10 +432,15 @@ hipError_t launch_merge(const double* xs, const double* A, const double* invn, c
                         const double* thr, const uint32_t* cnt, const int32_t* buf, int64_t cap, int64_t N, int L,
                         int p, int keep, double margin, int best_exact, int32_t* hc, double* hS, int32_t* hn,
                         double* hbound, double* hsig, uint64_t* best, int32_t* fail, unsigned long long* nfail,
-                        unsigned long long* nappend, hipStream_t st) {
+                        int32_t* big, unsigned long long* nbig, unsigned long long* nappend, hipStream_t st) {
   if (N <= 0) return hipSuccess;
-  k_merge<<<(unsigned)N, kWave, 0, st>>>(xs, A, invn, sig, flat, thr, cnt, buf, cap, N, L, p, keep, margin,
-                                        best_exact, hc, hS, hn, hbound, hsig, best, fail, nfail, nappend);
+  if (cap <= 0 || cap > kMergeCap || keep < 0 || keep > p) return hipErrorInvalidValue;
+  k_merge_small<<<blocks_for(N, kWave / kSmallG), kWave, 0, st>>>(xs, A, invn, sig, flat, thr, cnt, buf, cap, N, L, p,
+                                                                   keep, margin, best_exact, hc, hS, hn, hbound, hsig,
+                                                                   best, fail, nfail, big, nbig);
+  k_merge_big<<<(unsigned)(N < 2048 ? N : 2048), kWave, (size_t)cap * 3 * sizeof(double), st>>>(
+      xs, A, invn, sig, thr, cnt, buf, cap, L, p, keep, margin, hc, hS, hn, hbound, hsig, best, big, nbig);
+  k_sum_counts<<<64, 1024, 0, st>>>(cnt, N, nappend);
   return hipGetLastError();
 }
 
@@ -308,10 +455,11 @@ hipError_t launch_sweep(const double* xs, const double* A, const double* invn, c
 }
 
 hipError_t launch_recompute(const double* xs, const double* A, const double* invn, const uint8_t* flat,
-                            const int32_t* fail, int64_t nfail, int64_t N, int L, int64_t e, uint64_t* best,
-                            hipStream_t st) {
-  if (nfail <= 0) return hipSuccess;
-  k_recompute<<<(unsigned)nfail, kWave, 0, st>>>(xs, A, invn, flat, fail, nfail, N, L, e, best);
+                            const int32_t* fail, const unsigned long long* nfail, int64_t max_listed, int64_t N,
+                            int L, int64_t e, uint64_t* best, hipStream_t st) {
+  if (max_listed <= 0 || N <= 0) return hipSuccess;
+  const dim3 grid(blocks_for(N, kWave * kRecK), (unsigned)(max_listed < 32 ? max_listed : 32));
+  k_recompute<<<grid, kWave, 0, st>>>(xs, A, invn, flat, fail, nfail, N, L, e, best);
   return hipGetLastError();
 }
 

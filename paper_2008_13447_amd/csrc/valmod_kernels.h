@@ -8,6 +8,21 @@ namespace valmod {
 
 constexpr int kPassKMax = 8;  // largest supported diagonals-per-lane of the pass (4 or 8)
 
+// Slots of the device counter block of a run (64-bit each). The per-length ones
+// are recorded and cleared by launch_record_stats at the end of every length.
+enum CounterSlot {
+  CNT_ERR = 0,       // error flag (non-finite input)
+  CNT_NFLAT = 1,     // flat windows at this length
+  CNT_EV_STEPS = 2,  // pass wavefront steps that took the slow path
+  CNT_EV_HITS = 3,   // pass queue entries
+  CNT_APPENDS = 4,   // candidates collected by the collecting pass
+  CNT_NFAIL = 5,     // owners in the recompute list
+  CNT_VALID = 6,     // owners certified by the sweep
+  CNT_HARD = 7,      // FP32 work items listed for the FP64 kernel
+  CNT_BIG = 8,       // owners listed for the wavefront-per-owner merge
+  CNT_WORDS = 32
+};
+
 struct PassLaunch {
   const double *xs, *mu, *df, *dg, *invn;
   const float* sw32;
@@ -64,11 +79,13 @@ hipError_t launch_thr_to_f32(const double* thr, int64_t n, float* thr32, hipStre
 hipError_t launch_finalize(const double* xs, const double* mu, const double* sig, const uint64_t* best,
                            int64_t N, int L, double* prof_dist, int32_t* prof_idx, double* valmp_norm,
                            double* valmp_dist, int32_t* valmp_len, int32_t* valmp_idx, hipStream_t st);
-// counters layout: [0] error flag, [1] flat windows, [2] pass slow-path steps,
-// [3] pass owner hits, [4] appended candidates, [7] FP64 fallback work items;
-// the per-length ones are reset after recording
+// Writes one stats row (host-known values and the per-length device counters;
+// `recomputed`: the recompute list was processed at this length) and clears
+// the per-length counters.
 hipError_t launch_record_stats(unsigned long long* cnt, int64_t* row, int full_pass, int64_t valid,
-                               int64_t failed, int64_t recomputed, int64_t passes, hipStream_t st);
+                               int64_t failed, int recomputed, int64_t passes, hipStream_t st);
+// clears n consecutive counters (a kernel, so that the sequence stays capturable)
+hipError_t launch_zero_counters(unsigned long long* p, int n, hipStream_t st);
 hipError_t launch_fill_tail(int64_t from, int64_t to, double* prof_dist, int32_t* prof_idx, hipStream_t st);
 hipError_t launch_valmp_init(int64_t N0, double* norm, double* dist, int32_t* len, int32_t* idx,
                              hipStream_t st);
@@ -90,14 +107,15 @@ hipError_t launch_merge(const double* xs, const double* A, const double* invn, c
                         const double* thr, const uint32_t* cnt, const int32_t* buf, int64_t cap, int64_t N, int L,
                         int p, int keep, double margin, int best_exact, int32_t* hc, double* hS, int32_t* hn,
                         double* hbound, double* hsig, uint64_t* best, int32_t* fail, unsigned long long* nfail,
-                        unsigned long long* nappend, hipStream_t st);
+                        int32_t* big, unsigned long long* nbig, unsigned long long* nappend, hipStream_t st);
 hipError_t launch_sweep(const double* xs, const double* A, const double* invn, const double* sig, const uint8_t* flat,
                         int64_t N, int L, int64_t e, int p, int base, const int32_t* hc, double* hS, const int32_t* hn,
                         const double* hbound, const double* hsig, uint64_t* best, int32_t* fail,
                         unsigned long long* nfail, unsigned long long* nvalid, hipStream_t st);
+// the list length is read on the device (nfail); max_listed bounds it
 hipError_t launch_recompute(const double* xs, const double* A, const double* invn, const uint8_t* flat,
-                            const int32_t* fail, int64_t nfail, int64_t N, int L, int64_t e, uint64_t* best,
-                            hipStream_t st);
+                            const int32_t* fail, const unsigned long long* nfail, int64_t max_listed, int64_t N,
+                            int L, int64_t e, uint64_t* best, hipStream_t st);
 // copies best keys into an int32 index array (-1 for empty keys)
 hipError_t launch_keys_to_idx(const uint64_t* best, int64_t N, int32_t* idx, hipStream_t st);
 

@@ -201,21 +201,26 @@ __global__ void k_finalize(const double* __restrict__ xs, const double* __restri
 // Per-length diagnostic counters: copies the running device counters into the
 // stats row of length t and clears them.
 __global__ void k_record_stats(unsigned long long* __restrict__ cnt, int64_t* __restrict__ row, int full_pass,
-                               int64_t valid, int64_t failed, int64_t recomputed, int64_t passes) {
+                               int64_t valid, int64_t failed, int recomputed, int64_t passes) {
   if (threadIdx.x != 0) return;
   if (row) {
     row[0] = valid;
     row[1] = failed;
-    row[2] = recomputed;
+    row[2] = recomputed ? (int64_t)cnt[CNT_NFAIL] : 0;
     row[3] = full_pass;
-    row[4] = (int64_t)cnt[1];
-    row[5] = (int64_t)cnt[4];
-    row[6] = (int64_t)cnt[2];
-    row[7] = (int64_t)cnt[3];
-    row[8] = (int64_t)cnt[7];
+    row[4] = (int64_t)cnt[CNT_NFLAT];
+    row[5] = (int64_t)cnt[CNT_APPENDS];
+    row[6] = (int64_t)cnt[CNT_EV_STEPS];
+    row[7] = (int64_t)cnt[CNT_EV_HITS];
+    row[8] = (int64_t)cnt[CNT_HARD];
     row[9] = passes;
   }
-  cnt[1] = cnt[2] = cnt[3] = cnt[4] = cnt[7] = 0;
+  cnt[CNT_NFLAT] = cnt[CNT_EV_STEPS] = cnt[CNT_EV_HITS] = cnt[CNT_APPENDS] = 0;
+  cnt[CNT_NFAIL] = cnt[CNT_VALID] = cnt[CNT_HARD] = cnt[CNT_BIG] = 0;
+}
+
+__global__ void k_zero_counters(unsigned long long* __restrict__ p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
 __global__ void k_fill_tail(int64_t from, int64_t to, double* __restrict__ prof_dist,
@@ -518,8 +523,14 @@ hipError_t launch_finalize(const double* xs, const double* mu, const double* sig
 }
 
 hipError_t launch_record_stats(unsigned long long* cnt, int64_t* row, int full_pass, int64_t valid,
-                               int64_t failed, int64_t recomputed, int64_t passes, hipStream_t st) {
+                               int64_t failed, int recomputed, int64_t passes, hipStream_t st) {
   k_record_stats<<<1, 64, 0, st>>>(cnt, row, full_pass, valid, failed, recomputed, passes);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_counters(unsigned long long* p, int n, hipStream_t st) {
+  if (n <= 0 || n > 64) return hipErrorInvalidValue;
+  k_zero_counters<<<1, 64, 0, st>>>(p, n);
   return hipGetLastError();
 }
 

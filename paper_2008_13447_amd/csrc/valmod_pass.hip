@@ -125,6 +125,7 @@ __device__ __forceinline__ void load_run(const float* p, float* dst) {
 // drain all prefetches); the queue is flushed to global memory when it could
 // overflow at the next step and at the end of the work item.
 constexpr int kQueue = 1024;
+static_assert(kQueue >= 2 * kWave * kPassKMax, "one collecting step must fit an empty queue");
 
 // min of two thresholds (never NaN) without the IEEE quieting of the operands
 // that fmin() implies.
@@ -137,35 +138,6 @@ __device__ __forceinline__ float vmin(float a, float b) {
   float r;
   asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
   return r;
-}
-
-// FP64 anchors computed directly: S[q] = sum_{k<L} (x_{i0+k} - x_{i0}) (x_{j+k} - x_j)
-// for the K diagonals j = i0 + dl + q. The lane's K consecutive windows share a
-// register window of K values that slides by one element per k.
-template <int K>
-__device__ __forceinline__ void direct_anchors(const double* __restrict__ xs, int64_t i0, int64_t dl, int L,
-                                               double* S) {
-  const double xi = xs[i0];
-  const double* xc = xs + i0 + dl;
-  double base[K], w[K];
-#pragma unroll
-  for (int q = 0; q < K; ++q) {
-    base[q] = xc[q];
-    w[q] = base[q];
-    S[q] = 0.0;
-  }
-  // at step k, slot (q + k) mod K holds x_{j0 + q + k}
-  for (int kb = 0; kb < L; kb += K) {
-#pragma unroll
-    for (int u = 0; u < K; ++u) {
-      const int k = kb + u;
-      if (k >= L) break;
-      const double r = xs[i0 + k] - xi;
-#pragma unroll
-      for (int q = 0; q < K; ++q) S[q] = fma(r, w[(q + u) % K] - base[q], S[q]);
-      w[u] = xc[K + k];  // the slot of x_{j0 + k} takes x_{j0 + K + k}
-    }
-  }
 }
 
 template <typename T, int K, int MODE>
@@ -184,6 +156,7 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
   const int64_t N = a.N;
   int64_t seg = blockIdx.x, band = blockIdx.y;
   if (a.items) {
+    // listed items: one per workgroup; the grid is an upper bound of the device count
     if ((unsigned long long)blockIdx.x >= *a.nitems) return;
     const int64_t id = a.items[blockIdx.x];
     seg = id / a.bands;
@@ -262,8 +235,8 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
     __syncthreads();
     qn = 0;
   };
-  auto push = [&](bool want, int32_t owner, uint64_t val) {
-    const uint64_t m = __ballot(want);
+  // append the lanes of mask m (this lane: `want`) to the queue
+  auto push_m = [&](uint64_t m, bool want, int32_t owner, uint64_t val) {
     if (!m) return;
     if (want) {
       const int pos = qn + __popcll(m & ((uint64_t(1) << t) - 1));
@@ -272,6 +245,7 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
     }
     qn += __popcll(m);
   };
+  auto push = [&](bool want, int32_t owner, uint64_t val) { push_m(__ballot(want), want, owner, val); };
 
   // one block of K rows starting at row ib; slots start in P and move to Q
   auto block = [&](int64_t ib, T* Pdf, T* Pdg, T* Pinv, T* Pthr, T* Qdf, T* Qdg, T* Qinv, T* Qthr) {
@@ -299,8 +273,10 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
         const T th = (s < u ? Qthr[s] : Pthr[s]) - delta;
         pass |= (C[q] * inv) * rinv[u] >= vmin(th, rthr[u]);
       }
-      if (__any(pass)) {
+      const bool any_pass = __any(pass);
+      if (MODE == MODE_MP && any_pass) {
         ++ev_steps;
+        // at most K column entries per lane and one row entry per step
         if (qn + kWave * K + 1 > kQueue) flush();
         uint64_t rowkey = kEmptyKey;
 #pragma unroll
@@ -312,25 +288,44 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
           const T rho = (C[q] * inv) * rinv[u];
           const bool ok = j < N && rinv[u] > (T)0 && inv > (T)0;
           const bool col = ok && rho >= th - delta;
-          if (MODE == MODE_MP) {
-            const uint64_t key = col ? make_key((double)rho, i) : kEmptyKey;
-            push(col, (int32_t)j, key);
-            if (col) {
-              const T nt = (T)key_threshold(key);
-              th = nt > th ? nt : th;
-            }
-            if (ok && rho >= rthr[u]) {
-              const uint64_t k2 = make_key((double)rho, j);
-              rowkey = k2 < rowkey ? k2 : rowkey;
-            }
-          } else {
-            push(col, (int32_t)j, (uint64_t)i);
-            push(ok && rho >= rthr[u], (int32_t)i, (uint64_t)j);
+          const uint64_t key = col ? make_key((double)rho, i) : kEmptyKey;
+          push(col, (int32_t)j, key);
+          if (col) {
+            const T nt = (T)key_threshold(key);
+            th = nt > th ? nt : th;
+          }
+          if (ok && rho >= rthr[u]) {
+            const uint64_t k2 = make_key((double)rho, j);
+            rowkey = k2 < rowkey ? k2 : rowkey;
           }
         }
-        if (MODE == MODE_MP && __any(rowkey != kEmptyKey)) {
+        if (__any(rowkey != kEmptyKey)) {
           rowkey = wave_min_u64(rowkey);
           push(t == 0, (int32_t)i, rowkey);
+        }
+      } else if (MODE == MODE_APPEND && any_pass) {
+        ++ev_steps;
+        // up to two entries per cell (column and row owner): count them first
+        uint64_t mcol[K], mrow[K];
+        int tot = 0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          const int s = (q + u) % K;
+          const int64_t j = i + dl + q;
+          const T inv = s < u ? Qinv[s] : Pinv[s];
+          const T th = s < u ? Qthr[s] : Pthr[s];
+          const T rho = (C[q] * inv) * rinv[u];
+          const bool ok = j < N && rinv[u] > (T)0 && inv > (T)0;
+          mcol[q] = __ballot(ok && rho >= th - delta);
+          mrow[q] = __ballot(ok && rho >= rthr[u]);
+          tot += __popcll(mcol[q]) + __popcll(mrow[q]);
+        }
+        if (qn + tot > kQueue) flush();  // tot <= 2 * kWave * K == kQueue
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          const int64_t j = i + dl + q;
+          push_m(mcol[q], (mcol[q] >> t) & 1, (int32_t)j, (uint64_t)i);
+          push_m(mrow[q], (mrow[q] >> t) & 1, (int32_t)i, (uint64_t)j);
         }
       }
       // advance every diagonal one row: C(i+1, j+1) = C(i, j) + df_i dg_j + df_j dg_i
@@ -418,29 +413,47 @@ __global__ void k_delta(const float* __restrict__ bsw_max, const float* __restri
   delta[id] = d < 1.0 ? (float)d * 1.0000002f : 1.0f;
 }
 
-// Per-block (64 windows) extrema feeding k_delta.
-__global__ void k_block_extrema(const double* __restrict__ sig, const double* __restrict__ invn,
-                                const double* __restrict__ df, const double* __restrict__ dg, int64_t N, int L,
-                                float* __restrict__ bsw_max, float* __restrict__ bsw_min,
-                                float* __restrict__ bdf_max, float* __restrict__ bdg_max, int64_t nblk) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nblk) return;
+// Per-block (64 windows) extrema feeding k_delta: one wavefront per block.
+__device__ __forceinline__ double wave_max_f64(double v) {
+#pragma unroll
+  for (int m = kWave / 2; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, kWave));
+  return v;
+}
+__device__ __forceinline__ double wave_min_f64(double v) {
+#pragma unroll
+  for (int m = kWave / 2; m >= 1; m >>= 1) v = fmin(v, __shfl_xor(v, m, kWave));
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_block_extrema(const double* __restrict__ sig, const double* __restrict__ invn,
+                                                       const double* __restrict__ df, const double* __restrict__ dg,
+                                                       int64_t N, int L, float* __restrict__ bsw_max,
+                                                       float* __restrict__ bsw_min, float* __restrict__ bdf_max,
+                                                       float* __restrict__ bdg_max, int64_t nblk) {
+  const int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (b >= nblk) return;  // uniform per wavefront
+  const int64_t i = b * kWave + threadIdx.x % kWave;
   double smax = 0.0, smin = INFINITY, fmx = 0.0, gmx = 0.0;
-  const double sl = sqrt((double)L);
-  for (int64_t i = b * 64; i < b * 64 + 64 && i < N; ++i) {
+  if (i < N) {
     if (invn[i] > 0.0) {
-      const double w = sig[i] * sl;
-      smax = w > smax ? w : smax;
-      smin = w < smin ? w : smin;
+      const double w = sig[i] * sqrt((double)L);
+      smax = w;
+      smin = w;
     }
-    fmx = fmax(fmx, fabs(df[i]));
-    gmx = fmax(gmx, fabs(dg[i]));
+    fmx = fabs(df[i]);
+    gmx = fabs(dg[i]);
   }
-  // rounded outward so that the item bound stays an upper bound
-  bsw_max[b] = smax > 0.0 ? __double2float_ru(smax) : 0.0f;
-  bsw_min[b] = smin < INFINITY ? __double2float_rd(smin) : INFINITY;
-  bdf_max[b] = __double2float_ru(fmx);
-  bdg_max[b] = __double2float_ru(gmx);
+  smax = wave_max_f64(smax);
+  smin = wave_min_f64(smin);
+  fmx = wave_max_f64(fmx);
+  gmx = wave_max_f64(gmx);
+  if (threadIdx.x % kWave == 0) {
+    // rounded outward so that the item bound stays an upper bound
+    bsw_max[b] = smax > 0.0 ? __double2float_ru(smax) : 0.0f;
+    bsw_min[b] = smin < INFINITY ? __double2float_rd(smin) : INFINITY;
+    bdf_max[b] = __double2float_ru(fmx);
+    bdg_max[b] = __double2float_ru(gmx);
+  }
 }
 
 // FP32 copies of the recurrence inputs (nearest rounding; their error is part
@@ -514,7 +527,7 @@ static hipError_t launch_pass_k(const PassLaunch& p, hipStream_t st) {
   a.bands = g.bands;
   a.L = p.L;
   if (p.items && (p.nitems <= 0 || !p.nitems_dev)) return p.nitems < 0 ? hipErrorInvalidValue : hipSuccess;
-  dim3 grid = p.items ? dim3((unsigned)p.nitems, 1) : dim3((unsigned)g.segs, (unsigned)g.bands);
+  const dim3 grid = p.items ? dim3((unsigned)p.nitems, 1) : dim3((unsigned)g.segs, (unsigned)g.bands);
   const T* df = (const T*)(sizeof(T) == 8 ? (const void*)p.df : (const void*)p.df32);
   const T* dg = (const T*)(sizeof(T) == 8 ? (const void*)p.dg : (const void*)p.dg32);
   const T* inv = (const T*)(sizeof(T) == 8 ? (const void*)p.invn : (const void*)p.inv32);
@@ -542,8 +555,8 @@ hipError_t launch_fp32_prep(const double* sig, const double* invn, const double*
   const int64_t n = N + kPad;
   k_to_f32<<<blocks_for(n, 256), 256, 0, st>>>(df, dg, invn, n, df32, dg32, inv32);
   const int64_t nblk = (N + 63) / 64;
-  k_block_extrema<<<blocks_for(nblk, 128), 128, 0, st>>>(sig, invn, df, dg, N, L, bsw_max, bsw_min, bdf_max,
-                                                         bdg_max, nblk);
+  k_block_extrema<<<blocks_for(nblk, 4), 256, 0, st>>>(sig, invn, df, dg, N, L, bsw_max, bsw_min, bdf_max, bdg_max,
+                                                       nblk);
   return hipGetLastError();
 }
 

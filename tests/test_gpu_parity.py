@@ -292,3 +292,17 @@ def test_config2_fp32_sampled_parity(oracle_mod):
     extra = [v for (a, b, _) in w.planted_motifs for v in (a, b)] + [c for c, _ in w.planted_discords]
     rep = compare.check_sampled(w.x, w.l_min, g, [100, 101, 150, 200], 96, TOL64, extra=extra)
     _say(f"config2 fp32 sampled report {dict(rep)} stats sums {g['stats'].sum(axis=0).tolist()}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_direct_anchors_without_table(oracle_mod, monkeypatch, precision):
+    """A zero anchor-table budget makes every work item form its FP64 anchors
+    directly (L FMAs per diagonal) instead of reading the grown table."""
+    from oracle import compare
+
+    monkeypatch.setenv("VALMOD_ANCHOR_BUDGET_MIB", "0")
+    x = gen.small_random_walk(2600, 74, np.float32)
+    _say(f"direct anchors {precision}")
+    g = run_gpu(x, 25, 33, p=5, k_motifs=3, k_discords=3, path="full", precision=precision)
+    r = oracle_mod.valmod(x, 25, 33, k_motifs=3, k_discords=3)
+    compare.check_full(x, 25, g, r, TOL64)
