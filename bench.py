@@ -3,6 +3,8 @@
 A step is one valmod_run over one series: window statistics, the diagonal
 pass(es), the per-length update, VALMP and the rankings for every length of the
 workload. Inputs are resident in HBM before timing starts. Prints one JSON line.
+The headline path is the FP32 recurrence with FP64 refresh; the FP64 path is
+timed beside it on the same input and the two outputs are compared.
 
 Metric (matrix-profile cells per second): sum over lengths L of N_L (N_L - 1) / 2,
 N_L = n - L + 1, divided by the time of one step.
@@ -80,7 +82,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 5])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"],
+                    help="headline path (the other one is timed beside it unless --no-compare)")
+    ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--path", default="auto", choices=["auto", "full", "recompute"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -110,19 +114,25 @@ def main():
     w = gen.WORKLOADS[args.config]()
     dev = torch.device("cuda:0")
     x = torch.from_numpy(np.ascontiguousarray(w.x)).to(dev)
-    v = native.Valmod(x, w.l_min, w.l_max, p=w.p, k_motifs=w.k_motifs, k_discords=w.k_discords,
-                      excl_den=w.excl_den, precision=args.precision, path=args.path)
-    for _ in range(args.warmup):
-        v.run()
-    torch.cuda.synchronize(dev)
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        v.run()
-    torch.cuda.synchronize(dev)
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
     cells = cells_total(w.n, w.l_min, w.l_max)
-    pass_ms, launches, pass_cells = v.pass_timing()
+
+    def timed(precision):
+        v = native.Valmod(x, w.l_min, w.l_max, p=w.p, k_motifs=w.k_motifs, k_discords=w.k_discords,
+                          excl_den=w.excl_den, precision=precision, path=args.path)
+        for _ in range(args.warmup):
+            v.run()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            v.run()
+        torch.cuda.synchronize(dev)
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        timing = v.pass_timing()
+        res = v.result(0)
+        v.close()
+        return ms, timing, res
+
+    ms, (pass_ms, launches, pass_cells), res = timed(args.precision)
     avg_ms = pass_ms / max(launches, 1)
     achieved = (pass_cells / max(launches, 1)) * FLOP_PER_CELL / (avg_ms * 1e-3) / 1e12
     peak = FP64_PEAK_TFLOPS if args.precision == "fp64" else FP32_PEAK_TFLOPS
@@ -133,19 +143,32 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "l_min": w.l_min, "l_max": w.l_max, "p": w.p,
                    "k": w.k_motifs, "precision": args.precision, "path": args.path},
-        "roofline": {"bound": "alu", "kernel": "k_pass (diagonal pass)", "achieved": achieved, "peak": peak,
+        "roofline": {"bound": "alu", "kernel": f"k_pass<{'double' if args.precision == 'fp64' else 'float'}> "
+                     "(diagonal pass)", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": profiled_traffic(args.precision),
                      "avg_launch_ms": avg_ms, "launches_per_step": launches,
                      "cells_per_launch": pass_cells / max(launches, 1)},
     }
-    res = v.result(0)
     st = res["stats"].sum(axis=0)
     out["diagnostics"] = {name: int(st[c]) for c, name in enumerate(native.STAT_NAMES)}
-    out["diagnostics"]["wave_steps_per_pass"] = int(pass_cells / max(launches, 1) / 512)
+    if not args.no_compare:
+        # the other precision on the same input: throughput and output agreement
+        other = "fp64" if args.precision == "fp32" else "fp32"
+        ms2, _, res2 = timed(other)
+        L = np.arange(w.l_min, w.l_max + 1)[:, None]
+        a, b = res["prof_dist"] / np.sqrt(L), res2["prof_dist"] / np.sqrt(L)
+        fin = np.isfinite(a) & np.isfinite(b)
+        out[f"{other}_path"] = {
+            "value": cells / (ms2 * 1e-3), "ms_per_step": ms2,
+            "speedup_of_headline": ms2 / ms,
+            "max_abs_dn_diff": float(np.max(np.abs(a[fin] - b[fin]))) if fin.any() else 0.0,
+            "idx_diff": int(np.sum(res["prof_idx"] != res2["prof_idx"])),
+        }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w.x, w.l_min, w.excl_den, res["prof_dist"][0], res["prof_idx"][0],
+        Lc = (w.l_min + w.l_max) // 2  # a length the per-length update computes, not the first one
+        t = Lc - w.l_min
+        out["cpu_baseline"] = cpu_baseline(w.x, Lc, w.excl_den, res["prof_dist"][t], res["prof_idx"][t],
                                            args.cpu_seconds)
-    v.close()
     print(json.dumps(out), flush=True)
 
 
