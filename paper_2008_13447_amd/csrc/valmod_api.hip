@@ -41,7 +41,7 @@ PassGeom pass_geom(int64_t n, int32_t l_min, int32_t excl_den, bool fp32, int32_
   PassGeom g;
   const int64_t N0 = n - l_min + 1;
   const int64_t e0 = excl_zone(l_min, excl_den);
-  g.K = fp32 ? 8 : (env_int("VALMOD_PASS_K", 8) == 4 ? 4 : 8);
+  g.K = env_int(fp32 ? "VALMOD_PASS_K32" : "VALMOD_PASS_K", 8) == 4 ? 4 : 8;
   const int64_t bw = 64 * g.K;
   g.dstart = (e0 + 1) / 8 * 8;  // bands start on a multiple of 8 (aligned wide loads)
   g.bands = (N0 - g.dstart + bw - 1) / bw;

@@ -4,6 +4,7 @@
 #include "valmod_kernels.h"
 
 #include <math.h>
+#include <type_traits>
 
 namespace valmod {
 
@@ -108,14 +109,23 @@ __device__ __forceinline__ void load_run(const double* p, double* dst) {
 }
 template <int n>
 __device__ __forceinline__ void load_run(const float* p, float* dst) {
-  static_assert(n % 4 == 0, "float runs are loaded 4 at a time");
+  static_assert(n % 2 == 0, "float runs are loaded 4 (or 2) at a time");
+  if (n % 4 == 0) {
 #pragma unroll
-  for (int u = 0; u < n; u += 4) {
-    const float4 v = *(const float4*)(p + u);
-    dst[u] = v.x;
-    dst[u + 1] = v.y;
-    dst[u + 2] = v.z;
-    dst[u + 3] = v.w;
+    for (int u = 0; u < n; u += 4) {
+      const float4 v = *(const float4*)(p + u);
+      dst[u] = v.x;
+      dst[u + 1] = v.y;
+      dst[u + 2] = v.z;
+      dst[u + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < n; u += 2) {
+      const float2 v = *(const float2*)(p + u);
+      dst[u] = v.x;
+      dst[u + 1] = v.y;
+    }
   }
 }
 
@@ -124,8 +134,12 @@ __device__ __forceinline__ void load_run(const float* p, float* dst) {
 // loads, and a write inside a data-dependent branch makes every later wait
 // drain all prefetches); the queue is flushed to global memory when it could
 // overflow at the next step and at the end of the work item.
-constexpr int kQueue = 1024;
-static_assert(kQueue >= 2 * kWave * kPassKMax, "one collecting step must fit an empty queue");
+// Queue capacity of a wavefront: one collecting step (two entries per cell) fits
+// an empty queue.
+template <int K>
+struct PassQueue {
+  static constexpr int size = 2 * kWave * K;
+};
 
 // min of two thresholds (never NaN) without the IEEE quieting of the operands
 // that fmin() implies.
@@ -147,11 +161,13 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
                                                 const double* __restrict__ g_A, PassArgs a) {
   // g_thr aliases the threshold array this kernel updates in MODE_MP: reads
   // through it may return older values, which only loosens the filter.
-  static_assert(K % 8 == 0 || (sizeof(T) == 8 && K % 4 == 0), "run loads need K multiple of 8 (4 for double)");
+  static_assert(K % 4 == 0, "run loads need K multiple of 4");
   constexpr int64_t BW = (int64_t)kWave * K;  // diagonals per band
   constexpr int HK = K / 2;
+  constexpr int kQueue = PassQueue<K>::size;
+  using QVal = typename std::conditional<MODE == MODE_MP, uint64_t, uint32_t>::type;
   __shared__ int32_t q_owner[kQueue];
-  __shared__ uint64_t q_val[kQueue];  // MODE_MP: packed key; MODE_APPEND: candidate index
+  __shared__ QVal q_val[kQueue];  // MODE_MP: packed key; MODE_APPEND: candidate index
   const int t = threadIdx.x;
   const int64_t N = a.N;
   int64_t seg = blockIdx.x, band = blockIdx.y;
@@ -241,7 +257,7 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
     if (want) {
       const int pos = qn + __popcll(m & ((uint64_t(1) << t) - 1));
       q_owner[pos] = owner;
-      q_val[pos] = val;
+      q_val[pos] = (QVal)val;
     }
     qn += __popcll(m);
   };
@@ -542,6 +558,7 @@ static hipError_t launch_pass_k(const PassLaunch& p, hipStream_t st) {
 hipError_t launch_pass(const PassLaunch& p, hipStream_t st) {
   if (p.fp32) {
     if (p.K == 8) return launch_pass_k<float, 8>(p, st);
+    if (p.K == 4) return launch_pass_k<float, 4>(p, st);
     return hipErrorInvalidValue;
   }
   if (p.K == 8) return launch_pass_k<double, 8>(p, st);

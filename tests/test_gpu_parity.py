@@ -306,3 +306,18 @@ def test_direct_anchors_without_table(oracle_mod, monkeypatch, precision):
     g = run_gpu(x, 25, 33, p=5, k_motifs=3, k_discords=3, path="full", precision=precision)
     r = oracle_mod.valmod(x, 25, 33, k_motifs=3, k_discords=3)
     compare.check_full(x, 25, g, r, TOL64)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_four_diagonals_per_lane(oracle_mod, monkeypatch, precision):
+    """The pass with K = 4 diagonals per lane (bands of 256) gives the same exact
+    results as the default K = 8."""
+    from oracle import compare
+
+    monkeypatch.setenv("VALMOD_PASS_K", "4")
+    monkeypatch.setenv("VALMOD_PASS_K32", "4")
+    x = gen.small_random_walk(2300, 75, np.float32)
+    _say(f"K=4 {precision}")
+    g = run_gpu(x, 28, 36, p=5, k_motifs=3, k_discords=3, path="full", precision=precision)
+    r = oracle_mod.valmod(x, 28, 36, k_motifs=3, k_discords=3)
+    compare.check_full(x, 28, g, r, TOL64)
