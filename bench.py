@@ -121,12 +121,14 @@ def main():
                           excl_den=w.excl_den, precision=precision, path=args.path)
         for _ in range(args.warmup):
             v.run()
+            print(f"bench: {precision} warm-up step done", file=sys.stderr, flush=True)
         torch.cuda.synchronize(dev)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             v.run()
         torch.cuda.synchronize(dev)
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        print(f"bench: {precision} {ms:.1f} ms per step", file=sys.stderr, flush=True)
         timing = v.pass_timing()
         res = v.result(0)
         v.close()

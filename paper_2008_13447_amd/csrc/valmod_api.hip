@@ -6,6 +6,7 @@
 
 #include <math.h>
 #include <new>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #include <vector>
@@ -390,6 +391,9 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
     const int D = p < 15 ? p : 15;
     const double margin = 1.0e-11;  // pass rounding of the FP64 correlation
     const double rec_factor = env_int("VALMOD_RECOMPUTE_FACTOR_X100", 80) / 100.0;
+    // VALMOD_PROGRESS=k: one line on stderr every k lengths (the line is written
+    // when the length is enqueued; the sweep's host reads keep it close to the GPU)
+    const int progress = env_int("VALMOD_PROGRESS", 0);
     unsigned long long* hcnt = host_cnt.data();
     auto read_counters = [&]() -> hipError_t {
       hipError_t e1 = hipMemcpyAsync(hcnt, cnt, CNT_WORDS * 8, hipMemcpyDeviceToHost, st);
@@ -576,6 +580,12 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
         VCHECK(launch_fill_tail(N, N0, pd, pi, st));
         VCHECK(launch_record_stats(cnt, o->stats ? o->stats + Ls.stats + t * VALMOD_NSTATS : nullptr, full ? 1 : 0,
                                    nvalid, nswept_fail, recompute ? 1 : 0, passes, st));
+        if (progress > 0 && (t % progress == 0 || L == Ls.l_max)) {
+          VCHECK(hipStreamSynchronize(st));
+          fprintf(stderr, "valmod: series %d length %d (%lld of %lld) done, heaps %s\n", s, L, (long long)t + 1,
+                  (long long)Ls.nlen, heaps_on ? "on" : "off");
+          fflush(stderr);
+        }
       }
       VCHECK(launch_rankings(o->prof_dist + Ls.prof, o->prof_idx + Ls.prof, N0, n, Ls.l_min, (int)Ls.nlen,
                              excl_den, km, kd, o->motif_ab + 2 * Ls.motif, o->motif_d + Ls.motif,

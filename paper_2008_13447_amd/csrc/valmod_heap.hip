@@ -438,7 +438,7 @@ hipError_t launch_merge(const double* xs, const double* A, const double* invn, c
   k_merge_small<<<blocks_for(N, kWave / kSmallG), kWave, 0, st>>>(xs, A, invn, sig, flat, thr, cnt, buf, cap, N, L, p,
                                                                    keep, margin, best_exact, hc, hS, hn, hbound, hsig,
                                                                    best, fail, nfail, big, nbig);
-  k_merge_big<<<(unsigned)(N < 2048 ? N : 2048), kWave, (size_t)cap * 3 * sizeof(double), st>>>(
+  k_merge_big<<<(unsigned)(N < 65536 ? N : 65536), kWave, (size_t)cap * 3 * sizeof(double), st>>>(
       xs, A, invn, sig, thr, cnt, buf, cap, L, p, keep, margin, hc, hS, hn, hbound, hsig, best, big, nbig);
   k_sum_counts<<<64, 1024, 0, st>>>(cnt, N, nappend);
   return hipGetLastError();

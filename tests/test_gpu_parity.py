@@ -321,3 +321,79 @@ def test_four_diagonals_per_lane(oracle_mod, monkeypatch, precision):
     g = run_gpu(x, 28, 36, p=5, k_motifs=3, k_discords=3, path="full", precision=precision)
     r = oracle_mod.valmod(x, 28, 36, k_motifs=3, k_discords=3)
     compare.check_full(x, 28, g, r, TOL64)
+
+
+def _check_reported_pairs(x, g, l_min, tol, lengths):
+    """Oracle distances of the reported motif pairs and discord neighbours at the
+    given lengths (statistics formed once per length)."""
+    import oracle
+
+    for L in lengths:
+        t = L - l_min
+        pairs, got = [], []
+        for (a, b), d in zip(g["motif_ab"][t], g["motif_d"][t]):
+            if a >= 0:
+                pairs.append((a, b))
+                got.append(d)
+        for (o, nn), d in zip(g["discord_on"][t], g["discord_d"][t]):
+            if o >= 0 and nn >= 0:
+                pairs.append((o, nn))
+                got.append(d)
+        if pairs:
+            ref = oracle.pair_dists(x, L, pairs)
+            err = np.abs(ref - np.asarray(got)) / np.sqrt(L)
+            assert (err <= tol).all(), (L, pairs, ref, got)
+
+
+def test_config3_sensor_fp32_sampled_parity(oracle_mod):
+    """n = 2^20 sensor-like series, lengths 256..384, p = 20, top-10, FP32 path:
+    sampled owners at three lengths (plus every reported motif and discord
+    endpoint) against the oracle, reported pairs re-evaluated."""
+    from oracle import compare
+
+    w = gen.config3()
+    _say(f"config3 n={w.n} L={w.l_min}..{w.l_max} fp32")
+    g = run_gpu(w.x, w.l_min, w.l_max, p=w.p, k_motifs=w.k_motifs, k_discords=w.k_discords, precision="fp32")
+    _say(f"config3 GPU done, stats sums {g['stats'].sum(axis=0).tolist()}")
+    t = 320 - w.l_min
+    extra = [int(v) for v in np.concatenate([g["motif_ab"][t].ravel(), g["discord_on"][t][:, 0]]) if v >= 0]
+    rep = compare.check_sampled(w.x, w.l_min, g, [256, 320, 384], 48, TOL64, extra=extra)
+    _say(f"config3 sampled report {dict(rep)}")
+    _check_reported_pairs(w.x, g, w.l_min, TOL64, [256, 320, 384])
+
+
+def test_config5_offset_flats_precision_stress(oracle_mod):
+    """n = 2^21, offset 1e4, 20 flat stretches, planted pairs of length 300, at
+    lengths 200..212: both precisions agree to the FP64 tolerance, sampled
+    owners match the oracle, flat windows are +inf / -1."""
+    from oracle import compare
+
+    w = gen.config5()
+    lo, hi = 200, 212
+    _say(f"config5 n={w.n} L={lo}..{hi}")
+    g32 = run_gpu(w.x, lo, hi, p=w.p, k_motifs=w.k_motifs, k_discords=w.k_discords, precision="fp32")
+    _say("config5 fp32 done")
+    g64 = run_gpu(w.x, lo, hi, p=w.p, k_motifs=w.k_motifs, k_discords=w.k_discords, precision="fp64")
+    _say("config5 fp64 done")
+    # both paths are exact: distances agree to the FP64 tolerance; an index may
+    # differ only where two candidates tie within it
+    sq = np.sqrt(np.arange(lo, hi + 1))[:, None]
+    a, b = g32["prof_dist"] / sq, g64["prof_dist"] / sq
+    assert np.array_equal(np.isinf(a), np.isinf(b))
+    fin = np.isfinite(a)
+    dmax = float(np.max(np.abs(a[fin] - b[fin])))
+    _say(f"config5 fp32 vs fp64: max |d/sqrt(L) diff| {dmax:.3g}, "
+         f"{int(np.sum(g32['prof_idx'] != g64['prof_idx']))} index differences")
+    assert dmax <= TOL64
+    extra = [a for (a, b, _) in w.planted_motifs] + [b for (a, b, _) in w.planted_motifs]
+    extra += [s + 10 for s, ln in w.flats]
+    rep = compare.check_sampled(w.x, lo, g32, [200, 212], 48, TOL64, extra=extra)
+    _say(f"config5 sampled report {dict(rep)}")
+    for s, ln in w.flats:
+        if ln > hi + 2:
+            assert np.isinf(g32["prof_dist"][0, s + 1:s + ln - hi]).all()
+            assert (g32["prof_idx"][0, s + 1:s + ln - hi] == -1).all()
+    e = -(-lo // 4)
+    for a, b, _ in w.planted_motifs:
+        assert abs(int(g32["prof_idx"][0, a]) - b) <= e
+    _check_reported_pairs(w.x, g32, lo, TOL64, [lo, hi])
