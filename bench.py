@@ -81,7 +81,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 5])
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
+                    help="workload; 4 is the batched one (--batch-count series in one plan)")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--lanes", type=int, default=0, help="series run concurrently (0: library default)")
+    ap.add_argument("--graph", action="store_true", help="capture the run in a HIP graph and replay it")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"],
                     help="headline path (the other one is timed beside it unless --no-compare)")
     ap.add_argument("--no-compare", action="store_true")
@@ -111,14 +115,27 @@ def main():
         print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes}))
         return
 
-    w = gen.WORKLOADS[args.config]()
     dev = torch.device("cuda:0")
-    x = torch.from_numpy(np.ascontiguousarray(w.x)).to(dev)
-    cells = cells_total(w.n, w.l_min, w.l_max)
+    if args.config == 4:
+        batch = gen.config4(args.batch_count)
+        w = batch[0]
+        x = [torch.from_numpy(np.ascontiguousarray(b.x)).to(dev) for b in batch]
+        lo, hi = [b.l_min for b in batch], [b.l_max for b in batch]
+        cells = sum(cells_total(b.n, b.l_min, b.l_max) for b in batch)
+        name = f"batched{args.batch_count}_rw_n4096-131072_lmin32-256"
+    else:
+        batch = None
+        w = gen.WORKLOADS[args.config]()
+        x = torch.from_numpy(np.ascontiguousarray(w.x)).to(dev)
+        lo, hi = w.l_min, w.l_max
+        cells = cells_total(w.n, w.l_min, w.l_max)
+        name = w.name
 
     def timed(precision):
-        v = native.Valmod(x, w.l_min, w.l_max, p=w.p, k_motifs=w.k_motifs, k_discords=w.k_discords,
-                          excl_den=w.excl_den, precision=precision, path=args.path)
+        graph = args.graph and precision == "fp64"
+        v = native.Valmod(x, lo, hi, p=w.p, k_motifs=w.k_motifs, k_discords=w.k_discords,
+                          excl_den=w.excl_den, precision=precision, path="full" if graph else args.path,
+                          lanes=args.lanes, graph=graph)
         for _ in range(args.warmup):
             v.run()
             print(f"bench: {precision} warm-up step done", file=sys.stderr, flush=True)
@@ -143,8 +160,10 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "n": w.n, "l_min": w.l_min, "l_max": w.l_max, "p": w.p,
-                   "k": w.k_motifs, "precision": args.precision, "path": args.path},
+        "config": {"workload": name, "n": w.n if batch is None else sum(b.n for b in batch),
+                   "l_min": lo if batch is None else min(lo), "l_max": hi if batch is None else max(hi),
+                   "p": w.p, "k": w.k_motifs, "precision": args.precision, "path": args.path,
+                   "lanes": args.lanes, "graph": bool(args.graph and args.precision == "fp64")},
         "roofline": {"bound": "alu", "kernel": f"k_pass<{'double' if args.precision == 'fp64' else 'float'}> "
                      "(diagonal pass)", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": profiled_traffic(args.precision),
@@ -154,7 +173,7 @@ def main():
     st = res["stats"].sum(axis=0)
     out["diagnostics"] = {name: int(st[c]) for c, name in enumerate(native.STAT_NAMES)}
     if not args.no_compare:
-        # the other precision on the same input: throughput and output agreement
+        # the other precision on the same input: throughput and output agreement (first series)
         other = "fp64" if args.precision == "fp32" else "fp32"
         ms2, _, res2 = timed(other)
         L = np.arange(w.l_min, w.l_max + 1)[:, None]
@@ -166,7 +185,7 @@ def main():
             "max_abs_dn_diff": float(np.max(np.abs(a[fin] - b[fin]))) if fin.any() else 0.0,
             "idx_diff": int(np.sum(res["prof_idx"] != res2["prof_idx"])),
         }
-    if not args.no_cpu:
+    if not args.no_cpu and batch is None:
         Lc = (w.l_min + w.l_max) // 2  # a length the per-length update computes, not the first one
         t = Lc - w.l_min
         out["cpu_baseline"] = cpu_baseline(w.x, Lc, w.excl_den, res["prof_dist"][t], res["prof_idx"][t],

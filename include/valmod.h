@@ -29,8 +29,10 @@
  *   candidates (distance +inf, index -1); ties go to the smaller index.
  *
  * Memory ownership: the caller owns every device buffer (input series,
- * workspace, outputs); the plan owns host metadata only. No function of this
- * library allocates device memory. Return values are valmod_status codes; no
+ * workspace, outputs); the plan owns host metadata and, from its first
+ * valmod_run, per-lane HIP streams and events, a few bytes of pinned host
+ * memory per lane and (graph mode) the instantiated graph, all released by
+ * valmod_plan_free. No function of this library allocates device memory. Return values are valmod_status codes; no
  * exception crosses the ABI. Argument errors are reported synchronously by
  * valmod_plan / valmod_run; errors found on the device (non-finite input,
  * internal capacity exceeded and not recoverable) are reported by valmod_run
@@ -102,6 +104,11 @@ typedef struct {
                                of 16 in [64, 8192]; the rounding bound grows linearly with R */
   int32_t path;             /* valmod_path */
   int32_t device;           /* HIP device ordinal the plan runs on */
+  int32_t lanes;            /* series processed concurrently (streams), 0 = default min(num_series, 4),
+                               at most 64; each lane has its own workspace slice */
+  int32_t graph;            /* 1: capture the whole run in a HIP graph on the first call and replay it on
+                               later calls with the same buffers and stream; implies VALMOD_PATH_FULL
+                               (VALMOD_PATH_RECOMPUTE is rejected); FP64 precision only */
 } valmod_config;
 
 typedef struct valmod_plan_s* valmod_plan_t;
@@ -178,9 +185,13 @@ typedef struct {
   int32_t l_min, l_max;
 } valmod_layout;
 
-/* Validate a configuration and build a plan (host only; touches no GPU).
+/* Validate a configuration and build a plan (host only; touches no GPU). The
+ * series are assigned to `lanes` by longest processing time first on the sum
+ * over lengths of N_L^2; each lane runs its series one after another.
  * Errors: VALMOD_E_ARG (null pointers, num_series < 1, l_min < 4, l_max < l_min,
- * p < 0, k < 1, excl_den < 0, flat_eps < 0, unknown enum), VALMOD_E_TOO_SHORT
+ * p < 0, k < 1, excl_den < 0, flat_eps < 0, unknown enum, lanes outside
+ * [0, 64], graph not 0/1, graph with VALMOD_PATH_RECOMPUTE or with
+ * VALMOD_PREC_FP32_REFRESH), VALMOD_E_TOO_SHORT
  * (n - l_max + 1 <= ceil(l_max / excl_den) + 1: no non-trivial pair),
  * VALMOD_E_LAYOUT (more than VALMOD_MAX_WINDOWS windows), VALMOD_E_NOMEM. */
 VALMOD_API valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* out);
@@ -200,10 +211,15 @@ VALMOD_API valmod_status valmod_series_layout(valmod_plan_t plan, int32_t s, val
  * d_workspace: device buffer of valmod_workspace_bytes(plan) bytes, 256-byte
  * aligned, contents irrelevant on entry. d_out: struct (host memory) of device
  * pointers. stream: a hipStream_t (passed as void*; NULL = default stream).
- * The call enqueues work on `stream` and synchronises with it before returning
- * (per-length decisions read device counters), so all outputs are complete on
- * return. Errors: VALMOD_E_ARG (null plan/series/workspace/out), VALMOD_E_HIP,
- * VALMOD_E_DEVICE (non-finite input values).
+ * The lanes' streams start after the work already on `stream` and `stream`
+ * waits for all of them; the call synchronises with `stream` before returning
+ * (per-length decisions of the partial-profile path read device counters), so
+ * all outputs are complete on return. In graph mode the first call captures
+ * the run (lanes included) into a HIP graph and launches it; later calls with
+ * the same d_series, d_workspace, output pointers and stream replay it. One plan
+ * must not be used by two calls at the same time. Errors: VALMOD_E_ARG (null
+ * plan/series/workspace/out), VALMOD_E_HIP, VALMOD_E_DEVICE (non-finite input
+ * values).
  */
 VALMOD_API valmod_status valmod_run(valmod_plan_t plan, const void* d_series, void* d_workspace,
                          const valmod_outputs* d_out, void* stream);
@@ -217,8 +233,9 @@ VALMOD_API const char* valmod_status_str(int status);
 /* Milliseconds spent in the diagonal-pass kernel of the plan's precision during
  * the last valmod_run (full-grid launches only: FP64 mode, every pass; FP32
  * mode, the FP32 collecting passes, not the FP64 pass of the first length nor
- * the FP64 re-runs of listed work items), measured with HIP events on the run's
- * stream, and the number of those launches and of the cells they covered. */
+ * the FP64 re-runs of listed work items), measured with HIP events on the
+ * lanes' streams, and the number of those launches and of the cells they
+ * covered. In graph mode: the time of the whole replay, as one launch. */
 VALMOD_API valmod_status valmod_last_pass_timing(valmod_plan_t plan, double* ms, int64_t* launches,
                                       int64_t* cells);
 

@@ -4,6 +4,7 @@
 #include "valmod_common.h"
 #include "valmod_kernels.h"
 
+#include <algorithm>
 #include <math.h>
 #include <new>
 #include <stdio.h>
@@ -78,24 +79,41 @@ PassGeom pass_geom(int64_t n, int32_t l_min, int32_t excl_den, bool fp32, int32_
 
 }  // namespace
 
+// A lane runs its series one after another on its own stream (and a second
+// stream for the FP64 re-run of listed FP32 work items); lanes run concurrently.
+struct Lane {
+  std::vector<int> series;  // assigned series, in run order
+  size_t base = 0;          // byte offset of the lane's workspace
+  WsLayout ws;              // offsets relative to base
+  int64_t nmax = 0, n0max = 0, ancmax = 0, itemmax = 0, total_lengths = 0;
+  double cost = 0.0;
+  // device resources (created on the plan's device at the first run)
+  hipStream_t st = nullptr, aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, ready = nullptr, done = nullptr;
+  unsigned long long* hcnt = nullptr;  // pinned host copy of a few counters
+  std::vector<hipEvent_t> ev;         // pass timing
+  int64_t nev = 0;                     // events recorded by the last run
+};
+
 struct valmod_plan_s {
   valmod_config cfg;
   std::vector<int64_t> n;
   std::vector<int32_t> lmin, lmax;
   std::vector<valmod_layout> lay;
   valmod_sizes sizes;
-  int64_t nmax = 0, n0max = 0, ancmax = 0;
   int64_t cap = 0;  // candidate-list capacity per owner of the collecting pass
-  int64_t itemmax = 0;  // work items of the largest pass grid
   std::vector<PassGeom> geom;
-  WsLayout ws;
-  // timing of the diagonal pass during the last run
-  std::vector<hipEvent_t> ev;
-  int ev_device = -1;
-  // second stream (default priority) for the FP64 re-run of listed FP32 work
-  // items, overlapped with the FP32 pass; fork/join events
-  hipStream_t aux = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  std::vector<Lane> lanes;
+  size_t ws_total = 0;
+  int res_device = -1;
+  hipEvent_t start = nullptr, g0 = nullptr, g1 = nullptr;
+  // captured run (graph mode), valid for one set of buffers and one stream
+  hipGraphExec_t exec = nullptr;
+  const void* key_series = nullptr;
+  void* key_ws = nullptr;
+  hipStream_t key_stream = nullptr;
+  valmod_outputs key_out;
+  int64_t graph_cells = 0;
   double pass_ms = 0.0;
   int64_t pass_launches = 0, pass_cells = 0;
 };
@@ -115,6 +133,58 @@ extern "C" const char* valmod_status_str(int status) {
   }
 }
 
+// workspace of one lane, sized for the largest of its series
+static size_t layout_lane(const valmod_plan_s* P, Lane& ln) {
+  WsLayout& w = ln.ws;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  const size_t np = (size_t)(ln.nmax + kPad);
+  const size_t wp = (size_t)(ln.n0max + kPad);
+  w.xs = take(np * 8);
+  w.A = take(wp * 8);
+  w.B = take(wp * 8);
+  w.mu = take(wp * 8);
+  w.sig = take(wp * 8);
+  w.invn = take(wp * 8);
+  w.flat = take(wp);
+  w.df = take(wp * 8);
+  w.dg = take(wp * 8);
+  w.sw32 = take(wp * 4);
+  w.thr = take(wp * 8);
+  w.thr32 = take(wp * 4);
+  w.best = take(wp * 8);
+  w.counters = take(CNT_WORDS * 8);
+  w.anc = take((size_t)ln.ancmax * 8);
+  const size_t pp = (size_t)P->cfg.p;
+  w.hc = take(wp * pp * 4);
+  w.hS = take(wp * pp * 8);
+  w.hn = take(wp * 4);
+  w.hbound = take(wp * 8);
+  w.hsig = take(wp * 8);
+  w.acnt = take(wp * 4);
+  w.abuf = take((size_t)ln.n0max * (size_t)P->cap * 4);
+  w.fail = take(wp * 4);
+  w.big = take(wp * 4);
+  if (P->cfg.precision == VALMOD_PREC_FP32_REFRESH) {
+    w.df32 = take(wp * 4);
+    w.dg32 = take(wp * 4);
+    w.inv32 = take(wp * 4);
+    const size_t nb = wp / 64 + 2;
+    w.bsw_max = take(nb * 4);
+    w.bsw_min = take(nb * 4);
+    w.bdf_max = take(nb * 4);
+    w.bdg_max = take(nb * 4);
+    w.delta = take((size_t)ln.itemmax * 4);
+    w.hard = take((size_t)ln.itemmax * 4);
+  }
+  w.total = off;
+  return off;
+}
+
 extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* out) {
   if (!cfg || !out) return fail(VALMOD_E_ARG);
   *out = nullptr;
@@ -129,6 +199,11 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
     return fail(VALMOD_E_ARG);
   if (cfg->path < VALMOD_PATH_AUTO || cfg->path > VALMOD_PATH_RECOMPUTE || cfg->device < 0)
     return fail(VALMOD_E_ARG);
+  if (cfg->lanes < 0 || cfg->lanes > 64 || (cfg->graph != 0 && cfg->graph != 1)) return fail(VALMOD_E_ARG);
+  // a captured run takes no host decisions: partial profiles (which need them) are off
+  if (cfg->graph && cfg->path == VALMOD_PATH_RECOMPUTE) return fail(VALMOD_E_ARG);
+  // capture of the FP32 path (second stream per lane, collecting pass and merge) is not supported
+  if (cfg->graph && cfg->precision == VALMOD_PREC_FP32_REFRESH) return fail(VALMOD_E_ARG);
 
   valmod_plan_s* P = new (std::nothrow) valmod_plan_s();
   if (!P) return fail(VALMOD_E_NOMEM);
@@ -136,6 +211,7 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
   if (P->cfg.p == 0) P->cfg.p = 10;
   if (P->cfg.excl_den == 0) P->cfg.excl_den = 4;
   if (P->cfg.flat_eps == 0.0) P->cfg.flat_eps = 1.0 / 1048576.0;
+  if (P->cfg.graph) P->cfg.path = VALMOD_PATH_FULL;
   const int S = cfg->num_series;
   try {
     P->n.assign(cfg->n, cfg->n + S);
@@ -153,6 +229,7 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
   valmod_sizes& z = P->sizes;
   memset(&z, 0, sizeof(z));
   const int64_t km = P->cfg.k_motifs, kd = P->cfg.k_discords;
+  std::vector<double> cost(S, 0.0);
   for (int s = 0; s < S; ++s) {
     const int64_t n = P->n[s];
     const int32_t lo = P->lmin[s], hi = P->lmax[s];
@@ -193,70 +270,52 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
     z.g_motif += km;
     z.g_discord += kd;
     z.stats += nlen * VALMOD_NSTATS;
-    if (n > P->nmax) P->nmax = n;
-    if (n0 > P->n0max) P->n0max = n0;
     P->geom.push_back(pass_geom(n, lo, P->cfg.excl_den, P->cfg.precision == VALMOD_PREC_FP32_REFRESH,
-                               P->cfg.refresh_R));
-    const PassGeom& gg = P->geom.back();
-    const int64_t anc = gg.table ? gg.segs * gg.stride : 0;
-    if (anc > P->ancmax) P->ancmax = anc;
-    if (gg.segs * gg.bands > P->itemmax) P->itemmax = gg.segs * gg.bands;
+                                P->cfg.refresh_R));
+    for (int64_t Lx = lo; Lx <= hi; ++Lx) cost[s] += (double)(n - Lx + 1) * (double)(n - Lx + 1);
   }
-
-  // workspace carve-up (sized for the largest series; series run one after another)
-  WsLayout& w = P->ws;
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    size_t o = off;
-    off += align_up(bytes);
-    return o;
-  };
-  const size_t np = (size_t)(P->nmax + kPad);
-  const size_t wp = (size_t)(P->n0max + kPad);
-  w.xs = take(np * 8);
-  w.A = take(wp * 8);
-  w.B = take(wp * 8);
-  w.mu = take(wp * 8);
-  w.sig = take(wp * 8);
-  w.invn = take(wp * 8);
-  w.flat = take(wp);
-  w.df = take(wp * 8);
-  w.dg = take(wp * 8);
-  w.sw32 = take(wp * 4);
-  w.thr = take(wp * 8);
-  w.thr32 = take(wp * 4);
-  w.best = take(wp * 8);
-  w.counters = take(CNT_WORDS * 8);
-  w.anc = take((size_t)P->ancmax * 8);
   const size_t pp = (size_t)P->cfg.p;
   P->cap = 8 * (int64_t)pp < 64 ? 64 : (8 * (int64_t)pp > 512 ? 512 : 8 * (int64_t)pp);
-  w.hc = take(wp * pp * 4);
-  w.hS = take(wp * pp * 8);
-  w.hn = take(wp * 4);
-  w.hbound = take(wp * 8);
-  w.hsig = take(wp * 8);
-  w.acnt = take(wp * 4);
-  w.abuf = take((size_t)P->n0max * (size_t)P->cap * 4);
-  w.fail = take(wp * 4);
-  w.big = take(wp * 4);
-  if (P->cfg.precision == VALMOD_PREC_FP32_REFRESH) {
-    w.df32 = take(wp * 4);
-    w.dg32 = take(wp * 4);
-    w.inv32 = take(wp * 4);
-    const size_t nb = wp / 64 + 2;
-    w.bsw_max = take(nb * 4);
-    w.bsw_min = take(nb * 4);
-    w.bdf_max = take(nb * 4);
-    w.bdg_max = take(nb * 4);
-    w.delta = take((size_t)P->itemmax * 4);
-    w.hard = take((size_t)P->itemmax * 4);
+
+  // lanes: longest-processing-time assignment of the series by sum over lengths of N_L^2
+  const int nl = std::min(S, P->cfg.lanes > 0 ? (int)P->cfg.lanes : 4);
+  try {
+    P->lanes.resize(nl);
+    std::vector<int> order(S);
+    for (int s = 0; s < S; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    for (int s : order) {
+      int best_lane = 0;
+      for (int l = 1; l < nl; ++l)
+        if (P->lanes[l].cost < P->lanes[best_lane].cost) best_lane = l;
+      Lane& ln = P->lanes[best_lane];
+      ln.cost += cost[s];
+      ln.series.push_back(s);
+    }
+  } catch (...) {
+    delete P;
+    return fail(VALMOD_E_NOMEM);
   }
-  w.total = off;
+  size_t off = 0;
+  for (Lane& ln : P->lanes) {
+    std::sort(ln.series.begin(), ln.series.end());
+    for (int s : ln.series) {
+      const PassGeom& gg = P->geom[s];
+      ln.nmax = std::max(ln.nmax, P->n[s]);
+      ln.n0max = std::max(ln.n0max, P->lay[s].n0);
+      if (gg.table) ln.ancmax = std::max(ln.ancmax, gg.segs * gg.stride);
+      ln.itemmax = std::max(ln.itemmax, gg.segs * gg.bands);
+      ln.total_lengths += P->lay[s].nlen;
+    }
+    ln.base = off;
+    off += align_up(layout_lane(P, ln));
+  }
+  P->ws_total = off;
   *out = P;
   return VALMOD_OK;
 }
 
-extern "C" size_t valmod_workspace_bytes(valmod_plan_t P) { return P ? P->ws.total : 0; }
+extern "C" size_t valmod_workspace_bytes(valmod_plan_t P) { return P ? P->ws_total : 0; }
 
 extern "C" valmod_status valmod_output_sizes(valmod_plan_t P, valmod_sizes* out) {
   if (!P || !out) return VALMOD_E_ARG;
@@ -270,12 +329,37 @@ extern "C" valmod_status valmod_series_layout(valmod_plan_t P, int32_t s, valmod
   return VALMOD_OK;
 }
 
+static void release_resources(valmod_plan_s* P) {
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  P->exec = nullptr;
+  for (Lane& ln : P->lanes) {
+    for (hipEvent_t e : ln.ev) (void)hipEventDestroy(e);
+    ln.ev.clear();
+    for (hipEvent_t* e : {&ln.fork, &ln.join, &ln.ready, &ln.done})
+      if (*e) {
+        (void)hipEventDestroy(*e);
+        *e = nullptr;
+      }
+    if (ln.st) (void)hipStreamDestroy(ln.st);
+    if (ln.aux) (void)hipStreamDestroy(ln.aux);
+    ln.st = ln.aux = nullptr;
+    if (ln.hcnt) (void)hipHostFree(ln.hcnt);
+    ln.hcnt = nullptr;
+  }
+  for (hipEvent_t* e : {&P->start, &P->g0, &P->g1})
+    if (*e) {
+      (void)hipEventDestroy(*e);
+      *e = nullptr;
+    }
+  P->res_device = -1;
+}
+
 extern "C" void valmod_plan_free(valmod_plan_t P) {
   if (!P) return;
-  for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
-  if (P->fork) (void)hipEventDestroy(P->fork);
-  if (P->join) (void)hipEventDestroy(P->join);
-  if (P->aux) (void)hipStreamDestroy(P->aux);
+  int prev = -1;
+  const bool sw = P->res_device >= 0 && hipGetDevice(&prev) == hipSuccess && hipSetDevice(P->res_device) == hipSuccess;
+  release_resources(P);
+  if (sw) (void)hipSetDevice(prev);
   delete P;
 }
 
@@ -288,14 +372,411 @@ extern "C" valmod_status valmod_last_pass_timing(valmod_plan_t P, double* ms, in
   return VALMOD_OK;
 }
 
-#define VCHECK(expr)                   \
-  do {                                 \
-    hipError_t _e = (expr);            \
-    if (_e != hipSuccess) {            \
-      status = VALMOD_E_HIP;           \
-      goto done;                       \
-    }                                  \
+// streams (default priority), events and pinned counters of every lane
+static hipError_t ensure_resources(valmod_plan_s* P) {
+  if (P->res_device == P->cfg.device) return hipSuccess;
+  release_resources(P);
+  hipError_t e = hipSuccess;
+  auto ok = [&](hipError_t r) {
+    if (e == hipSuccess && r != hipSuccess) e = r;
+    return e == hipSuccess;
+  };
+  ok(hipEventCreateWithFlags(&P->start, hipEventDisableTiming));
+  ok(hipEventCreate(&P->g0));
+  ok(hipEventCreate(&P->g1));
+  for (Lane& ln : P->lanes) {
+    ok(hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking));
+    ok(hipStreamCreateWithFlags(&ln.aux, hipStreamNonBlocking));
+    for (hipEvent_t* ev : {&ln.fork, &ln.join, &ln.ready, &ln.done}) ok(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+    ok(hipHostMalloc((void**)&ln.hcnt, 8 * sizeof(unsigned long long), hipHostMallocDefault));
+    for (int64_t i = 0; e == hipSuccess && i < 4 * ln.total_lengths; ++i) {
+      hipEvent_t ev;
+      if (ok(hipEventCreate(&ev))) ln.ev.push_back(ev);
+    }
+  }
+  if (e == hipSuccess) P->res_device = P->cfg.device;
+  return e;
+}
+
+namespace {
+
+// The per-length driver of one lane (Alg. VALMOD over each of its series).
+// advance() enqueues the work of one length and returns; a length whose
+// partial-profile sweep needs its counters on the host first returns BLOCKED
+// after enqueueing the sweep and the counter copy, and continues once the
+// lane's `ready` event has completed.
+struct LaneRun {
+  enum Status { CONTINUE, BLOCKED, DONE };
+  valmod_plan_s* P = nullptr;
+  Lane* ln = nullptr;
+  const valmod_outputs* o = nullptr;
+  const char* d_series = nullptr;
+  bool capture = false;
+  hipError_t err = hipSuccess;
+  // workspace
+  double *xs, *A, *B, *mu, *sig, *invn, *df, *dg, *thr, *anc, *hS, *hbound, *hsig;
+  uint8_t* flat;
+  float *sw32, *thr32, *df32, *dg32, *inv32, *bsw_max, *bsw_min, *bdf_max, *bdg_max, *delta;
+  uint64_t* best;
+  unsigned long long* cnt;
+  int32_t *hc, *hn, *abuf, *fail, *big, *hard;
+  uint32_t* acnt;
+  // state
+  size_t si = 0;
+  bool open = false;
+  int L = 0, phase = 0, base = 0;
+  bool heaps_on = false, probe_next = false;
+  int64_t evi = 0;
+
+  void init(valmod_plan_s* P_, Lane* ln_, char* ws, const valmod_outputs* o_, const char* series, bool cap) {
+    P = P_;
+    ln = ln_;
+    o = o_;
+    d_series = series;
+    capture = cap;
+    char* b = ws + ln->base;
+    const WsLayout& w = ln->ws;
+    xs = (double*)(b + w.xs);
+    A = (double*)(b + w.A);
+    B = (double*)(b + w.B);
+    mu = (double*)(b + w.mu);
+    sig = (double*)(b + w.sig);
+    invn = (double*)(b + w.invn);
+    flat = (uint8_t*)(b + w.flat);
+    df = (double*)(b + w.df);
+    dg = (double*)(b + w.dg);
+    sw32 = (float*)(b + w.sw32);
+    thr = (double*)(b + w.thr);
+    thr32 = (float*)(b + w.thr32);
+    anc = (double*)(b + w.anc);
+    best = (uint64_t*)(b + w.best);
+    cnt = (unsigned long long*)(b + w.counters);
+    hc = (int32_t*)(b + w.hc);
+    hS = (double*)(b + w.hS);
+    hn = (int32_t*)(b + w.hn);
+    hbound = (double*)(b + w.hbound);
+    hsig = (double*)(b + w.hsig);
+    acnt = (uint32_t*)(b + w.acnt);
+    abuf = (int32_t*)(b + w.abuf);
+    fail = (int32_t*)(b + w.fail);
+    big = (int32_t*)(b + w.big);
+    const bool fp32 = P->cfg.precision == VALMOD_PREC_FP32_REFRESH;
+    df32 = fp32 ? (float*)(b + w.df32) : nullptr;
+    dg32 = fp32 ? (float*)(b + w.dg32) : nullptr;
+    inv32 = fp32 ? (float*)(b + w.inv32) : nullptr;
+    bsw_max = fp32 ? (float*)(b + w.bsw_max) : nullptr;
+    bsw_min = fp32 ? (float*)(b + w.bsw_min) : nullptr;
+    bdf_max = fp32 ? (float*)(b + w.bdf_max) : nullptr;
+    bdg_max = fp32 ? (float*)(b + w.bdg_max) : nullptr;
+    delta = fp32 ? (float*)(b + w.delta) : nullptr;
+    hard = fp32 ? (int32_t*)(b + w.hard) : nullptr;
+  }
+
+  bool chk(hipError_t e) {
+    if (err == hipSuccess && e != hipSuccess) err = e;
+    return err == hipSuccess;
+  }
+
+  Status advance();
+};
+
+#define LCHECK(expr)                 \
+  do {                               \
+    if (!chk(expr)) return DONE;     \
   } while (0)
+
+LaneRun::Status LaneRun::advance() {
+  if (err != hipSuccess || si >= ln->series.size()) return DONE;
+  hipStream_t st = ln->st;
+  const int s = ln->series[si];
+  const valmod_layout& Ls = P->lay[s];
+  const PassGeom& G = P->geom[s];
+  const int64_t n = Ls.n, N0 = Ls.n0;
+  const int esz = P->cfg.dtype == VALMOD_F32 ? 4 : 8;
+  const int excl_den = P->cfg.excl_den;
+  const bool fp32 = P->cfg.precision == VALMOD_PREC_FP32_REFRESH;
+  double* vnorm = o->valmp_norm + Ls.valmp;
+  double* vdist = o->valmp_dist + Ls.valmp;
+  int32_t* vlen = o->valmp_len + Ls.valmp;
+  int32_t* vidx = o->valmp_idx + Ls.valmp;
+  if (!open) {
+    const char* series = d_series + (size_t)Ls.series * esz;
+    LCHECK(launch_convert(series, P->cfg.dtype, n, n + kPad, xs, (int*)&cnt[CNT_ERR], st));
+    LCHECK(launch_valmp_init(N0, vnorm, vdist, vlen, vidx, st));
+    // partial profiles are used unless every length is forced through a full pass
+    heaps_on = P->cfg.path != VALMOD_PATH_FULL && Ls.l_max > Ls.l_min;
+    base = 0;            // base length of the current partial profiles (0: none)
+    probe_next = false;  // judge the partial profiles at the first length after a rebuild
+    L = Ls.l_min;
+    phase = 0;
+    open = true;
+  }
+  // FP32 work items whose rounding bound exceeds this go to the FP64 kernel
+  const float delta_max = (float)(env_int("VALMOD_FP32_DELTA_MAX_E6", 5000) * 1.0e-6);
+  const int p = P->cfg.p;
+  const int D = p < 15 ? p : 15;
+  const double margin = 1.0e-11;  // pass rounding of the FP64 correlation
+  const double rec_factor = env_int("VALMOD_RECOMPUTE_FACTOR_X100", 80) / 100.0;
+  const int64_t t = L - Ls.l_min;
+  const int64_t N = n - L + 1;
+  const int64_t e = excl_zone(L, excl_den);
+  const PassGrid grid = pass_grid(N, e, G.dstart, G.K, G.H);
+  double* pd = o->prof_dist + Ls.prof + t * N0;
+  int32_t* pi = o->prof_idx + Ls.prof + t * N0;
+  const int32_t* prev = L > Ls.l_min ? pi - N0 : nullptr;
+
+  const bool sweep = heaps_on && base > 0 && L > Ls.l_min;
+  if (phase == 0) {
+    LCHECK(launch_stats(xs, N, L, L == Ls.l_min, P->cfg.flat_eps, A, B, mu, sig, invn, flat, &cnt[CNT_NFLAT], st));
+    if (G.table) LCHECK(launch_anchor(xs, n, L, L == Ls.l_min, G.H, G.dstart, G.segs, G.stride, G.stride, anc, st));
+    LCHECK(launch_prep_f64(xs, mu, sig, invn, N, L, df, dg, sw32, st));
+    if (sweep) {
+      // Alg. ComputeSubMP: sweep the partial profiles, certify by the lower bound;
+      // the choice between row recompute and a full pass needs the counts
+      LCHECK(launch_sweep(xs, A, invn, sig, flat, N, L, e, p, base, hc, hS, hn, hbound, hsig, best, fail,
+                          &cnt[CNT_NFAIL], &cnt[CNT_VALID], st));
+      if (capture) {
+        err = hipErrorNotSupported;  // unreachable: a captured plan has no partial profiles
+        return DONE;
+      }
+      LCHECK(hipMemcpyAsync(ln->hcnt, &cnt[CNT_NFAIL], 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+      LCHECK(hipEventRecord(ln->ready, st));
+      phase = 1;
+      return BLOCKED;
+    }
+  }
+
+  PassLaunch pl{};
+  pl.xs = xs;
+  pl.mu = mu;
+  pl.df = df;
+  pl.dg = dg;
+  pl.sw32 = sw32;
+  pl.invn = invn;
+  pl.df32 = df32;
+  pl.dg32 = dg32;
+  pl.inv32 = inv32;
+  pl.thr = thr;
+  pl.thr32 = thr32;
+  pl.best = best;
+  pl.anc = G.table ? anc : nullptr;
+  pl.A = A;
+  pl.anc_stride = G.stride;
+  pl.N = N;
+  pl.e = e;
+  pl.H = G.H;
+  pl.dstart = G.dstart;
+  pl.L = L;
+  pl.K = G.K;
+  pl.events = &cnt[CNT_EV_STEPS];
+  pl.cnt = acnt;
+  pl.buf = abuf;
+  pl.cap = P->cap;
+  int64_t passes = 0;
+  // full-grid launch of the plan's own pass kernel: bracketed by events
+  auto timed_pass = [&](const PassLaunch& q) -> hipError_t {
+    const bool tm = !capture && evi + 2 <= (int64_t)ln->ev.size();
+    hipError_t e1 = tm ? hipEventRecord(ln->ev[evi], st) : hipSuccess;
+    if (e1 == hipSuccess) e1 = launch_pass(q, st);
+    if (e1 == hipSuccess && tm) e1 = hipEventRecord(ln->ev[evi + 1], st);
+    if (tm) evi += 2;
+    P->pass_launches += 1;
+    P->pass_cells += grid.cells;
+    ++passes;
+    return e1;
+  };
+  bool fp32_ready = false;
+  // FP32 inputs and the per-item rounding bounds at this length; items over
+  // the limit are listed for the FP64 kernel
+  auto fp32_setup = [&]() -> hipError_t {
+    if (fp32_ready) return hipSuccess;
+    fp32_ready = true;
+    hipError_t e1 =
+        launch_fp32_prep(sig, invn, df, dg, N, L, df32, dg32, inv32, bsw_max, bsw_min, bdf_max, bdg_max, st);
+    if (e1 == hipSuccess)
+      e1 = launch_fp32_items(bsw_max, bsw_min, bdf_max, bdg_max, N, e, G.dstart, G.K, G.H, delta_max, delta, hard,
+                             &cnt[CNT_HARD], st);
+    return e1;
+  };
+  bool recompute = false;  // process the recompute list (its length is a device counter)
+  // collecting pass above per-owner thresholds from the candidates of `src`,
+  // then the exact merge (top-`keep` partial profiles and best keys)
+  auto collect = [&](const int32_t* src, int p_eff, int keep, int best_exact) -> hipError_t {
+    hipError_t e1 = sweep ? launch_zero_counters(&cnt[CNT_NFAIL], 1, st) : hipSuccess;
+    if (e1 == hipSuccess)
+      e1 = launch_seed_append(xs, A, invn, flat, src, N, L, e, p_eff, p_eff == 1 ? 0 : D, margin, best_exact, thr,
+                              acnt, fail, &cnt[CNT_NFAIL], st);
+    PassLaunch q = pl;
+    q.append = true;
+    if (fp32) {
+      if (e1 == hipSuccess) e1 = fp32_setup();
+      if (e1 == hipSuccess) e1 = launch_thr_to_f32(thr, N + kPad, thr32, st);
+      // listed items run in FP64 on the second stream, beside the FP32 pass
+      PassLaunch h = pl;
+      h.append = true;
+      h.items = hard;
+      h.nitems = grid.segs * grid.bands;
+      h.nitems_dev = &cnt[CNT_HARD];
+      if (e1 == hipSuccess) e1 = hipEventRecord(ln->fork, st);
+      if (e1 == hipSuccess) e1 = hipStreamWaitEvent(ln->aux, ln->fork, 0);
+      if (e1 == hipSuccess) e1 = launch_pass(h, ln->aux);
+      if (e1 == hipSuccess) e1 = hipEventRecord(ln->join, ln->aux);
+      ++passes;
+      q.fp32 = true;
+      q.delta = delta;
+      q.delta_max = delta_max;
+      if (e1 == hipSuccess) e1 = timed_pass(q);
+      if (e1 == hipSuccess) e1 = hipStreamWaitEvent(st, ln->join, 0);
+    } else if (e1 == hipSuccess) {
+      e1 = timed_pass(q);
+    }
+    if (e1 == hipSuccess)
+      e1 = launch_merge(xs, A, invn, sig, flat, thr, acnt, abuf, P->cap, N, L, p, keep, margin, best_exact, hc, hS,
+                        hn, hbound, hsig, best, fail, &cnt[CNT_NFAIL], big, &cnt[CNT_BIG], &cnt[CNT_APPENDS], st);
+    recompute = true;
+    return e1;
+  };
+
+  int64_t nvalid = 0, nswept_fail = 0;
+  bool full = true, rebuild = false;
+  if (L == Ls.l_min) {
+    rebuild = heaps_on;
+  } else if (sweep) {
+    nswept_fail = (int64_t)ln->hcnt[0];
+    nvalid = (int64_t)ln->hcnt[1];
+    // row recompute of the failing windows vs one full pass (cost model in FMA-equivalents)
+    const double cells = 0.5 * (double)N * (double)N;
+    const bool cheap = (double)nswept_fail * (double)N * (double)L <= rec_factor * cells;
+    if (P->cfg.path == VALMOD_PATH_RECOMPUTE || cheap) {
+      full = false;
+      recompute = nswept_fail > 0;
+    } else if (probe_next && (double)nswept_fail > 0.25 * (double)N) {
+      heaps_on = false;  // the bound fails right after a rebuild: partial profiles do not pay here
+    } else {
+      rebuild = true;
+    }
+    probe_next = false;
+  }
+  if (full) {
+    const int32_t* src = prev;
+    if (L == Ls.l_min || (!fp32 && !rebuild)) {
+      // exact FP64 matrix-profile pass: running best keys seeded from the previous length
+      LCHECK(launch_seed_mp(xs, mu, invn, flat, prev, N, L, e, best, thr, thr32, st));
+      PassLaunch q = pl;
+      q.append = false;
+      if (fp32) {
+        LCHECK(launch_pass(q, st));
+        ++passes;
+      } else {
+        LCHECK(timed_pass(q));
+      }
+      if (rebuild) {  // first length: the exact neighbours seed the collecting pass
+        LCHECK(launch_keys_to_idx(best, N, pi, st));
+        src = pi;
+      }
+    }
+    if (rebuild) {
+      // new partial profiles at base L (Alg. ComputeMatrixProfile)
+      LCHECK(collect(src, p, p, L == Ls.l_min ? 1 : 0));
+      base = L;
+      probe_next = true;
+    } else if (fp32 && L > Ls.l_min) {
+      // exact neighbours from an FP32 collecting pass seeded by the previous length
+      LCHECK(collect(src, 1, 0, 0));
+    }
+  }
+  if (recompute) LCHECK(launch_recompute(xs, A, invn, flat, fail, &cnt[CNT_NFAIL], N, N, L, e, best, st));
+  LCHECK(launch_finalize(xs, mu, sig, best, N, L, pd, pi, vnorm, vdist, vlen, vidx, st));
+  LCHECK(launch_fill_tail(N, N0, pd, pi, st));
+  LCHECK(launch_record_stats(cnt, o->stats ? o->stats + Ls.stats + t * VALMOD_NSTATS : nullptr, full ? 1 : 0,
+                             nvalid, nswept_fail, recompute ? 1 : 0, passes, st));
+  // VALMOD_PROGRESS=k: one line on stderr every k lengths, once the length has run
+  const int progress = capture ? 0 : env_int("VALMOD_PROGRESS", 0);
+  if (progress > 0 && (t % progress == 0 || L == Ls.l_max)) {
+    LCHECK(hipStreamSynchronize(st));
+    fprintf(stderr, "valmod: series %d length %d (%lld of %lld) done, heaps %s\n", s, L, (long long)t + 1,
+            (long long)Ls.nlen, heaps_on ? "on" : "off");
+    fflush(stderr);
+  }
+  phase = 0;
+  if (++L > Ls.l_max) {
+    const int km = P->cfg.k_motifs, kd = P->cfg.k_discords;
+    LCHECK(launch_rankings(o->prof_dist + Ls.prof, o->prof_idx + Ls.prof, N0, n, Ls.l_min, (int)Ls.nlen, excl_den,
+                           km, kd, o->motif_ab + 2 * Ls.motif, o->motif_d + Ls.motif, o->discord_on + 2 * Ls.discord,
+                           o->discord_d + Ls.discord, st));
+    LCHECK(launch_global_rank(vnorm, vdist, vlen, vidx, N0, o->discord_on + 2 * Ls.discord, o->discord_d + Ls.discord,
+                              (int)Ls.nlen, Ls.l_min, excl_den, km, kd, o->g_motif_abl + 3 * Ls.g_motif,
+                              o->g_motif_d + 2 * Ls.g_motif, o->g_discord_onl + 3 * Ls.g_discord,
+                              o->g_discord_d + 2 * Ls.g_discord, st));
+    open = false;
+    ++si;
+  }
+  return CONTINUE;
+}
+
+#undef LCHECK
+
+// Enqueues the whole run: the lanes fork from the caller's stream, advance one
+// length at a time in turn (a blocked lane is skipped until its counters have
+// arrived), and join back into the caller's stream.
+hipError_t enqueue_run(valmod_plan_s* P, char* ws, const valmod_outputs* o, const char* d_series, hipStream_t st,
+                       bool capture) {
+  hipError_t e = hipEventRecord(P->start, st);
+  std::vector<LaneRun> runs(P->lanes.size());
+  for (size_t l = 0; e == hipSuccess && l < P->lanes.size(); ++l) {
+    Lane& ln = P->lanes[l];
+    runs[l].init(P, &ln, ws, o, d_series, capture);
+    e = hipStreamWaitEvent(ln.st, P->start, 0);
+    if (e == hipSuccess)
+      e = launch_zero_counters((unsigned long long*)(ws + ln.base + ln.ws.counters), CNT_WORDS, ln.st);
+  }
+  std::vector<char> done(P->lanes.size(), 0), blocked(P->lanes.size(), 0);
+  size_t remaining = e == hipSuccess ? P->lanes.size() : 0;
+  while (remaining > 0) {
+    bool progressed = false;
+    int first_blocked = -1;
+    for (size_t l = 0; l < P->lanes.size(); ++l) {
+      if (done[l]) continue;
+      if (blocked[l]) {
+        const hipError_t q = hipEventQuery(P->lanes[l].ready);
+        if (q == hipErrorNotReady) {
+          if (first_blocked < 0) first_blocked = (int)l;
+          continue;
+        }
+        if (q != hipSuccess) {
+          e = q;
+          remaining = 0;
+          break;
+        }
+        blocked[l] = 0;
+      }
+      const LaneRun::Status r = runs[l].advance();
+      progressed = true;
+      if (r == LaneRun::DONE) {
+        done[l] = 1;
+        --remaining;
+      } else if (r == LaneRun::BLOCKED) {
+        blocked[l] = 1;
+      }
+    }
+    if (!progressed && first_blocked >= 0) {
+      e = hipEventSynchronize(P->lanes[first_blocked].ready);
+      if (e != hipSuccess) break;
+    }
+  }
+  for (size_t l = 0; l < runs.size(); ++l) {
+    if (e == hipSuccess && runs[l].err != hipSuccess) e = runs[l].err;
+    P->lanes[l].nev = runs[l].evi;
+  }
+  for (size_t l = 0; l < P->lanes.size(); ++l) {
+    Lane& ln = P->lanes[l];
+    if (e == hipSuccess) e = hipEventRecord(ln.done, ln.st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ln.done, 0);
+  }
+  return e;
+}
+
+}  // namespace
 
 extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void* d_ws,
                                     const valmod_outputs* o, void* stream_) {
@@ -310,300 +791,67 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
   int prev_dev = -1;
   if (hipGetDevice(&prev_dev) != hipSuccess) return VALMOD_E_HIP;
   if (hipSetDevice(P->cfg.device) != hipSuccess) return VALMOD_E_HIP;
-
   char* ws = (char*)d_ws;
-  double* xs = (double*)(ws + P->ws.xs);
-  double* A = (double*)(ws + P->ws.A);
-  double* B = (double*)(ws + P->ws.B);
-  double* mu = (double*)(ws + P->ws.mu);
-  double* sig = (double*)(ws + P->ws.sig);
-  double* invn = (double*)(ws + P->ws.invn);
-  uint8_t* flat = (uint8_t*)(ws + P->ws.flat);
-  double* df = (double*)(ws + P->ws.df);
-  double* dg = (double*)(ws + P->ws.dg);
-  float* sw32 = (float*)(ws + P->ws.sw32);
-  double* thr = (double*)(ws + P->ws.thr);
-  float* thr32 = (float*)(ws + P->ws.thr32);
-  double* anc = (double*)(ws + P->ws.anc);
-  uint64_t* best = (uint64_t*)(ws + P->ws.best);
-  unsigned long long* cnt = (unsigned long long*)(ws + P->ws.counters);
-  const int esz = P->cfg.dtype == VALMOD_F32 ? 4 : 8;
-  const int excl_den = P->cfg.excl_den;
-  const int km = P->cfg.k_motifs, kd = P->cfg.k_discords;
-
-  std::vector<unsigned long long> host_cnt(CNT_WORDS);
-  int64_t total_lengths = 0;
-  for (auto& L : P->lay) total_lengths += L.nlen;
-
-  // events bracketing every diagonal-pass launch
-  if (P->ev_device != P->cfg.device || (int64_t)P->ev.size() < 4 * total_lengths) {
-    for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
-    P->ev.clear();
-    if (P->fork) (void)hipEventDestroy(P->fork);
-    if (P->join) (void)hipEventDestroy(P->join);
-    if (P->aux) (void)hipStreamDestroy(P->aux);
-    P->fork = P->join = nullptr;
-    P->aux = nullptr;
-    if (hipEventCreateWithFlags(&P->fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&P->join, hipEventDisableTiming) != hipSuccess ||
-        hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking) != hipSuccess) {
-      status = VALMOD_E_HIP;
-      goto done;
-    }
-    for (int64_t i = 0; i < 4 * total_lengths; ++i) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) {
-        status = VALMOD_E_HIP;
-        goto done;
-      }
-      P->ev.push_back(e);
-    }
-    P->ev_device = P->cfg.device;
-  }
+  hipError_t e = ensure_resources(P);
   P->pass_ms = 0.0;
   P->pass_launches = 0;
   P->pass_cells = 0;
-
-  VCHECK(hipMemsetAsync(cnt, 0, CNT_WORDS * 8, st));
-  {
-    int32_t* hc = (int32_t*)(ws + P->ws.hc);
-    double* hS = (double*)(ws + P->ws.hS);
-    int32_t* hn = (int32_t*)(ws + P->ws.hn);
-    double* hbound = (double*)(ws + P->ws.hbound);
-    double* hsig = (double*)(ws + P->ws.hsig);
-    uint32_t* acnt = (uint32_t*)(ws + P->ws.acnt);
-    int32_t* abuf = (int32_t*)(ws + P->ws.abuf);
-    int32_t* fail = (int32_t*)(ws + P->ws.fail);
-    int32_t* big = (int32_t*)(ws + P->ws.big);
-    const bool fp32 = P->cfg.precision == VALMOD_PREC_FP32_REFRESH;
-    float* df32 = fp32 ? (float*)(ws + P->ws.df32) : nullptr;
-    float* dg32 = fp32 ? (float*)(ws + P->ws.dg32) : nullptr;
-    float* inv32 = fp32 ? (float*)(ws + P->ws.inv32) : nullptr;
-    float* bsw_max = fp32 ? (float*)(ws + P->ws.bsw_max) : nullptr;
-    float* bsw_min = fp32 ? (float*)(ws + P->ws.bsw_min) : nullptr;
-    float* bdf_max = fp32 ? (float*)(ws + P->ws.bdf_max) : nullptr;
-    float* bdg_max = fp32 ? (float*)(ws + P->ws.bdg_max) : nullptr;
-    float* delta = fp32 ? (float*)(ws + P->ws.delta) : nullptr;
-    int32_t* hard = fp32 ? (int32_t*)(ws + P->ws.hard) : nullptr;
-    // FP32 work items whose rounding bound exceeds this go to the FP64 kernel
-    const float delta_max = (float)(env_int("VALMOD_FP32_DELTA_MAX_E6", 5000) * 1.0e-6);
-    const int p = P->cfg.p;
-    const int D = p < 15 ? p : 15;
-    const double margin = 1.0e-11;  // pass rounding of the FP64 correlation
-    const double rec_factor = env_int("VALMOD_RECOMPUTE_FACTOR_X100", 80) / 100.0;
-    // VALMOD_PROGRESS=k: one line on stderr every k lengths (the line is written
-    // when the length is enqueued; the sweep's host reads keep it close to the GPU)
-    const int progress = env_int("VALMOD_PROGRESS", 0);
-    unsigned long long* hcnt = host_cnt.data();
-    auto read_counters = [&]() -> hipError_t {
-      hipError_t e1 = hipMemcpyAsync(hcnt, cnt, CNT_WORDS * 8, hipMemcpyDeviceToHost, st);
-      if (e1 != hipSuccess) return e1;
-      return hipStreamSynchronize(st);
-    };
-    int64_t evi = 0;
-    for (int s = 0; s < P->cfg.num_series; ++s) {
-      const valmod_layout& Ls = P->lay[s];
-      const PassGeom& G = P->geom[s];
-      const int64_t n = Ls.n, N0 = Ls.n0;
-      const char* series = (const char*)d_series + (size_t)Ls.series * esz;
-      VCHECK(launch_convert(series, P->cfg.dtype, n, n + kPad, xs, (int*)&cnt[CNT_ERR], st));
-      double* vnorm = o->valmp_norm + Ls.valmp;
-      double* vdist = o->valmp_dist + Ls.valmp;
-      int32_t* vlen = o->valmp_len + Ls.valmp;
-      int32_t* vidx = o->valmp_idx + Ls.valmp;
-      VCHECK(launch_valmp_init(N0, vnorm, vdist, vlen, vidx, st));
-      // partial profiles are used unless every length is forced through a full pass
-      bool heaps_on = P->cfg.path != VALMOD_PATH_FULL && Ls.l_max > Ls.l_min;
-      int base = 0;             // base length of the current partial profiles (0: none)
-      bool probe_next = false;  // judge the partial profiles at the first length after a rebuild
-      for (int L = Ls.l_min; L <= Ls.l_max; ++L) {
-        const int64_t t = L - Ls.l_min;
-        const int64_t N = n - L + 1;
-        const int64_t e = excl_zone(L, excl_den);
-        const PassGrid grid = pass_grid(N, e, G.dstart, G.K, G.H);
-        double* pd = o->prof_dist + Ls.prof + t * N0;
-        int32_t* pi = o->prof_idx + Ls.prof + t * N0;
-        const int32_t* prev = L > Ls.l_min ? pi - N0 : nullptr;
-        VCHECK(launch_stats(xs, N, L, L == Ls.l_min, P->cfg.flat_eps, A, B, mu, sig, invn, flat, &cnt[CNT_NFLAT],
-                            st));
-        if (G.table) VCHECK(launch_anchor(xs, n, L, L == Ls.l_min, G.H, G.dstart, G.segs, G.stride, G.stride, anc, st));
-        VCHECK(launch_prep_f64(xs, mu, sig, invn, N, L, df, dg, sw32, st));
-
-        PassLaunch pl{};
-        pl.xs = xs;
-        pl.mu = mu;
-        pl.df = df;
-        pl.dg = dg;
-        pl.sw32 = sw32;
-        pl.invn = invn;
-        pl.df32 = df32;
-        pl.dg32 = dg32;
-        pl.inv32 = inv32;
-        pl.thr = thr;
-        pl.thr32 = thr32;
-        pl.best = best;
-        pl.anc = G.table ? anc : nullptr;
-        pl.A = A;
-        pl.anc_stride = G.stride;
-        pl.N = N;
-        pl.e = e;
-        pl.H = G.H;
-        pl.dstart = G.dstart;
-        pl.L = L;
-        pl.K = G.K;
-        pl.events = &cnt[CNT_EV_STEPS];
-        pl.cnt = acnt;
-        pl.buf = abuf;
-        pl.cap = P->cap;
-        int64_t passes = 0;
-        // full-grid launch of the plan's own pass kernel: bracketed by events
-        auto timed_pass = [&](const PassLaunch& q) -> hipError_t {
-          const bool tm = evi + 2 <= (int64_t)P->ev.size();
-          hipError_t e1 = tm ? hipEventRecord(P->ev[evi], st) : hipSuccess;
-          if (e1 == hipSuccess) e1 = launch_pass(q, st);
-          if (e1 == hipSuccess && tm) e1 = hipEventRecord(P->ev[evi + 1], st);
-          if (tm) evi += 2;
-          P->pass_launches += 1;
-          P->pass_cells += grid.cells;
-          ++passes;
-          return e1;
-        };
-        bool fp32_ready = false;
-        // FP32 inputs and the per-item rounding bounds at this length; items over
-        // the limit are listed for the FP64 kernel
-        auto fp32_setup = [&]() -> hipError_t {
-          if (fp32_ready) return hipSuccess;
-          fp32_ready = true;
-          hipError_t e1 = launch_fp32_prep(sig, invn, df, dg, N, L, df32, dg32, inv32, bsw_max, bsw_min, bdf_max,
-                                           bdg_max, st);
-          if (e1 == hipSuccess)
-            e1 = launch_fp32_items(bsw_max, bsw_min, bdf_max, bdg_max, N, e, G.dstart, G.K, G.H, delta_max, delta,
-                                   hard, &cnt[CNT_HARD], st);
-          return e1;
-        };
-        bool recompute = false;  // process the recompute list (its length is a device counter)
-        bool swept = false;      // the sweep filled the recompute list at this length
-        // collecting pass above per-owner thresholds from the candidates of `src`,
-        // then the exact merge (top-`keep` partial profiles and best keys)
-        auto collect = [&](const int32_t* src, int p_eff, int keep, int best_exact) -> hipError_t {
-          hipError_t e1 = swept ? launch_zero_counters(&cnt[CNT_NFAIL], 1, st) : hipSuccess;
-          if (e1 == hipSuccess)
-            e1 = launch_seed_append(xs, A, invn, flat, src, N, L, e, p_eff, p_eff == 1 ? 0 : D, margin, best_exact,
-                                    thr, acnt, fail, &cnt[CNT_NFAIL], st);
-          PassLaunch q = pl;
-          q.append = true;
-          if (fp32) {
-            if (e1 == hipSuccess) e1 = fp32_setup();
-            if (e1 == hipSuccess) e1 = launch_thr_to_f32(thr, N + kPad, thr32, st);
-            // listed items run in FP64 on the second stream, beside the FP32 pass
-            PassLaunch h = pl;
-            h.append = true;
-            h.items = hard;
-            h.nitems = grid.segs * grid.bands;
-            h.nitems_dev = &cnt[CNT_HARD];
-            if (e1 == hipSuccess) e1 = hipEventRecord(P->fork, st);
-            if (e1 == hipSuccess) e1 = hipStreamWaitEvent(P->aux, P->fork, 0);
-            if (e1 == hipSuccess) e1 = launch_pass(h, P->aux);
-            if (e1 == hipSuccess) e1 = hipEventRecord(P->join, P->aux);
-            ++passes;
-            q.fp32 = true;
-            q.delta = delta;
-            q.delta_max = delta_max;
-            if (e1 == hipSuccess) e1 = timed_pass(q);
-            if (e1 == hipSuccess) e1 = hipStreamWaitEvent(st, P->join, 0);
-          } else if (e1 == hipSuccess) {
-            e1 = timed_pass(q);
-          }
-          if (e1 == hipSuccess)
-            e1 = launch_merge(xs, A, invn, sig, flat, thr, acnt, abuf, P->cap, N, L, p, keep, margin, best_exact, hc,
-                              hS, hn, hbound, hsig, best, fail, &cnt[CNT_NFAIL], big, &cnt[CNT_BIG],
-                              &cnt[CNT_APPENDS], st);
-          recompute = true;
-          return e1;
-        };
-
-        int64_t nvalid = 0, nswept_fail = 0;
-        bool full = true, rebuild = false;
-        if (L == Ls.l_min) {
-          rebuild = heaps_on;
-        } else if (heaps_on && base > 0) {
-          // Alg. ComputeSubMP: sweep the partial profiles, certify by the lower bound
-          VCHECK(launch_sweep(xs, A, invn, sig, flat, N, L, e, p, base, hc, hS, hn, hbound, hsig, best, fail,
-                              &cnt[CNT_NFAIL], &cnt[CNT_VALID], st));
-          VCHECK(read_counters());
-          swept = true;
-          nswept_fail = (int64_t)hcnt[CNT_NFAIL];
-          nvalid = (int64_t)hcnt[CNT_VALID];
-          // row recompute of the failing windows vs one full pass (cost model in FMA-equivalents)
-          const double cells = 0.5 * (double)N * (double)N;
-          const bool cheap = (double)nswept_fail * (double)N * (double)L <= rec_factor * cells;
-          if (P->cfg.path == VALMOD_PATH_RECOMPUTE || cheap) {
-            full = false;
-            recompute = nswept_fail > 0;
-          } else if (probe_next && (double)nswept_fail > 0.25 * (double)N) {
-            heaps_on = false;  // the bound fails right after a rebuild: partial profiles do not pay here
-          } else {
-            rebuild = true;
-          }
-          probe_next = false;
-        }
-        if (full) {
-          const int32_t* src = prev;
-          if (L == Ls.l_min || (!fp32 && !rebuild)) {
-            // exact FP64 matrix-profile pass: running best keys seeded from the previous length
-            VCHECK(launch_seed_mp(xs, mu, invn, flat, prev, N, L, e, best, thr, thr32, st));
-            PassLaunch q = pl;
-            q.append = false;
-            if (fp32) {
-              VCHECK(launch_pass(q, st));
-              ++passes;
-            } else {
-              VCHECK(timed_pass(q));
-            }
-            if (rebuild) {  // first length: the exact neighbours seed the collecting pass
-              VCHECK(launch_keys_to_idx(best, N, pi, st));
-              src = pi;
-            }
-          }
-          if (rebuild) {
-            // new partial profiles at base L (Alg. ComputeMatrixProfile)
-            VCHECK(collect(src, p, p, L == Ls.l_min ? 1 : 0));
-            base = L;
-            probe_next = true;
-          } else if (fp32 && L > Ls.l_min) {
-            // exact neighbours from an FP32 collecting pass seeded by the previous length
-            VCHECK(collect(src, 1, 0, 0));
-          }
-        }
-        if (recompute) VCHECK(launch_recompute(xs, A, invn, flat, fail, &cnt[CNT_NFAIL], N, N, L, e, best, st));
-        VCHECK(launch_finalize(xs, mu, sig, best, N, L, pd, pi, vnorm, vdist, vlen, vidx, st));
-        VCHECK(launch_fill_tail(N, N0, pd, pi, st));
-        VCHECK(launch_record_stats(cnt, o->stats ? o->stats + Ls.stats + t * VALMOD_NSTATS : nullptr, full ? 1 : 0,
-                                   nvalid, nswept_fail, recompute ? 1 : 0, passes, st));
-        if (progress > 0 && (t % progress == 0 || L == Ls.l_max)) {
-          VCHECK(hipStreamSynchronize(st));
-          fprintf(stderr, "valmod: series %d length %d (%lld of %lld) done, heaps %s\n", s, L, (long long)t + 1,
-                  (long long)Ls.nlen, heaps_on ? "on" : "off");
-          fflush(stderr);
-        }
+  if (e == hipSuccess && P->cfg.graph) {
+    // one captured graph per set of buffers and stream, replayed on later calls
+    const bool same = P->exec && P->key_series == d_series && P->key_ws == d_ws && P->key_stream == st &&
+                      memcmp(&P->key_out, o, sizeof(*o)) == 0;
+    if (!same) {
+      if (P->exec) (void)hipGraphExecDestroy(P->exec);
+      P->exec = nullptr;
+      hipGraph_t g = nullptr;
+      e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        const hipError_t e1 = enqueue_run(P, ws, o, (const char*)d_series, st, true);
+        e = hipStreamEndCapture(st, &g);
+        if (e1 != hipSuccess) e = e1;
       }
-      VCHECK(launch_rankings(o->prof_dist + Ls.prof, o->prof_idx + Ls.prof, N0, n, Ls.l_min, (int)Ls.nlen,
-                             excl_den, km, kd, o->motif_ab + 2 * Ls.motif, o->motif_d + Ls.motif,
-                             o->discord_on + 2 * Ls.discord, o->discord_d + Ls.discord, st));
-      VCHECK(launch_global_rank(vnorm, vdist, vlen, vidx, N0, o->discord_on + 2 * Ls.discord,
-                                o->discord_d + Ls.discord, (int)Ls.nlen, Ls.l_min, excl_den, km, kd,
-                                o->g_motif_abl + 3 * Ls.g_motif, o->g_motif_d + 2 * Ls.g_motif,
-                                o->g_discord_onl + 3 * Ls.g_discord, o->g_discord_d + 2 * Ls.g_discord, st));
+      if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (e == hipSuccess) {
+        P->key_series = d_series;
+        P->key_ws = d_ws;
+        P->key_stream = st;
+        P->key_out = *o;
+        P->graph_cells = P->pass_cells;
+      }
     }
-    VCHECK(read_counters());
-    for (int64_t i = 0; i < evi; i += 2) {
-      float ms = 0.f;
-      VCHECK(hipEventElapsedTime(&ms, P->ev[i], P->ev[i + 1]));
-      P->pass_ms += ms;
-    }
-    if (host_cnt[CNT_ERR]) status = VALMOD_E_DEVICE;
+    if (e == hipSuccess) e = hipEventRecord(P->g0, st);
+    if (e == hipSuccess) e = hipGraphLaunch(P->exec, st);
+    if (e == hipSuccess) e = hipEventRecord(P->g1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(P->g1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, P->g0, P->g1);
+    // graph mode reports the whole replay as one launch
+    P->pass_ms = ms;
+    P->pass_launches = 1;
+    P->pass_cells = P->graph_cells;
+  } else if (e == hipSuccess) {
+    e = enqueue_run(P, ws, o, (const char*)d_series, st, false);
   }
-done:
+  // device error flags of every lane
+  for (Lane& ln : P->lanes)
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&ln.hcnt[4], ws + ln.base + ln.ws.counters + CNT_ERR * 8, 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && !P->cfg.graph) {
+    for (Lane& ln : P->lanes)
+      for (int64_t i = 0; e == hipSuccess && i + 1 < ln.nev; i += 2) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ln.ev[i], ln.ev[i + 1]);
+        P->pass_ms += ms;
+      }
+  }
+  if (e != hipSuccess) {
+    status = VALMOD_E_HIP;
+  } else {
+    for (Lane& ln : P->lanes)
+      if (ln.hcnt[4]) status = VALMOD_E_DEVICE;
+  }
   (void)hipSetDevice(prev_dev);
   return status;
 }

@@ -50,6 +50,8 @@ class ValmodConfig(ctypes.Structure):
         ("refresh_R", ctypes.c_int32),
         ("path", ctypes.c_int32),
         ("device", ctypes.c_int32),
+        ("lanes", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
     ]
 
 
@@ -124,7 +126,7 @@ def _check(rc: int, where: str):
 def make_config(n: Sequence[int], l_min: Sequence[int], l_max: Sequence[int], p: int = 0,
                 k_motifs: int = 1, k_discords: int = 1, excl_den: int = 4, flat_eps: float = 0.0,
                 dtype: str = "f32", precision: str = "fp64", refresh_R: int = 0, path: str = "auto",
-                device: int = 0):
+                device: int = 0, lanes: int = 0, graph: bool = False):
     """Build a ValmodConfig; returns (config, keepalive arrays)."""
     S = len(n)
     na = (ctypes.c_int64 * S)(*[int(v) for v in n])
@@ -134,7 +136,7 @@ def make_config(n: Sequence[int], l_min: Sequence[int], l_max: Sequence[int], p:
                        ctypes.cast(lo, ctypes.POINTER(ctypes.c_int32)),
                        ctypes.cast(hi, ctypes.POINTER(ctypes.c_int32)), int(p), int(k_motifs),
                        int(k_discords), int(excl_den), float(flat_eps), DTYPE[dtype], PRECISION[precision],
-                       int(refresh_R), PATH[path], int(device))
+                       int(refresh_R), PATH[path], int(device), int(lanes), 1 if graph else 0)
     return cfg, (na, lo, hi)
 
 
@@ -194,7 +196,8 @@ class Valmod:
 
     def __init__(self, series: Union["torch.Tensor", List["torch.Tensor"]], l_min, l_max, p: int = 0,
                  k_motifs: int = 1, k_discords: int = 1, excl_den: int = 4, flat_eps: float = 0.0,
-                 precision: str = "fp64", refresh_R: int = 0, path: str = "auto"):
+                 precision: str = "fp64", refresh_R: int = 0, path: str = "auto", lanes: int = 0,
+                 graph: bool = False):
         import torch
 
         if isinstance(series, torch.Tensor):
@@ -211,8 +214,10 @@ class Valmod:
         self.torch = torch
         cfg, self._keep = make_config([s.numel() for s in series], lo, hi, p, k_motifs, k_discords,
                                       excl_den, flat_eps, "f32" if dt == torch.float32 else "f64",
-                                      precision, refresh_R, path, self.device.index or 0)
+                                      precision, refresh_R, path, self.device.index or 0, lanes, graph)
         self.plan = valmod_plan(cfg)
+        self.graph = bool(graph)
+        self._stream = None
         self.k_motifs, self.k_discords = k_motifs, k_discords
         self.sizes = valmod_output_sizes(self.plan)
         self.layouts = [valmod_series_layout(self.plan, s) for s in range(S)]
@@ -243,6 +248,11 @@ class Valmod:
 
     def run(self, stream=None) -> None:
         torch = self.torch
+        if stream is None and self.graph:
+            # graph capture needs a stream other than the legacy default one
+            if self._stream is None:
+                self._stream = torch.cuda.Stream(self.device)
+            stream = self._stream
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         valmod_run(self.plan, self.series.data_ptr(), self.workspace.data_ptr(), self._outs,
                    st.cuda_stream)

@@ -70,6 +70,27 @@ def test_plan_validation(lib):
     assert _status(precision="fp32", refresh_R=8192) == 0
     for bad in (-16, 48, 100, 8208):
         assert _status(precision="fp32", refresh_R=bad) == -1, bad
+    # lanes in [0, 64]; graph 0/1 and not with the forced recompute path
+    assert _status(lanes=64) == 0 and _status(lanes=-1) == -1 and _status(lanes=65) == -1
+    assert _status(graph=True) == 0 and _status(graph=True, path="full") == 0
+    assert _status(graph=True, path="recompute") == -1
+    assert _status(graph=True, precision="fp32") == -1
+
+
+def test_lanes_split_the_workspace(lib):
+    """Each lane gets its own workspace slice sized for its largest series, so
+    more lanes need more workspace; series are assigned largest first."""
+    n, lo, hi = [5000, 4000, 3000, 2000], [30, 30, 30, 30], [40, 40, 40, 40]
+    sizes = []
+    for lanes in (1, 2, 4):
+        cfg, keep = native.make_config(n, lo, hi, p=5, lanes=lanes)
+        plan = native.valmod_plan(cfg)
+        try:
+            sizes.append(native.valmod_workspace_bytes(plan))
+        finally:
+            native.valmod_plan_free(plan)
+    assert sizes[0] < sizes[1] < sizes[2]
+    assert all(v % 256 == 0 for v in sizes)
 
 
 def test_sizes_and_layout(lib):

@@ -397,3 +397,75 @@ def test_config5_offset_flats_precision_stress(oracle_mod):
     for a, b, _ in w.planted_motifs:
         assert abs(int(g32["prof_idx"][0, a]) - b) <= e
     _check_reported_pairs(w.x, g32, lo, TOL64, [lo, hi])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lanes_match_sequential(precision):
+    """Series run concurrently on several lanes give the same outputs as one lane."""
+    torch = _torch()
+    from paper_2008_13447_amd import native
+
+    xs = [gen.small_random_walk(n, 80 + i, np.float32) for i, n in enumerate([3000, 1200, 2500, 900, 1800])]
+    lo, hi = [30, 16, 24, 12, 20], [38, 22, 30, 17, 26]
+    ts = [torch.from_numpy(x).cuda() for x in xs]
+    res = []
+    for lanes in (1, 3):
+        v = native.Valmod(ts, lo, hi, p=5, k_motifs=2, k_discords=2, precision=precision, lanes=lanes)
+        v.run()
+        res.append([v.result(s) for s in range(len(xs))])
+        v.close()
+    for s in range(len(xs)):
+        for key in ("prof_dist", "prof_idx", "valmp_norm", "valmp_idx", "motif_ab", "discord_on", "g_motif_abl"):
+            assert np.array_equal(res[0][s][key], res[1][s][key], equal_nan=True), (s, key)
+
+
+@pytest.mark.parametrize("precision", [
+    "fp64",
+    pytest.param("fp32", marks=pytest.mark.skip(
+        reason="capture of the FP32 path ended the process with a host segmentation fault inside valmod_run; "
+               "the cause is not found, so the plan rejects graph mode with FP32 precision")),
+])
+def test_graph_replays_follow_the_input(oracle_mod, precision):
+    """Graph mode: the first call captures the run, later calls replay it. The
+    input buffer is rewritten between replays (eager work in between); every
+    replay must match an eager run on the same data."""
+    torch = _torch()
+    from paper_2008_13447_amd import native
+
+    a = gen.small_random_walk(2200, 90, np.float32)
+    b = gen.small_random_walk(2200, 91, np.float32)
+    lo, hi = 26, 33
+    g = native.Valmod(torch.from_numpy(a).cuda(), lo, hi, p=5, k_motifs=3, k_discords=3, precision=precision,
+                      graph=True, lanes=1)
+    for rep, x in enumerate([a, b, a, b]):
+        g.series.copy_(torch.from_numpy(x).cuda())
+        torch.cuda.synchronize()
+        g.run()
+        got = g.result(0)
+        ref = run_gpu(x, lo, hi, p=5, k_motifs=3, k_discords=3, precision=precision, path="full")
+        for key in ("prof_dist", "prof_idx", "valmp_norm", "valmp_idx", "motif_ab", "discord_on", "g_motif_abl",
+                    "g_discord_onl"):
+            assert np.array_equal(got[key], ref[key], equal_nan=True), (rep, key)
+        _say(f"graph replay {rep} ok")
+    g.close()
+
+
+def test_batched_random_walks_sampled_parity(oracle_mod):
+    """The first 12 series of the batched workload (random walks of uneven
+    length, each with its own length range) in one plan on four lanes, FP32
+    path: sampled owners of every series at l_min, the middle and l_max."""
+    torch = _torch()
+    from oracle import compare
+    from paper_2008_13447_amd import native
+
+    ws = gen.config4(12)
+    _say("batched: " + ", ".join(f"n={w.n} L={w.l_min}..{w.l_max}" for w in ws))
+    v = native.Valmod([torch.from_numpy(w.x).cuda() for w in ws], [w.l_min for w in ws], [w.l_max for w in ws],
+                      p=10, k_motifs=10, k_discords=10, precision="fp32", lanes=4)
+    v.run()
+    for s, w in enumerate(ws):
+        g = v.result(s)
+        mid = (w.l_min + w.l_max) // 2
+        rep = compare.check_sampled(w.x, w.l_min, g, [w.l_min, mid, w.l_max], 12, TOL64)
+        _say(f"series {s}: {dict(rep)}")
+    v.close()
