@@ -86,6 +86,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--lanes", type=int, default=0, help="series run concurrently (0: library default)")
     ap.add_argument("--graph", action="store_true", help="capture the run in a HIP graph and replay it")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default pass geometry")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"],
                     help="headline path (the other one is timed beside it unless --no-compare)")
     ap.add_argument("--no-compare", action="store_true")
@@ -136,6 +137,12 @@ def main():
         v = native.Valmod(x, lo, hi, p=w.p, k_motifs=w.k_motifs, k_discords=w.k_discords,
                           excl_den=w.excl_den, precision=precision, path="full" if graph else args.path,
                           lanes=args.lanes, graph=graph)
+        tune = None
+        if not args.no_autotune:
+            t0 = time.perf_counter()
+            H, K = v.autotune()
+            tune = {"segment_rows": H, "diagonals_per_lane": K, "ms": (time.perf_counter() - t0) * 1e3}
+            print(f"bench: {precision} autotune {tune}", file=sys.stderr, flush=True)
         for _ in range(args.warmup):
             v.run()
             print(f"bench: {precision} warm-up step done", file=sys.stderr, flush=True)
@@ -149,9 +156,9 @@ def main():
         timing = v.pass_timing()
         res = v.result(0)
         v.close()
-        return ms, timing, res
+        return ms, timing, res, tune
 
-    ms, (pass_ms, launches, pass_cells), res = timed(args.precision)
+    ms, (pass_ms, launches, pass_cells), res, tune = timed(args.precision)
     avg_ms = pass_ms / max(launches, 1)
     achieved = (pass_cells / max(launches, 1)) * FLOP_PER_CELL / (avg_ms * 1e-3) / 1e12
     peak = FP64_PEAK_TFLOPS if args.precision == "fp64" else FP32_PEAK_TFLOPS
@@ -170,12 +177,13 @@ def main():
                      "avg_launch_ms": avg_ms, "launches_per_step": launches,
                      "cells_per_launch": pass_cells / max(launches, 1)},
     }
+    out["autotune"] = tune
     st = res["stats"].sum(axis=0)
     out["diagnostics"] = {name: int(st[c]) for c, name in enumerate(native.STAT_NAMES)}
     if not args.no_compare:
         # the other precision on the same input: throughput and output agreement (first series)
         other = "fp64" if args.precision == "fp32" else "fp32"
-        ms2, _, res2 = timed(other)
+        ms2, _, res2, _ = timed(other)
         L = np.arange(w.l_min, w.l_max + 1)[:, None]
         a, b = res["prof_dist"] / np.sqrt(L), res2["prof_dist"] / np.sqrt(L)
         fin = np.isfinite(a) & np.isfinite(b)

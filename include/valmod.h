@@ -224,6 +224,23 @@ VALMOD_API valmod_status valmod_series_layout(valmod_plan_t plan, int32_t s, val
 VALMOD_API valmod_status valmod_run(valmod_plan_t plan, const void* d_series, void* d_workspace,
                          const valmod_outputs* d_out, void* stream);
 
+/*
+ * Autotuner: choose the diagonal-pass geometry empirically, on the series with
+ * the most work. FP64 plans try segment heights of 1x, 2x and 4x the default;
+ * FP32 plans without a fixed refresh_R try R = 256, 512 and 1024. Each candidate
+ * runs the first three lengths of that series on the full path twice; the
+ * second run is timed and the fastest candidate whose workspace fits in
+ * valmod_workspace_bytes (as it was before the call) is kept. The plan's
+ * workspace requirement can only shrink. Results do not depend on the choice
+ * (exact mode). Arguments are those of valmod_run (same buffers); the outputs of
+ * the tuned series are overwritten and are complete only after a valmod_run.
+ * chosen (optional, host int32[2]): segment height and diagonals per lane of the
+ * tuned series; zeros when there was nothing to tune (fixed refresh_R or
+ * VALMOD_PASS_H set). Errors: those of valmod_run.
+ */
+VALMOD_API valmod_status valmod_autotune(valmod_plan_t plan, const void* d_series, void* d_workspace,
+                                         const valmod_outputs* d_out, void* stream, int32_t* chosen);
+
 /* Release a plan (NULL is ignored). */
 VALMOD_API void valmod_plan_free(valmod_plan_t plan);
 

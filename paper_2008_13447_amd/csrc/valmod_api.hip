@@ -5,6 +5,7 @@
 #include "valmod_kernels.h"
 
 #include <algorithm>
+#include <chrono>
 #include <math.h>
 #include <new>
 #include <stdio.h>
@@ -39,7 +40,7 @@ int env_int(const char* name, int dflt) {
   return v && *v ? atoi(v) : dflt;
 }
 
-PassGeom pass_geom(int64_t n, int32_t l_min, int32_t excl_den, bool fp32, int32_t refresh_R) {
+PassGeom pass_geom(int64_t n, int32_t l_min, int32_t excl_den, bool fp32, int32_t refresh_R, int hmul) {
   PassGeom g;
   const int64_t N0 = n - l_min + 1;
   const int64_t e0 = excl_zone(l_min, excl_den);
@@ -68,6 +69,8 @@ PassGeom pass_geom(int64_t n, int32_t l_min, int32_t excl_den, bool fp32, int32_
     const double items = env_int("VALMOD_PASS_ITEMS", 16384);
     H = 4096;
     while (H > 128 && cells / ((double)bw * (double)H) < items) H /= 2;
+    H *= hmul;  // autotuned: taller segments trade work items for per-item overhead
+    if (H > 8192) H = 8192;
     const int hforce = env_int("VALMOD_PASS_H", 0);
     if (hforce >= 64 && hforce % 8 == 0) H = hforce;
   }
@@ -114,6 +117,9 @@ struct valmod_plan_s {
   hipStream_t key_stream = nullptr;
   valmod_outputs key_out;
   int64_t graph_cells = 0;
+  // autotuned geometry: FP64 segment-height multiplier, FP32 refresh interval (0: default)
+  int tune_hmul = 1;
+  int32_t tune_R = 0;
   double pass_ms = 0.0;
   int64_t pass_launches = 0, pass_cells = 0;
 };
@@ -183,6 +189,31 @@ static size_t layout_lane(const valmod_plan_s* P, Lane& ln) {
   }
   w.total = off;
   return off;
+}
+
+// pass geometry of every series and the workspace of every lane (the lane
+// assignment is fixed at plan time)
+static void build_layout(valmod_plan_s* P) {
+  const bool fp32 = P->cfg.precision == VALMOD_PREC_FP32_REFRESH;
+  const int32_t R = P->cfg.refresh_R > 0 ? P->cfg.refresh_R : P->tune_R;
+  P->geom.clear();
+  for (int s = 0; s < P->cfg.num_series; ++s)
+    P->geom.push_back(pass_geom(P->n[s], P->lmin[s], P->cfg.excl_den, fp32, R, P->tune_hmul));
+  size_t off = 0;
+  for (Lane& ln : P->lanes) {
+    ln.nmax = ln.n0max = ln.ancmax = ln.itemmax = ln.total_lengths = 0;
+    for (int s : ln.series) {
+      const PassGeom& gg = P->geom[s];
+      ln.nmax = std::max(ln.nmax, P->n[s]);
+      ln.n0max = std::max(ln.n0max, P->lay[s].n0);
+      if (gg.table) ln.ancmax = std::max(ln.ancmax, gg.segs * gg.stride);
+      ln.itemmax = std::max(ln.itemmax, gg.segs * gg.bands);
+      ln.total_lengths += P->lay[s].nlen;
+    }
+    ln.base = off;
+    off += align_up(layout_lane(P, ln));
+  }
+  P->ws_total = off;
 }
 
 extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* out) {
@@ -270,8 +301,6 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
     z.g_motif += km;
     z.g_discord += kd;
     z.stats += nlen * VALMOD_NSTATS;
-    P->geom.push_back(pass_geom(n, lo, P->cfg.excl_den, P->cfg.precision == VALMOD_PREC_FP32_REFRESH,
-                                P->cfg.refresh_R));
     for (int64_t Lx = lo; Lx <= hi; ++Lx) cost[s] += (double)(n - Lx + 1) * (double)(n - Lx + 1);
   }
   const size_t pp = (size_t)P->cfg.p;
@@ -296,21 +325,8 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
     delete P;
     return fail(VALMOD_E_NOMEM);
   }
-  size_t off = 0;
-  for (Lane& ln : P->lanes) {
-    std::sort(ln.series.begin(), ln.series.end());
-    for (int s : ln.series) {
-      const PassGeom& gg = P->geom[s];
-      ln.nmax = std::max(ln.nmax, P->n[s]);
-      ln.n0max = std::max(ln.n0max, P->lay[s].n0);
-      if (gg.table) ln.ancmax = std::max(ln.ancmax, gg.segs * gg.stride);
-      ln.itemmax = std::max(ln.itemmax, gg.segs * gg.bands);
-      ln.total_lengths += P->lay[s].nlen;
-    }
-    ln.base = off;
-    off += align_up(layout_lane(P, ln));
-  }
-  P->ws_total = off;
+  for (Lane& ln : P->lanes) std::sort(ln.series.begin(), ln.series.end());
+  build_layout(P);
   *out = P;
   return VALMOD_OK;
 }
@@ -854,4 +870,114 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
   }
   (void)hipSetDevice(prev_dev);
   return status;
+}
+
+// Empirical choice of the pass geometry (FP64: segment height; FP32: refresh
+// interval R) on the series with the most work: each candidate runs the first
+// lengths of that series through the full path twice, the second run is timed,
+// and the fastest candidate whose workspace fits is kept. Outputs of that series
+// are overwritten (the real run writes them again).
+extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, void* d_ws, const valmod_outputs* o,
+                                         void* stream, int32_t* chosen) {
+  if (!P || !d_series || !d_ws || !o) return VALMOD_E_ARG;
+  const bool fp32 = P->cfg.precision == VALMOD_PREC_FP32_REFRESH;
+  int sbest = 0;
+  double cbest = -1.0;
+  for (int s = 0; s < P->cfg.num_series; ++s) {
+    double c = 0.0;
+    for (int64_t L = P->lmin[s]; L <= P->lmax[s]; ++L) c += (double)(P->n[s] - L + 1) * (double)(P->n[s] - L + 1);
+    if (c > cbest) {
+      cbest = c;
+      sbest = s;
+    }
+  }
+  std::vector<std::pair<int, int32_t>> cand;  // (hmul, R)
+  if (fp32) {
+    if (P->cfg.refresh_R <= 0)
+      for (int32_t R : {256, 512, 1024}) cand.push_back({1, R});
+  } else if (env_int("VALMOD_PASS_H", 0) == 0) {
+    for (int h : {1, 2, 4}) cand.push_back({h, 0});
+  }
+  if (cand.size() < 2) {
+    if (chosen) chosen[0] = chosen[1] = 0;
+    return VALMOD_OK;
+  }
+  const valmod_layout& Ls = P->lay[sbest];
+  const int esz = P->cfg.dtype == VALMOD_F32 ? 4 : 8;
+  const int32_t T = (int32_t)std::min<int64_t>(3, Ls.nlen);
+  valmod_outputs so = *o;  // the first T lengths of series sbest
+  so.prof_dist += Ls.prof;
+  so.prof_idx += Ls.prof;
+  so.valmp_norm += Ls.valmp;
+  so.valmp_dist += Ls.valmp;
+  so.valmp_len += Ls.valmp;
+  so.valmp_idx += Ls.valmp;
+  so.motif_ab += 2 * Ls.motif;
+  so.motif_d += Ls.motif;
+  so.discord_on += 2 * Ls.discord;
+  so.discord_d += Ls.discord;
+  so.g_motif_abl += 3 * Ls.g_motif;
+  so.g_motif_d += 2 * Ls.g_motif;
+  so.g_discord_onl += 3 * Ls.g_discord;
+  so.g_discord_d += 2 * Ls.g_discord;
+  if (so.stats) so.stats += Ls.stats;
+  const void* sub_series = (const char*)d_series + (size_t)Ls.series * esz;
+  double best_ms = -1.0;
+  std::pair<int, int32_t> best = {P->tune_hmul, P->tune_R};
+  for (const auto& c : cand) {
+    valmod_config sc = P->cfg;
+    const int64_t n1 = Ls.n;
+    const int32_t lo1 = Ls.l_min, hi1 = Ls.l_min + T - 1;
+    sc.num_series = 1;
+    sc.n = &n1;
+    sc.l_min = &lo1;
+    sc.l_max = &hi1;
+    sc.path = VALMOD_PATH_FULL;
+    sc.lanes = 1;
+    sc.graph = 0;
+    sc.refresh_R = c.second;
+    valmod_plan_t sub = nullptr;
+    valmod_status st = valmod_plan(&sc, &sub);
+    if (st != VALMOD_OK) return st;
+    sub->tune_hmul = c.first;
+    build_layout(sub);
+    if (sub->ws_total > P->ws_total) {
+      valmod_plan_free(sub);
+      continue;
+    }
+    st = valmod_run(sub, sub_series, d_ws, &so, stream);
+    const auto t0 = std::chrono::steady_clock::now();
+    if (st == VALMOD_OK) st = valmod_run(sub, sub_series, d_ws, &so, stream);
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    valmod_plan_free(sub);
+    if (st != VALMOD_OK) return st;
+    if (best_ms < 0.0 || ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  const int old_hmul = P->tune_hmul;
+  const int32_t old_R = P->tune_R;
+  const size_t old_total = P->ws_total;
+  P->tune_hmul = best.first;
+  P->tune_R = best.second;
+  build_layout(P);
+  if (P->ws_total > old_total) {  // never needs more workspace than the caller holds
+    P->tune_hmul = old_hmul;
+    P->tune_R = old_R;
+    build_layout(P);
+  }
+  if (P->exec) {  // a captured run used the old geometry
+    int prev = -1;
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(P->cfg.device) == hipSuccess) {
+      (void)hipGraphExecDestroy(P->exec);
+      (void)hipSetDevice(prev);
+    }
+    P->exec = nullptr;
+  }
+  if (chosen) {
+    chosen[0] = (int32_t)P->geom[sbest].H;
+    chosen[1] = P->geom[sbest].K;
+  }
+  return VALMOD_OK;
 }

@@ -31,7 +31,7 @@ STAT_NAMES = ["valid", "failed", "recomputed", "full_pass", "flat", "appends", "
 
 # (name, C type) of every function declared in include/valmod.h
 EXPORTS = ["valmod_plan", "valmod_workspace_bytes", "valmod_output_sizes", "valmod_series_layout",
-           "valmod_run", "valmod_plan_free", "valmod_status_str", "valmod_last_pass_timing"]
+           "valmod_run", "valmod_autotune", "valmod_plan_free", "valmod_status_str", "valmod_last_pass_timing"]
 
 
 class ValmodConfig(ctypes.Structure):
@@ -103,6 +103,8 @@ def lib() -> ctypes.CDLL:
     L.valmod_series_layout.restype = ctypes.c_int
     L.valmod_run.argtypes = [P, P, P, ctypes.POINTER(ValmodOutputs), P]
     L.valmod_run.restype = ctypes.c_int
+    L.valmod_autotune.argtypes = [P, P, P, ctypes.POINTER(ValmodOutputs), P, ctypes.POINTER(ctypes.c_int32)]
+    L.valmod_autotune.restype = ctypes.c_int
     L.valmod_plan_free.argtypes = [P]
     L.valmod_plan_free.restype = None
     L.valmod_status_str.argtypes = [ctypes.c_int]
@@ -176,6 +178,15 @@ def valmod_run(plan: int, series_ptr: int, workspace_ptr: int, outputs: ValmodOu
                stream: Optional[int] = None) -> None:
     _check(lib().valmod_run(plan, series_ptr, workspace_ptr, ctypes.byref(outputs), stream),
            "valmod_run")
+
+
+def valmod_autotune(plan: int, series_ptr: int, workspace_ptr: int, outputs: ValmodOutputs,
+                    stream: Optional[int] = None):
+    """Returns (segment height, diagonals per lane) of the tuned series, or (0, 0)."""
+    chosen = (ctypes.c_int32 * 2)()
+    _check(lib().valmod_autotune(plan, series_ptr, workspace_ptr, ctypes.byref(outputs), stream, chosen),
+           "valmod_autotune")
+    return int(chosen[0]), int(chosen[1])
 
 
 def valmod_plan_free(plan: int) -> None:
@@ -256,6 +267,17 @@ class Valmod:
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         valmod_run(self.plan, self.series.data_ptr(), self.workspace.data_ptr(), self._outs,
                    st.cuda_stream)
+
+    def autotune(self, stream=None):
+        """Empirical pass geometry (see valmod_autotune); returns (H, K) of the tuned series."""
+        torch = self.torch
+        if stream is None and self.graph:
+            if self._stream is None:
+                self._stream = torch.cuda.Stream(self.device)
+            stream = self._stream
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return valmod_autotune(self.plan, self.series.data_ptr(), self.workspace.data_ptr(), self._outs,
+                               st.cuda_stream)
 
     def pass_timing(self):
         """(ms, launches, cells) of the diagonal-pass kernels of the last run."""

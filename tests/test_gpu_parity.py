@@ -469,3 +469,25 @@ def test_batched_random_walks_sampled_parity(oracle_mod):
         rep = compare.check_sampled(w.x, w.l_min, g, [w.l_min, mid, w.l_max], 12, TOL64)
         _say(f"series {s}: {dict(rep)}")
     v.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotune_keeps_results_exact(oracle_mod, precision):
+    """The autotuner changes only the pass geometry: the run after it still
+    matches the oracle everywhere."""
+    torch = _torch()
+    from oracle import compare
+    from paper_2008_13447_amd import native
+
+    x = gen.small_random_walk(6000, 95, np.float32)
+    lo, hi = 40, 48
+    v = native.Valmod(torch.from_numpy(x).cuda(), lo, hi, p=5, k_motifs=3, k_discords=3, precision=precision)
+    before = native.valmod_workspace_bytes(v.plan)
+    H, K = v.autotune()
+    assert native.valmod_workspace_bytes(v.plan) <= before
+    _say(f"autotune {precision}: H={H} K={K}")
+    v.run()
+    g = v.result(0)
+    v.close()
+    r = oracle_mod.valmod(x, lo, hi, k_motifs=3, k_discords=3)
+    compare.check_full(x, lo, g, r, TOL64)
