@@ -85,6 +85,15 @@ typedef enum {
   VALMOD_PATH_RECOMPUTE = 2  /* never a full pass after l_min (test hook) */
 } valmod_path;
 
+/* What the per-length update guarantees. */
+typedef enum {
+  VALMOD_MODE_EXACT = 0, /* every MP_L entry exact: every window whose bound test fails is recomputed */
+  VALMOD_MODE_PAPER = 1  /* Alg. ComputeSubMP as published: only the failing windows whose bound is
+                            below the best certified distance are recomputed (or a full pass when they
+                            are many), so the motif of every length is exact while other MP_L entries
+                            may be left uncomputed: index -2, distance = a lower bound of the entry */
+} valmod_mode;
+
 /* Maximum number of windows of one series (candidate indices are packed in 22 bits). */
 #define VALMOD_MAX_WINDOWS ((int64_t)1 << 22)
 
@@ -109,6 +118,7 @@ typedef struct {
   int32_t graph;            /* 1: capture the whole run in a HIP graph on the first call and replay it on
                                later calls with the same buffers and stream; implies VALMOD_PATH_FULL
                                (VALMOD_PATH_RECOMPUTE is rejected); FP64 precision only */
+  int32_t mode;             /* valmod_mode; VALMOD_MODE_PAPER needs VALMOD_PATH_AUTO and no graph */
 } valmod_config;
 
 typedef struct valmod_plan_s* valmod_plan_t;
@@ -125,7 +135,8 @@ enum {
   VALMOD_STAT_PASS_HITS = 7,  /* owner updates made by the diagonal pass */
   VALMOD_STAT_FP64_ITEMS = 8, /* FP32 path: work items whose rounding bound sent them to the FP64 kernel */
   VALMOD_STAT_PASSES = 9,     /* diagonal-pass launches at this length */
-  VALMOD_NSTATS = 10
+  VALMOD_STAT_PARTIAL = 10,   /* paper mode: profile entries left uncomputed (index -2) */
+  VALMOD_NSTATS = 11
 };
 
 /*
@@ -133,10 +144,13 @@ enum {
  * output). For series s with N0 = n_s - l_min_s + 1 and nlen = l_max_s - l_min_s + 1,
  * element offsets come from valmod_series_layout; inside one series:
  *   prof_dist[t * N0 + i]  f64  MP_L[i] for L = l_min + t (+inf if none; +inf for i >= N_L)
- *   prof_idx [t * N0 + i]  i32  IP_L[i] (-1 if none)
+ *   prof_idx [t * N0 + i]  i32  IP_L[i] (-1 if none; paper mode: -2 if not computed, and then
+ *                               prof_dist holds a lower bound of MP_L[i])
  *   valmp_norm/valmp_dist[i] f64, valmp_len/valmp_idx[i] i32, i < N0 (len 0 / idx -1 if empty)
  *   motif_ab[(t * k_m + r) * 2 + {0,1}] i32 (a < b), motif_d[t * k_m + r] f64 (NaN / -1 unused)
  *   discord_on[(t * k_d + r) * 2 + {0,1}] i32 (offset, neighbour), discord_d[t * k_d + r] f64
+ *   (paper mode: rankings use the computed entries only; the first motif of each length and the
+ *   first global motif are exact, later ranks and the discords are over the computed entries)
  *   g_motif_abl[r * 3 + {0,1,2}] i32 (a, b, L), g_motif_d[r * 2 + {0,1}] f64 (d, d*sqrt(1/L))
  *   g_discord_onl[r * 3 + {0,1,2}] i32 (offset, neighbour, L), g_discord_d[r * 2 + {0,1}] f64 (d, d/sqrt(L))
  *   stats[t * VALMOD_NSTATS + c] i64
@@ -191,7 +205,8 @@ typedef struct {
  * Errors: VALMOD_E_ARG (null pointers, num_series < 1, l_min < 4, l_max < l_min,
  * p < 0, k < 1, excl_den < 0, flat_eps < 0, unknown enum, lanes outside
  * [0, 64], graph not 0/1, graph with VALMOD_PATH_RECOMPUTE or with
- * VALMOD_PREC_FP32_REFRESH), VALMOD_E_TOO_SHORT
+ * VALMOD_PREC_FP32_REFRESH, unknown mode, paper mode with another path than
+ * VALMOD_PATH_AUTO or with graph), VALMOD_E_TOO_SHORT
  * (n - l_max + 1 <= ceil(l_max / excl_den) + 1: no non-trivial pair),
  * VALMOD_E_LAYOUT (more than VALMOD_MAX_WINDOWS windows), VALMOD_E_NOMEM. */
 VALMOD_API valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* out);

@@ -155,3 +155,35 @@ def check_sampled(x, l_min: int, gpu: Dict[str, np.ndarray], lengths: Sequence[i
         check_profile_rows(x, L, rows, gpu["prof_dist"][t, rows], gpu["prof_idx"][t, rows].astype(np.int64),
                            d_ref, i_ref, tol, excl_den, rep, "sampled")
     return rep
+
+
+def check_paper_mode(x, l_min: int, gpu: Dict[str, np.ndarray], ref: Dict[str, np.ndarray], tol: float,
+                     excl_den: int = 4) -> Report:
+    """Guarantees of Alg. ComputeSubMP as published: computed profile entries are
+    exact, uncomputed ones (index -2) carry a lower bound of the true entry, the
+    first motif of every length and the first global motif are exact."""
+    rep = Report()
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[0]
+    nl = ref["prof_dist"].shape[0]
+    partial = 0
+    for t in range(nl):
+        L = l_min + t
+        N = n - L + 1
+        gi = gpu["prof_idx"][t, :N].astype(np.int64)
+        rows = np.nonzero(gi != -2)[0]
+        check_profile_rows(x, L, rows, gpu["prof_dist"][t, rows], gi[rows], ref["prof_dist"][t, rows],
+                           ref["prof_idx"][t, rows], tol, excl_den, rep, "computed")
+        part = np.nonzero(gi == -2)[0]
+        partial += part.size
+        if part.size:
+            lb, true = gpu["prof_dist"][t, part], ref["prof_dist"][t, part]
+            assert np.all(lb <= true + tol * np.sqrt(L)), f"L={L}: a partial entry's bound exceeds MP_L"
+        gd, rd = gpu["motif_d"][t, 0], ref["motif_d"][t, 0]
+        assert abs(gd - rd) <= tol * np.sqrt(L), f"L={L}: motif distance {gd} vs {rd}"
+        a, b = (int(v) for v in gpu["motif_ab"][t, 0])
+        if a >= 0:
+            assert abs(pair_dists(x, L, [[a, b]])[0] - rd) <= tol * np.sqrt(L), f"L={L}: motif pair not optimal"
+    assert abs(gpu["g_motif_d"][0, 1] - ref["g_motif_d"][0, 1]) <= tol, "global motif differs"
+    rep["partial_entries"] = partial
+    return rep

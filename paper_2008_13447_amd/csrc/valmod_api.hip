@@ -23,7 +23,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
   size_t xs, A, B, mu, sig, invn, flat, df, dg, sw32, thr, thr32, best, counters, anc;
-  size_t hc, hS, hn, hbound, hsig, acnt, abuf, fail, big;
+  size_t hc, hS, hn, hbound, hsig, acnt, abuf, fail, big, lbm, rec, part;
   size_t df32, dg32, inv32, bsw_max, bsw_min, bdf_max, bdg_max, delta, hard;
   size_t total;
 };
@@ -175,6 +175,11 @@ static size_t layout_lane(const valmod_plan_s* P, Lane& ln) {
   w.abuf = take((size_t)ln.n0max * (size_t)P->cap * 4);
   w.fail = take(wp * 4);
   w.big = take(wp * 4);
+  if (P->cfg.mode == VALMOD_MODE_PAPER) {
+    w.lbm = take(wp * 8);
+    w.rec = take(wp * 4);
+    w.part = take(wp * 4);
+  }
   if (P->cfg.precision == VALMOD_PREC_FP32_REFRESH) {
     w.df32 = take(wp * 4);
     w.dg32 = take(wp * 4);
@@ -235,6 +240,8 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
   if (cfg->graph && cfg->path == VALMOD_PATH_RECOMPUTE) return fail(VALMOD_E_ARG);
   // capture of the FP32 path (second stream per lane, collecting pass and merge) is not supported
   if (cfg->graph && cfg->precision == VALMOD_PREC_FP32_REFRESH) return fail(VALMOD_E_ARG);
+  if (cfg->mode != VALMOD_MODE_EXACT && cfg->mode != VALMOD_MODE_PAPER) return fail(VALMOD_E_ARG);
+  if (cfg->mode == VALMOD_MODE_PAPER && (cfg->path != VALMOD_PATH_AUTO || cfg->graph)) return fail(VALMOD_E_ARG);
 
   valmod_plan_s* P = new (std::nothrow) valmod_plan_s();
   if (!P) return fail(VALMOD_E_NOMEM);
@@ -430,12 +437,12 @@ struct LaneRun {
   bool capture = false;
   hipError_t err = hipSuccess;
   // workspace
-  double *xs, *A, *B, *mu, *sig, *invn, *df, *dg, *thr, *anc, *hS, *hbound, *hsig;
+  double *xs, *A, *B, *mu, *sig, *invn, *df, *dg, *thr, *anc, *hS, *hbound, *hsig, *lbm;
   uint8_t* flat;
   float *sw32, *thr32, *df32, *dg32, *inv32, *bsw_max, *bsw_min, *bdf_max, *bdg_max, *delta;
   uint64_t* best;
   unsigned long long* cnt;
-  int32_t *hc, *hn, *abuf, *fail, *big, *hard;
+  int32_t *hc, *hn, *abuf, *fail, *big, *hard, *rec, *part;
   uint32_t* acnt;
   // state
   size_t si = 0;
@@ -476,6 +483,10 @@ struct LaneRun {
     abuf = (int32_t*)(b + w.abuf);
     fail = (int32_t*)(b + w.fail);
     big = (int32_t*)(b + w.big);
+    const bool paper = P->cfg.mode == VALMOD_MODE_PAPER;
+    lbm = paper ? (double*)(b + w.lbm) : nullptr;
+    rec = paper ? (int32_t*)(b + w.rec) : nullptr;
+    part = paper ? (int32_t*)(b + w.part) : nullptr;
     const bool fp32 = P->cfg.precision == VALMOD_PREC_FP32_REFRESH;
     df32 = fp32 ? (float*)(b + w.df32) : nullptr;
     dg32 = fp32 ? (float*)(b + w.dg32) : nullptr;
@@ -549,13 +560,16 @@ LaneRun::Status LaneRun::advance() {
     if (sweep) {
       // Alg. ComputeSubMP: sweep the partial profiles, certify by the lower bound;
       // the choice between row recompute and a full pass needs the counts
+      if (lbm) LCHECK(launch_fill_counters(&cnt[CNT_MINDIST], 2, 0x7FF0000000000000ull, st));  // +inf
       LCHECK(launch_sweep(xs, A, invn, sig, flat, N, L, e, p, base, hc, hS, hn, hbound, hsig, best, fail,
-                          &cnt[CNT_NFAIL], &cnt[CNT_VALID], st));
+                          &cnt[CNT_NFAIL], &cnt[CNT_VALID], lbm, lbm ? &cnt[CNT_MINDIST] : nullptr,
+                          lbm ? &cnt[CNT_MINLB] : nullptr, st));
       if (capture) {
         err = hipErrorNotSupported;  // unreachable: a captured plan has no partial profiles
         return DONE;
       }
-      LCHECK(hipMemcpyAsync(ln->hcnt, &cnt[CNT_NFAIL], 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+      // NFAIL, VALID, HARD, BIG, MINDIST, MINLB
+      LCHECK(hipMemcpyAsync(ln->hcnt, &cnt[CNT_NFAIL], 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
       LCHECK(hipEventRecord(ln->ready, st));
       phase = 1;
       return BLOCKED;
@@ -655,8 +669,30 @@ LaneRun::Status LaneRun::advance() {
 
   int64_t nvalid = 0, nswept_fail = 0;
   bool full = true, rebuild = false;
+  int paper_split = 0;  // paper mode: 1 recompute the failing owners below minDistAbs, 2 leave all partial
   if (L == Ls.l_min) {
     rebuild = heaps_on;
+  } else if (sweep && P->cfg.mode == VALMOD_MODE_PAPER) {
+    // Alg. ComputeSubMP: the motif is certified when the best certified distance is below
+    // every failing owner's bound; otherwise, when the failing owners are few
+    // (fewer than N log p / log N), only those whose bound is below it are recomputed;
+    // otherwise a full pass rebuilds the partial profiles at L (Alg. VALMOD)
+    nswept_fail = (int64_t)ln->hcnt[0];
+    nvalid = (int64_t)ln->hcnt[1];
+    uint64_t bd = ln->hcnt[4], bl = ln->hcnt[5];
+    double min_dist_abs, min_lb_abs;
+    memcpy(&min_dist_abs, &bd, 8);
+    memcpy(&min_lb_abs, &bl, 8);
+    const double limit = (double)N * log((double)(p > 1 ? p : 2)) / log((double)(N > 2 ? N : 3));
+    if (min_dist_abs < min_lb_abs) {
+      full = false;
+      paper_split = 2;
+    } else if ((double)nswept_fail < limit) {
+      full = false;
+      paper_split = 1;
+    } else {
+      rebuild = true;
+    }
   } else if (sweep) {
     nswept_fail = (int64_t)ln->hcnt[0];
     nvalid = (int64_t)ln->hcnt[1];
@@ -701,11 +737,17 @@ LaneRun::Status LaneRun::advance() {
       LCHECK(collect(src, 1, 0, 0));
     }
   }
+  if (paper_split) {
+    LCHECK(launch_split_fail(fail, &cnt[CNT_NFAIL], N, lbm, &cnt[CNT_MINDIST], paper_split == 2 ? 1 : 0, rec,
+                             &cnt[CNT_NREC], part, &cnt[CNT_NPART], st));
+    if (paper_split == 1) LCHECK(launch_recompute(xs, A, invn, flat, rec, &cnt[CNT_NREC], N, N, L, e, best, st));
+  }
   if (recompute) LCHECK(launch_recompute(xs, A, invn, flat, fail, &cnt[CNT_NFAIL], N, N, L, e, best, st));
   LCHECK(launch_finalize(xs, mu, sig, best, N, L, pd, pi, vnorm, vdist, vlen, vidx, st));
+  if (paper_split) LCHECK(launch_mark_partial(part, &cnt[CNT_NPART], N, lbm, pd, pi, st));
   LCHECK(launch_fill_tail(N, N0, pd, pi, st));
   LCHECK(launch_record_stats(cnt, o->stats ? o->stats + Ls.stats + t * VALMOD_NSTATS : nullptr, full ? 1 : 0,
-                             nvalid, nswept_fail, recompute ? 1 : 0, passes, st));
+                             nvalid, nswept_fail, paper_split == 1 ? 2 : (recompute ? 1 : 0), passes, st));
   // VALMOD_PROGRESS=k: one line on stderr every k lengths, once the length has run
   const int progress = capture ? 0 : env_int("VALMOD_PROGRESS", 0);
   if (progress > 0 && (t % progress == 0 || L == Ls.l_max)) {

@@ -210,17 +210,16 @@ __global__ __launch_bounds__(kWave) void k_merge_small(
 #pragma unroll
   for (int msk = kSmallG / 2; msk >= 1; msk >>= 1) nb = fmax(nb, __shfl_xor(nb, msk, kWave));
   if (!live) return;
-  if (skip) {
+  if (skip || m == 0 || m > cap || m > kMergeCap) {
+    // no partial profile: an empty one whose bound is 0 (bound correlation 1),
+    // so that the sweep of a later length never certifies from stale data
     if (l == 0) {
       hn[o] = 0;
-      if (!best_exact || flat[o]) best[o] = kEmptyKey;
-    }
-    return;
-  }
-  if (m == 0 || m > cap || m > kMergeCap) {
-    if (l == 0) {
-      hn[o] = 0;
-      if (!best_exact) {
+      hbound[o] = 2.0;
+      hsig[o] = sig[o];
+      if (skip) {
+        if (!best_exact || flat[o]) best[o] = kEmptyKey;
+      } else if (!best_exact) {
         best[o] = kEmptyKey;
         push_fail(fail, nfail, o);
       }
@@ -306,46 +305,95 @@ __global__ void k_sweep(const double* __restrict__ xs, const double* __restrict_
                         int p, int base, const int32_t* __restrict__ hc, double* __restrict__ hS,
                         const int32_t* __restrict__ hn, const double* __restrict__ hbound,
                         const double* __restrict__ hsig, uint64_t* __restrict__ best, int32_t* __restrict__ fail,
-                        unsigned long long* __restrict__ nfail, unsigned long long* __restrict__ nvalid) {
+                        unsigned long long* __restrict__ nfail, unsigned long long* __restrict__ nvalid,
+                        double* __restrict__ lbm, unsigned long long* __restrict__ min_dist,
+                        unsigned long long* __restrict__ min_lb) {
+  // lbm / min_dist / min_lb (optional, Alg. ComputeSubMP's bookkeeping): the
+  // bound of every failing owner, and the minima over the owners of the certified
+  // distances (minDistAbs) and of the failing owners' bounds (minLbAbs), as the
+  // bit patterns of non-negative doubles (ordered like the values).
   const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= N) return;
-  if (flat[o]) {
-    best[o] = kEmptyKey;
-    return;
-  }
-  const int nh = hn[o];
-  const double xo = xs[o], dx = xs[o + L - 1] - xo;
-  const double Ao = A[o], io = invn[o];
-  uint64_t kb = kEmptyKey;
-  double rb = -2.0;
-  for (int r = 0; r < nh; ++r) {
-    const int64_t c = hc[o * p + r];
-    if (c >= N) continue;  // no window of length L at c (nor at any longer length)
-    const double S = fma(dx, xs[c + L - 1] - xs[c], hS[o * p + r]);
-    hS[o * p + r] = S;
-    if (iabs64(c - o) <= e || flat[c]) continue;
-    const double rho = rho_from_sum(S, Ao, A[c], L, io, invn[c]);
-    const uint64_t k = make_key(rho, c);
-    if (k < kb) {
-      kb = k;
-      rb = rho;
-    }
-  }
+  const bool live = o < N;
+  const bool owner = live && !flat[o];
+  if (live && !owner) best[o] = kEmptyKey;
   bool valid = false;
-  if (kb != kEmptyKey && hsig[o] > 0.0) {
-    const double u = 1.0 - rb;
-    const double min_dist = sqrt(2.0 * (double)L * (u > 0.0 ? u : 0.0));
-    if (hbound[o] < -2.5) {
-      valid = true;  // complete profile: no candidate was left out
-    } else {
-      const double q = hbound[o] > 0.0 ? (hbound[o] < 1.0 ? hbound[o] : 1.0) : 0.0;
-      const double max_lb = sqrt((double)base * (1.0 - q * q)) * hsig[o] / sig[o];
-      valid = min_dist < max_lb * (1.0 - 1.0e-9);
+  double min_d = INFINITY, max_lb = 0.0;
+  uint64_t kb = kEmptyKey;
+  if (owner) {
+    const int nh = hn[o];
+    const double xo = xs[o], dx = xs[o + L - 1] - xo;
+    const double Ao = A[o], io = invn[o];
+    double rb = -2.0;
+    for (int r = 0; r < nh; ++r) {
+      const int64_t c = hc[o * p + r];
+      if (c >= N) continue;  // no window of length L at c (nor at any longer length)
+      const double S = fma(dx, xs[c + L - 1] - xs[c], hS[o * p + r]);
+      hS[o * p + r] = S;
+      if (iabs64(c - o) <= e || flat[c]) continue;
+      const double rho = rho_from_sum(S, Ao, A[c], L, io, invn[c]);
+      const uint64_t k = make_key(rho, c);
+      if (k < kb) {
+        kb = k;
+        rb = rho;
+      }
+    }
+    if (hsig[o] > 0.0) {
+      if (hbound[o] < -2.5) {
+        max_lb = INFINITY;  // complete profile: no candidate was left out
+      } else {
+        const double q = hbound[o] > 0.0 ? (hbound[o] < 1.0 ? hbound[o] : 1.0) : 0.0;
+        max_lb = sqrt((double)base * (1.0 - q * q)) * hsig[o] / sig[o];
+      }
+    }
+    if (kb != kEmptyKey) {
+      const double u = 1.0 - rb;
+      min_d = sqrt(2.0 * (double)L * (u > 0.0 ? u : 0.0));
+      valid = hsig[o] > 0.0 && (max_lb == INFINITY || min_d < max_lb * (1.0 - 1.0e-9));
+    }
+    best[o] = valid ? kb : kEmptyKey;
+    if (!valid && lbm) lbm[o] = max_lb < INFINITY ? max_lb : 0.0;
+  }
+  count_wave(valid, nvalid);
+  push_fail_wave(owner && !valid, fail, nfail, o);
+  if (min_dist) {
+    uint64_t a = valid ? (uint64_t)__double_as_longlong(min_d) : kEmptyKey;
+    uint64_t b = (owner && !valid && max_lb < INFINITY) ? (uint64_t)__double_as_longlong(max_lb) : kEmptyKey;
+    a = wave_min_u64(a);
+    b = wave_min_u64(b);
+    if ((threadIdx.x % kWave) == 0) {
+      if (a != kEmptyKey) atomicMin(min_dist, (unsigned long long)a);
+      if (b != kEmptyKey) atomicMin(min_lb, (unsigned long long)b);
     }
   }
-  best[o] = valid ? kb : kEmptyKey;
-  count_wave(valid, nvalid);
-  push_fail_wave(!valid, fail, nfail, o);
+}
+
+// Alg. ComputeSubMP after a failed bound test: the failing owners whose bound is
+// below the best certified distance (`limit`, bits of a non-negative double) are
+// listed for the row recompute; the others stay partial (their profile entry is
+// not computed at this length).
+__global__ void k_split_fail(const int32_t* __restrict__ fail, const unsigned long long* __restrict__ nfail,
+                             const double* __restrict__ lbm, const unsigned long long* __restrict__ limit,
+                             int all_partial, int32_t* __restrict__ rec, unsigned long long* __restrict__ nrec,
+                             int32_t* __restrict__ part, unsigned long long* __restrict__ npart) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t count = (int64_t)*nfail;
+  const bool live = w < count;
+  const int64_t o = live ? fail[w] : 0;
+  const double lim = __longlong_as_double((long long)*limit);
+  const bool r = live && !all_partial && lbm[o] < lim;
+  push_fail_wave(r, rec, nrec, o);
+  push_fail_wave(live && !r, part, npart, o);
+}
+
+// Partial entries: index -2 and, as distance, the lower bound of the entry.
+__global__ void k_mark_partial(const int32_t* __restrict__ part, const unsigned long long* __restrict__ npart,
+                               const double* __restrict__ lbm, double* __restrict__ prof_dist,
+                               int32_t* __restrict__ prof_idx) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= (int64_t)*npart) return;
+  const int64_t o = part[w];
+  if (prof_dist) prof_dist[o] = lbm[o];
+  if (prof_idx) prof_idx[o] = -2;
 }
 
 // --------------------------------------------------------------------------
@@ -447,10 +495,27 @@ hipError_t launch_merge(const double* xs, const double* A, const double* invn, c
 hipError_t launch_sweep(const double* xs, const double* A, const double* invn, const double* sig, const uint8_t* flat,
                         int64_t N, int L, int64_t e, int p, int base, const int32_t* hc, double* hS, const int32_t* hn,
                         const double* hbound, const double* hsig, uint64_t* best, int32_t* fail,
-                        unsigned long long* nfail, unsigned long long* nvalid, hipStream_t st) {
+                        unsigned long long* nfail, unsigned long long* nvalid, double* lbm,
+                        unsigned long long* min_dist, unsigned long long* min_lb, hipStream_t st) {
   if (N <= 0) return hipSuccess;
   k_sweep<<<blocks_for(N, 128), 128, 0, st>>>(xs, A, invn, sig, flat, N, L, e, p, base, hc, hS, hn, hbound, hsig,
-                                               best, fail, nfail, nvalid);
+                                               best, fail, nfail, nvalid, lbm, min_dist, min_lb);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_fail(const int32_t* fail, const unsigned long long* nfail, int64_t max_listed,
+                             const double* lbm, const unsigned long long* limit, int all_partial, int32_t* rec,
+                             unsigned long long* nrec, int32_t* part, unsigned long long* npart, hipStream_t st) {
+  if (max_listed <= 0) return hipSuccess;
+  k_split_fail<<<blocks_for(max_listed, 256), 256, 0, st>>>(fail, nfail, lbm, limit, all_partial, rec, nrec, part,
+                                                             npart);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_partial(const int32_t* part, const unsigned long long* npart, int64_t max_listed,
+                               const double* lbm, double* prof_dist, int32_t* prof_idx, hipStream_t st) {
+  if (max_listed <= 0) return hipSuccess;
+  k_mark_partial<<<blocks_for(max_listed, 256), 256, 0, st>>>(part, npart, lbm, prof_dist, prof_idx);
   return hipGetLastError();
 }
 

@@ -20,6 +20,10 @@ enum CounterSlot {
   CNT_VALID = 6,     // owners certified by the sweep
   CNT_HARD = 7,      // FP32 work items listed for the FP64 kernel
   CNT_BIG = 8,       // owners listed for the wavefront-per-owner merge
+  CNT_MINDIST = 9,   // paper mode: minimum certified distance (bits of a double)
+  CNT_MINLB = 10,    // paper mode: minimum bound of the failing owners (bits of a double)
+  CNT_NREC = 11,     // paper mode: owners listed for the row recompute
+  CNT_NPART = 12,    // paper mode: owners left partial
   CNT_WORDS = 32
 };
 
@@ -80,12 +84,15 @@ hipError_t launch_finalize(const double* xs, const double* mu, const double* sig
                            int64_t N, int L, double* prof_dist, int32_t* prof_idx, double* valmp_norm,
                            double* valmp_dist, int32_t* valmp_len, int32_t* valmp_idx, hipStream_t st);
 // Writes one stats row (host-known values and the per-length device counters;
-// `recomputed`: the recompute list was processed at this length) and clears
-// the per-length counters.
+// `recomputed`: 0 none, 1 the recompute list (CNT_NFAIL), 2 the paper-mode list
+// (CNT_NREC)) and clears the per-length counters.
 hipError_t launch_record_stats(unsigned long long* cnt, int64_t* row, int full_pass, int64_t valid,
                                int64_t failed, int recomputed, int64_t passes, hipStream_t st);
-// clears n consecutive counters (a kernel, so that the sequence stays capturable)
-hipError_t launch_zero_counters(unsigned long long* p, int n, hipStream_t st);
+// sets n consecutive counters to v (a kernel, so that the sequence stays capturable)
+hipError_t launch_fill_counters(unsigned long long* p, int n, unsigned long long v, hipStream_t st);
+inline hipError_t launch_zero_counters(unsigned long long* p, int n, hipStream_t st) {
+  return launch_fill_counters(p, n, 0ull, st);
+}
 hipError_t launch_fill_tail(int64_t from, int64_t to, double* prof_dist, int32_t* prof_idx, hipStream_t st);
 hipError_t launch_valmp_init(int64_t N0, double* norm, double* dist, int32_t* len, int32_t* idx,
                              hipStream_t st);
@@ -108,10 +115,17 @@ hipError_t launch_merge(const double* xs, const double* A, const double* invn, c
                         int p, int keep, double margin, int best_exact, int32_t* hc, double* hS, int32_t* hn,
                         double* hbound, double* hsig, uint64_t* best, int32_t* fail, unsigned long long* nfail,
                         int32_t* big, unsigned long long* nbig, unsigned long long* nappend, hipStream_t st);
+// lbm, min_dist, min_lb: optional (paper mode)
 hipError_t launch_sweep(const double* xs, const double* A, const double* invn, const double* sig, const uint8_t* flat,
                         int64_t N, int L, int64_t e, int p, int base, const int32_t* hc, double* hS, const int32_t* hn,
                         const double* hbound, const double* hsig, uint64_t* best, int32_t* fail,
-                        unsigned long long* nfail, unsigned long long* nvalid, hipStream_t st);
+                        unsigned long long* nfail, unsigned long long* nvalid, double* lbm,
+                        unsigned long long* min_dist, unsigned long long* min_lb, hipStream_t st);
+hipError_t launch_split_fail(const int32_t* fail, const unsigned long long* nfail, int64_t max_listed,
+                             const double* lbm, const unsigned long long* limit, int all_partial, int32_t* rec,
+                             unsigned long long* nrec, int32_t* part, unsigned long long* npart, hipStream_t st);
+hipError_t launch_mark_partial(const int32_t* part, const unsigned long long* npart, int64_t max_listed,
+                               const double* lbm, double* prof_dist, int32_t* prof_idx, hipStream_t st);
 // the list length is read on the device (nfail); max_listed bounds it
 hipError_t launch_recompute(const double* xs, const double* A, const double* invn, const uint8_t* flat,
                             const int32_t* fail, const unsigned long long* nfail, int64_t max_listed, int64_t N,

@@ -206,7 +206,7 @@ __global__ void k_record_stats(unsigned long long* __restrict__ cnt, int64_t* __
   if (row) {
     row[0] = valid;
     row[1] = failed;
-    row[2] = recomputed ? (int64_t)cnt[CNT_NFAIL] : 0;
+    row[2] = recomputed == 2 ? (int64_t)cnt[CNT_NREC] : (recomputed ? (int64_t)cnt[CNT_NFAIL] : 0);
     row[3] = full_pass;
     row[4] = (int64_t)cnt[CNT_NFLAT];
     row[5] = (int64_t)cnt[CNT_APPENDS];
@@ -214,13 +214,15 @@ __global__ void k_record_stats(unsigned long long* __restrict__ cnt, int64_t* __
     row[7] = (int64_t)cnt[CNT_EV_HITS];
     row[8] = (int64_t)cnt[CNT_HARD];
     row[9] = passes;
+    row[10] = (int64_t)cnt[CNT_NPART];
   }
   cnt[CNT_NFLAT] = cnt[CNT_EV_STEPS] = cnt[CNT_EV_HITS] = cnt[CNT_APPENDS] = 0;
   cnt[CNT_NFAIL] = cnt[CNT_VALID] = cnt[CNT_HARD] = cnt[CNT_BIG] = 0;
+  cnt[CNT_NREC] = cnt[CNT_NPART] = 0;
 }
 
-__global__ void k_zero_counters(unsigned long long* __restrict__ p, int n) {
-  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+__global__ void k_fill_counters(unsigned long long* __restrict__ p, int n, unsigned long long v) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = v;
 }
 
 __global__ void k_fill_tail(int64_t from, int64_t to, double* __restrict__ prof_dist,
@@ -528,9 +530,9 @@ hipError_t launch_record_stats(unsigned long long* cnt, int64_t* row, int full_p
   return hipGetLastError();
 }
 
-hipError_t launch_zero_counters(unsigned long long* p, int n, hipStream_t st) {
+hipError_t launch_fill_counters(unsigned long long* p, int n, unsigned long long v, hipStream_t st) {
   if (n <= 0 || n > 64) return hipErrorInvalidValue;
-  k_zero_counters<<<1, 64, 0, st>>>(p, n);
+  k_fill_counters<<<1, 64, 0, st>>>(p, n, v);
   return hipGetLastError();
 }
 

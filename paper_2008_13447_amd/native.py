@@ -24,10 +24,11 @@ STATUS = {0: "VALMOD_OK", -1: "VALMOD_E_ARG", -2: "VALMOD_E_TOO_SHORT", -3: "VAL
           -4: "VALMOD_E_HIP", -5: "VALMOD_E_LAYOUT", -6: "VALMOD_E_DEVICE"}
 DTYPE = {"f32": 0, "f64": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
+MODE = {"exact": 0, "paper": 1}
 PATH = {"auto": 0, "full": 1, "recompute": 2}
-NSTATS = 10
+NSTATS = 11
 STAT_NAMES = ["valid", "failed", "recomputed", "full_pass", "flat", "appends", "pass_events", "pass_hits",
-              "fp64_items", "passes"]
+              "fp64_items", "passes", "partial"]
 
 # (name, C type) of every function declared in include/valmod.h
 EXPORTS = ["valmod_plan", "valmod_workspace_bytes", "valmod_output_sizes", "valmod_series_layout",
@@ -52,6 +53,7 @@ class ValmodConfig(ctypes.Structure):
         ("device", ctypes.c_int32),
         ("lanes", ctypes.c_int32),
         ("graph", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
     ]
 
 
@@ -128,7 +130,7 @@ def _check(rc: int, where: str):
 def make_config(n: Sequence[int], l_min: Sequence[int], l_max: Sequence[int], p: int = 0,
                 k_motifs: int = 1, k_discords: int = 1, excl_den: int = 4, flat_eps: float = 0.0,
                 dtype: str = "f32", precision: str = "fp64", refresh_R: int = 0, path: str = "auto",
-                device: int = 0, lanes: int = 0, graph: bool = False):
+                device: int = 0, lanes: int = 0, graph: bool = False, mode: str = "exact"):
     """Build a ValmodConfig; returns (config, keepalive arrays)."""
     S = len(n)
     na = (ctypes.c_int64 * S)(*[int(v) for v in n])
@@ -138,7 +140,7 @@ def make_config(n: Sequence[int], l_min: Sequence[int], l_max: Sequence[int], p:
                        ctypes.cast(lo, ctypes.POINTER(ctypes.c_int32)),
                        ctypes.cast(hi, ctypes.POINTER(ctypes.c_int32)), int(p), int(k_motifs),
                        int(k_discords), int(excl_den), float(flat_eps), DTYPE[dtype], PRECISION[precision],
-                       int(refresh_R), PATH[path], int(device), int(lanes), 1 if graph else 0)
+                       int(refresh_R), PATH[path], int(device), int(lanes), 1 if graph else 0, MODE[mode])
     return cfg, (na, lo, hi)
 
 
@@ -208,7 +210,7 @@ class Valmod:
     def __init__(self, series: Union["torch.Tensor", List["torch.Tensor"]], l_min, l_max, p: int = 0,
                  k_motifs: int = 1, k_discords: int = 1, excl_den: int = 4, flat_eps: float = 0.0,
                  precision: str = "fp64", refresh_R: int = 0, path: str = "auto", lanes: int = 0,
-                 graph: bool = False):
+                 graph: bool = False, mode: str = "exact"):
         import torch
 
         if isinstance(series, torch.Tensor):
@@ -225,7 +227,7 @@ class Valmod:
         self.torch = torch
         cfg, self._keep = make_config([s.numel() for s in series], lo, hi, p, k_motifs, k_discords,
                                       excl_den, flat_eps, "f32" if dt == torch.float32 else "f64",
-                                      precision, refresh_R, path, self.device.index or 0, lanes, graph)
+                                      precision, refresh_R, path, self.device.index or 0, lanes, graph, mode)
         self.plan = valmod_plan(cfg)
         self.graph = bool(graph)
         self._stream = None

@@ -75,6 +75,9 @@ def test_plan_validation(lib):
     assert _status(graph=True) == 0 and _status(graph=True, path="full") == 0
     assert _status(graph=True, path="recompute") == -1
     assert _status(graph=True, precision="fp32") == -1
+    # paper mode: automatic path only, no graph
+    assert _status(mode="paper") == 0
+    assert _status(mode="paper", path="full") == -1 and _status(mode="paper", graph=True) == -1
 
 
 def test_lanes_split_the_workspace(lib):

@@ -491,3 +491,22 @@ def test_autotune_keeps_results_exact(oracle_mod, precision):
     v.close()
     r = oracle_mod.valmod(x, lo, hi, k_motifs=3, k_discords=3)
     compare.check_full(x, lo, g, r, TOL64)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("p", [3, 10])
+def test_paper_mode_motif_per_length_exact(oracle_mod, precision, p):
+    """Alg. ComputeSubMP as published: only the failing windows that could hold
+    the motif are recomputed; the motif of every length stays exact, computed
+    entries are exact and the others carry a lower bound."""
+    from oracle import compare
+
+    x = gen.small_random_walk(3000, 96, np.float32)
+    lo, hi = 30, 46
+    g = run_gpu(x, lo, hi, p=p, k_motifs=3, k_discords=3, precision=precision, mode="paper")
+    r = oracle_mod.valmod(x, lo, hi, k_motifs=3, k_discords=3)
+    rep = compare.check_paper_mode(x, lo, g, r, TOL64)
+    st = g["stats"]
+    _say(f"paper mode {precision} p={p}: {dict(rep)}; per-length partial {st[:, 10].tolist()}, "
+         f"recomputed {st[:, 2].tolist()}, full passes {st[:, 3].tolist()}")
+    assert rep["partial_entries"] == int(st[:, 10].sum())
