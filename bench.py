@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="series run concurrently (0: library default)")
     ap.add_argument("--graph", action="store_true", help="capture the run in a HIP graph and replay it")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default pass geometry")
+    ap.add_argument("--mode", default="exact", choices=["exact", "paper"],
+                    help="paper: Alg. ComputeSubMP as published (motif per length exact, other entries may be "
+                         "left uncomputed; the cells/s figure then counts cells not computed)")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"],
                     help="headline path (the other one is timed beside it unless --no-compare)")
     ap.add_argument("--no-compare", action="store_true")
@@ -136,7 +139,7 @@ def main():
         graph = args.graph and precision == "fp64"
         v = native.Valmod(x, lo, hi, p=w.p, k_motifs=w.k_motifs, k_discords=w.k_discords,
                           excl_den=w.excl_den, precision=precision, path="full" if graph else args.path,
-                          lanes=args.lanes, graph=graph)
+                          lanes=args.lanes, graph=graph, mode=args.mode)
         tune = None
         if not args.no_autotune:
             t0 = time.perf_counter()
@@ -170,7 +173,8 @@ def main():
         "config": {"workload": name, "n": w.n if batch is None else sum(b.n for b in batch),
                    "l_min": lo if batch is None else min(lo), "l_max": hi if batch is None else max(hi),
                    "p": w.p, "k": w.k_motifs, "precision": args.precision, "path": args.path,
-                   "lanes": args.lanes, "graph": bool(args.graph and args.precision == "fp64")},
+                   "lanes": args.lanes, "graph": bool(args.graph and args.precision == "fp64"),
+                   "mode": args.mode},
         "roofline": {"bound": "alu", "kernel": f"k_pass<{'double' if args.precision == 'fp64' else 'float'}> "
                      "(diagonal pass)", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": profiled_traffic(args.precision),
