@@ -65,6 +65,10 @@ def _load():
     lib.oracle_pair_dists.restype = ctypes.c_int
     lib.oracle_valid_fraction.argtypes = [P, I64, I64, I64, I64, I64, D, P]
     lib.oracle_valid_fraction.restype = I64
+    lib.oracle_mth_rows.argtypes = [P, I64, I64, I64, D, I64, P, I64, P, P]
+    lib.oracle_mth_rows.restype = ctypes.c_int
+    lib.oracle_mth_discords.argtypes = [P, I64, I64, I64, I64, D, I64, I64, P, P, P, P]
+    lib.oracle_mth_discords.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -184,3 +188,35 @@ def valmod(x, l_min: int, l_max: int, excl_den: int = 4, k_motifs: int = 1, k_di
     if rc != 0:
         raise ValueError("oracle_valmod: bad arguments")
     return o
+
+
+def mth_rows(x, L: int, m: int, rows: Optional[Sequence[int]] = None, excl_den: int = 4,
+             flat_eps: float = FLAT_EPS):
+    """The m smallest distance-profile entries (Def. m-th best match) of each
+    listed owner: (dist[rows, m], idx[rows, m]), +inf / -1 where missing."""
+    x = _f64(x)
+    N = x.shape[0] - L + 1
+    r = None if rows is None else np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+    cnt = N if r is None else r.shape[0]
+    d = np.empty((cnt, m))
+    i = np.empty((cnt, m), dtype=np.int64)
+    rc = _load().oracle_mth_rows(_ptr(x), x.shape[0], L, excl_den, flat_eps, m,
+                                 None if r is None else _ptr(r), cnt, _ptr(d), _ptr(i))
+    if rc != 0:
+        raise ValueError("oracle_mth_rows: invalid arguments")
+    return d, i
+
+
+def mth_discords(x, l_min: int, l_max: int, k: int, m: int, excl_den: int = 4, flat_eps: float = FLAT_EPS):
+    """Top-k m-th discords per length and across lengths (see the C header)."""
+    x = _f64(x)
+    nlen = l_max - l_min + 1
+    on = np.empty((nlen, m, k, 2), dtype=np.int64)
+    d = np.empty((nlen, m, k))
+    g_onl = np.empty((m, k, 3), dtype=np.int64)
+    g_d = np.empty((m, k, 2))
+    rc = _load().oracle_mth_discords(_ptr(x), x.shape[0], l_min, l_max, excl_den, flat_eps, k, m, _ptr(on),
+                                     _ptr(d), _ptr(g_onl), _ptr(g_d))
+    if rc != 0:
+        raise ValueError("oracle_mth_discords: invalid arguments")
+    return {"on": on, "d": d, "g_onl": g_onl, "g_d": g_d}

@@ -42,7 +42,9 @@
  * library on tiny inputs, planted motif / discord recovery, Example 2). The
  * flat rule and the greedy top-k rules are definitions of this build: parity
  * unpinned beyond their special cases (top-1 motif = the motif pair, top-1
- * discord = the 1st discord).
+ * discord = the 1st discord). oracle_mth_rows / oracle_mth_discords follow the
+ * definitions of the m-th best match and of the Top-k m-th discord (pinned
+ * against an independent brute force).
  */
 #include <math.h>
 #include <pthread.h>
@@ -520,6 +522,122 @@ ORACLE_EXPORT int oracle_valmod(const double* x, int64_t n, int64_t l_min, int64
     g_mot_d[2 * got] = g_mot_d[2 * got + 1] = NAN;
   }
   free(c);
+  return 0;
+}
+
+/*
+ * m-th best matches (Def. m-th best match): the m smallest entries of the
+ * distance profile of each listed owner at length L, excluding the owner's
+ * trivial matches (the neighbours may be trivial matches of each other), in
+ * order of (distance, index); missing entries are +inf / -1. Flat owners have
+ * none; flat candidates are skipped. dist[r*m + j], idx[r*m + j].
+ */
+typedef struct {
+  double d;
+  int64_t j;
+} dj_t;
+
+static int cmp_dj(const void* p, const void* q) {
+  const dj_t* u = (const dj_t*)p;
+  const dj_t* v = (const dj_t*)q;
+  if (u->d != v->d) return u->d < v->d ? -1 : 1;
+  return u->j < v->j ? -1 : (u->j > v->j ? 1 : 0);
+}
+
+ORACLE_EXPORT int oracle_mth_rows(const double* x, int64_t n, int64_t L, int64_t excl_den, double flat_eps,
+                                  int64_t m, const int64_t* rows, int64_t nrows, double* dist, int64_t* idx) {
+  int64_t N = n - L + 1;
+  if (L < 2 || N < 1 || excl_den < 1 || m < 1) return -1;
+  double* mu = (double*)malloc(sizeof(double) * N);
+  double* sg = (double*)malloc(sizeof(double) * N);
+  uint8_t* fl = (uint8_t*)malloc(N);
+  dj_t* prof = (dj_t*)malloc(sizeof(dj_t) * N);
+  oracle_stats(x, n, L, flat_eps, mu, sg, fl);
+  int64_t e = excl_zone(L, excl_den);
+  int64_t cnt = rows ? nrows : N;
+  for (int64_t r = 0; r < cnt; r++) {
+    int64_t i = rows ? rows[r] : r;
+    int64_t got = 0;
+    if (i >= 0 && i < N && !fl[i]) {
+      for (int64_t j = 0; j < N; j++) {
+        if (fl[j] || iabs64(i - j) <= e) continue;
+        prof[got].d = sqrt(sqdist(x, L, i, j, mu, sg));
+        prof[got].j = j;
+        got++;
+      }
+      qsort(prof, got, sizeof(dj_t), cmp_dj);
+    }
+    for (int64_t q = 0; q < m; q++) {
+      dist[r * m + q] = q < got ? prof[q].d : INFINITY;
+      idx[r * m + q] = q < got ? prof[q].j : -1;
+    }
+  }
+  free(mu);
+  free(sg);
+  free(fl);
+  free(prof);
+  return 0;
+}
+
+/*
+ * Top-k m-th discords (Defs. m-th discord and Top-k m-th discord), for every
+ * j = 1..m and length L: owners by their j-th best-match distance, descending
+ * (ties to the smaller offset), accepted greedily unless within the exclusion
+ * zone of an owner already accepted for the same j (the rule of the 1st
+ * discords); owners with fewer than j candidates are skipped. Across lengths
+ * (Alg. UpdateVariableLengthDiscords): for each (j, rank) the largest d / sqrt(L),
+ * strictly (the shorter length keeps ties).
+ *   on[((t*m + j)*k + r)*2 + {0,1}] (offset, j-th neighbour), d[(t*m + j)*k + r]
+ *   g_onl[((j*k) + r)*3 + {0,1,2}] (offset, neighbour, L), g_d[(j*k + r)*2 + {0,1}] (d, d/sqrt(L))
+ */
+ORACLE_EXPORT int oracle_mth_discords(const double* x, int64_t n, int64_t l_min, int64_t l_max, int64_t excl_den,
+                                      double flat_eps, int64_t k, int64_t m, int64_t* on, double* d,
+                                      int64_t* g_onl, double* g_d) {
+  if (l_min < 2 || l_max < l_min || excl_den < 1 || k < 1 || m < 1 || n - l_max + 1 < 1) return -1;
+  int64_t nlen = l_max - l_min + 1;
+  for (int64_t t = 0; t < nlen; t++) {
+    int64_t L = l_min + t;
+    int64_t N = n - L + 1;
+    int64_t e = excl_zone(L, excl_den);
+    double* md = (double*)malloc(sizeof(double) * N * m);
+    int64_t* mi = (int64_t*)malloc(sizeof(int64_t) * N * m);
+    double* col = (double*)malloc(sizeof(double) * N);
+    int64_t* nn = (int64_t*)malloc(sizeof(int64_t) * N);
+    oracle_mth_rows(x, n, L, excl_den, flat_eps, m, NULL, N, md, mi);
+    for (int64_t j = 0; j < m; j++) {
+      for (int64_t i = 0; i < N; i++) {
+        col[i] = md[i * m + j];
+        nn[i] = mi[i * m + j];
+      }
+      topk_discords(col, nn, N, e, k, on + (t * m + j) * k * 2, d + (t * m + j) * k);
+    }
+    free(md);
+    free(mi);
+    free(col);
+    free(nn);
+  }
+  for (int64_t j = 0; j < m; j++)
+    for (int64_t r = 0; r < k; r++) {
+      int64_t* go = g_onl + (j * k + r) * 3;
+      double* gd = g_d + (j * k + r) * 2;
+      go[0] = go[1] = go[2] = -1;
+      gd[0] = gd[1] = NAN;
+      double best = -INFINITY;
+      for (int64_t t = 0; t < nlen; t++) {
+        double v = d[(t * m + j) * k + r];
+        if (!(v == v)) continue;
+        int64_t L = l_min + t;
+        double dn = v / sqrt((double)L);
+        if (dn > best) {
+          best = dn;
+          go[0] = on[((t * m + j) * k + r) * 2];
+          go[1] = on[((t * m + j) * k + r) * 2 + 1];
+          go[2] = L;
+          gd[0] = v;
+          gd[1] = dn;
+        }
+      }
+    }
   return 0;
 }
 

@@ -288,3 +288,80 @@ def test_valid_heaps_give_exact_minimum(oracle_mod):
                 assert np.isclose(DL[o, order].min(), dL[o], rtol=1e-9)
         v, nv = oracle_mod.valid_fraction(x, b, L, 10 ** 6)
         assert nv == (v != 2).sum()
+
+
+def _brute_dist_matrix(x, L, excl_den=4):
+    """Independent brute force: z-normalised windows, all pair distances, trivial
+    matches masked with +inf."""
+    Z = _windows(x, L)
+    Z = (Z - Z.mean(axis=1, keepdims=True)) / Z.std(axis=1, keepdims=True)
+    D = cdist(Z, Z)
+    N = D.shape[0]
+    e = -(-L // excl_den)
+    ii = np.arange(N)
+    D[np.abs(ii[:, None] - ii[None, :]) <= e] = np.inf
+    return D
+
+
+@pytest.mark.parametrize("m", [1, 3])
+def test_mth_best_matches_vs_brute_force(oracle_mod, m):
+    """Def. m-th best match: the m smallest entries of each distance profile,
+    excluding the owner's trivial matches; j-th distances never decrease with j."""
+    x = gen.small_random_walk(260, 31)
+    L = 18
+    D = _brute_dist_matrix(x, L)
+    d, i = oracle_mod.mth_rows(x, L, m)
+    order = np.lexsort((np.broadcast_to(np.arange(D.shape[1]), D.shape), D), axis=1)[:, :m]
+    ref = np.take_along_axis(D, order, axis=1)
+    np.testing.assert_allclose(d, ref, rtol=0, atol=1e-10)
+    assert np.all(np.diff(d, axis=1) >= 0)
+    # indices equal except between ties
+    diff = i != order
+    assert np.all(np.abs(d[diff] - ref[diff]) <= 1e-10)
+    if m == 1:
+        d1, i1 = oracle_mod.profile(x, L)
+        np.testing.assert_allclose(d[:, 0], d1, rtol=0, atol=1e-12)
+
+
+def test_mth_discords_vs_brute_force(oracle_mod):
+    """Top-k m-th discords: for each j the owners by j-th best-match distance,
+    greedy with the exclusion zone; across lengths the largest d / sqrt(L)."""
+    x = gen.small_random_walk(240, 32)
+    lo, hi, k, m = 16, 19, 3, 3
+    r = oracle_mod.mth_discords(x, lo, hi, k, m)
+    best = {}
+    for t, L in enumerate(range(lo, hi + 1)):
+        D = _brute_dist_matrix(x, L)
+        S = np.sort(D, axis=1)
+        e = -(-L // 4)
+        for j in range(m):
+            v = S[:, j]
+            order = sorted(range(len(v)), key=lambda o: (-v[o], o))
+            got = []
+            for o in order:
+                if not np.isfinite(v[o]):
+                    continue
+                if all(abs(o - g) > e for g in got):
+                    got.append(o)
+                if len(got) == k:
+                    break
+            for rank, o in enumerate(got):
+                assert r["on"][t, j, rank, 0] == o, (L, j, rank)
+                assert abs(r["d"][t, j, rank] - v[o]) <= 1e-10
+                nn = r["on"][t, j, rank, 1]
+                assert abs(D[o, nn] - v[o]) <= 1e-10  # the reported neighbour is at that distance
+                dn = v[o] / np.sqrt(L)
+                if (j, rank) not in best or dn > best[(j, rank)][0]:
+                    best[(j, rank)] = (dn, o, L)
+    for (j, rank), (dn, o, L) in best.items():
+        assert abs(r["g_d"][j, rank, 1] - dn) <= 1e-12
+        assert tuple(r["g_onl"][j, rank, [0, 2]]) == (o, L)
+
+
+def test_first_discords_special_case(oracle_mod):
+    """m = 1 reduces to the 1st discords of the full run."""
+    x = gen.small_random_walk(300, 33)
+    r = oracle_mod.mth_discords(x, 20, 24, 3, 1)
+    v = oracle_mod.valmod(x, 20, 24, k_motifs=1, k_discords=3)
+    np.testing.assert_array_equal(r["on"][:, 0, :, 0], v["discord_on"][:, :, 0])
+    np.testing.assert_allclose(r["d"][:, 0], v["discord_d"], rtol=0, atol=1e-12)
