@@ -119,6 +119,8 @@ typedef struct {
                                later calls with the same buffers and stream; implies VALMOD_PATH_FULL
                                (VALMOD_PATH_RECOMPUTE is rejected); FP64 precision only */
   int32_t mode;             /* valmod_mode; VALMOD_MODE_PAPER needs VALMOD_PATH_AUTO and no graph */
+  int32_t m_discords;       /* m of the Top-k m-th discords (0 or 1: only the 1st discords); m > 1 needs
+                               m <= 16, m <= p, exact mode and no graph, and the mdiscord outputs */
 } valmod_config;
 
 typedef struct valmod_plan_s* valmod_plan_t;
@@ -154,6 +156,11 @@ enum {
  *   g_motif_abl[r * 3 + {0,1,2}] i32 (a, b, L), g_motif_d[r * 2 + {0,1}] f64 (d, d*sqrt(1/L))
  *   g_discord_onl[r * 3 + {0,1,2}] i32 (offset, neighbour, L), g_discord_d[r * 2 + {0,1}] f64 (d, d/sqrt(L))
  *   stats[t * VALMOD_NSTATS + c] i64
+ *   with m = m_discords > 1 (Defs. m-th best match and Top-k m-th discord; j = 0..m-1 is the
+ *   (j+1)-th best match, the neighbours may be trivial matches of each other):
+ *   mdiscord_on[((t * m + j) * k_d + r) * 2 + {0,1}] i32 (offset, (j+1)-th neighbour),
+ *   mdiscord_d[(t * m + j) * k_d + r] f64, g_mdiscord_onl[(j * k_d + r) * 3 + {0,1,2}] i32 (offset,
+ *   neighbour, L), g_mdiscord_d[(j * k_d + r) * 2 + {0,1}] f64 (d, d/sqrt(L)); unused slots -1 / NaN
  */
 typedef struct {
   double* prof_dist;
@@ -171,6 +178,10 @@ typedef struct {
   int32_t* g_discord_onl;
   double* g_discord_d;
   int64_t* stats;
+  int32_t* mdiscord_on;    /* m_discords > 1 only (else ignored) */
+  double* mdiscord_d;
+  int32_t* g_mdiscord_onl;
+  double* g_mdiscord_d;
 } valmod_outputs;
 
 /* Element counts of every output array over the whole batch. */
@@ -183,6 +194,8 @@ typedef struct {
   int64_t g_discord;  /* rows of g_discord_* */
   int64_t stats;      /* stats */
   int64_t series;     /* elements of the concatenated input series */
+  int64_t mdiscord;   /* mdiscord_d (mdiscord_on holds 2x); 0 unless m_discords > 1 */
+  int64_t g_mdiscord; /* rows of g_mdiscord_* */
 } valmod_sizes;
 
 /* Element offsets of series s inside the concatenated input and each output. */
@@ -197,6 +210,8 @@ typedef struct {
   int64_t stats;
   int64_t n, n0, nlen;
   int32_t l_min, l_max;
+  int64_t mdiscord;
+  int64_t g_mdiscord;
 } valmod_layout;
 
 /* Validate a configuration and build a plan (host only; touches no GPU). The

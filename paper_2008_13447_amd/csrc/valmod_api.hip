@@ -23,7 +23,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
   size_t xs, A, B, mu, sig, invn, flat, df, dg, sw32, thr, thr32, best, counters, anc;
-  size_t hc, hS, hn, hbound, hsig, acnt, abuf, fail, big, lbm, rec, part;
+  size_t hc, hS, hn, hbound, hsig, acnt, abuf, fail, big, lbm, rec, part, mvals, mnn, mkeys;
   size_t df32, dg32, inv32, bsw_max, bsw_min, bdf_max, bdg_max, delta, hard;
   size_t total;
 };
@@ -175,6 +175,12 @@ static size_t layout_lane(const valmod_plan_s* P, Lane& ln) {
   w.abuf = take((size_t)ln.n0max * (size_t)P->cap * 4);
   w.fail = take(wp * 4);
   w.big = take(wp * 4);
+  if (P->cfg.m_discords > 1) {
+    const size_t md = (size_t)P->cfg.m_discords;
+    w.mvals = take(md * wp * 8);
+    w.mnn = take(md * wp * 4);
+    w.mkeys = take(md * wp * 8);
+  }
   if (P->cfg.mode == VALMOD_MODE_PAPER) {
     w.lbm = take(wp * 8);
     w.rec = take(wp * 4);
@@ -241,6 +247,8 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
   // capture of the FP32 path (second stream per lane, collecting pass and merge) is not supported
   if (cfg->graph && cfg->precision == VALMOD_PREC_FP32_REFRESH) return fail(VALMOD_E_ARG);
   if (cfg->mode != VALMOD_MODE_EXACT && cfg->mode != VALMOD_MODE_PAPER) return fail(VALMOD_E_ARG);
+  if (cfg->m_discords < 0 || cfg->m_discords > 16) return fail(VALMOD_E_ARG);
+  if (cfg->m_discords > 1 && (cfg->mode != VALMOD_MODE_EXACT || cfg->graph)) return fail(VALMOD_E_ARG);
   if (cfg->mode == VALMOD_MODE_PAPER && (cfg->path != VALMOD_PATH_AUTO || cfg->graph)) return fail(VALMOD_E_ARG);
 
   valmod_plan_s* P = new (std::nothrow) valmod_plan_s();
@@ -250,6 +258,12 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
   if (P->cfg.excl_den == 0) P->cfg.excl_den = 4;
   if (P->cfg.flat_eps == 0.0) P->cfg.flat_eps = 1.0 / 1048576.0;
   if (P->cfg.graph) P->cfg.path = VALMOD_PATH_FULL;
+  if (P->cfg.m_discords < 1) P->cfg.m_discords = 1;
+  if (P->cfg.m_discords > P->cfg.p) {
+    delete P;
+    return fail(VALMOD_E_ARG);
+  }
+  const int64_t md = P->cfg.m_discords;
   const int S = cfg->num_series;
   try {
     P->n.assign(cfg->n, cfg->n + S);
@@ -295,6 +309,8 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
     L.g_motif = z.g_motif;
     L.g_discord = z.g_discord;
     L.stats = z.stats;
+    L.mdiscord = z.mdiscord;
+    L.g_mdiscord = z.g_mdiscord;
     L.n = n;
     L.n0 = n0;
     L.nlen = nlen;
@@ -308,6 +324,10 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
     z.g_motif += km;
     z.g_discord += kd;
     z.stats += nlen * VALMOD_NSTATS;
+    if (md > 1) {
+      z.mdiscord += nlen * md * kd;
+      z.g_mdiscord += md * kd;
+    }
     for (int64_t Lx = lo; Lx <= hi; ++Lx) cost[s] += (double)(n - Lx + 1) * (double)(n - Lx + 1);
   }
   const size_t pp = (size_t)P->cfg.p;
@@ -442,7 +462,9 @@ struct LaneRun {
   float *sw32, *thr32, *df32, *dg32, *inv32, *bsw_max, *bsw_min, *bdf_max, *bdg_max, *delta;
   uint64_t* best;
   unsigned long long* cnt;
-  int32_t *hc, *hn, *abuf, *fail, *big, *hard, *rec, *part;
+  int32_t *hc, *hn, *abuf, *fail, *big, *hard, *rec, *part, *mnn;
+  double* mvals;
+  uint64_t* mkeys;
   uint32_t* acnt;
   // state
   size_t si = 0;
@@ -483,6 +505,10 @@ struct LaneRun {
     abuf = (int32_t*)(b + w.abuf);
     fail = (int32_t*)(b + w.fail);
     big = (int32_t*)(b + w.big);
+    const bool mth = P->cfg.m_discords > 1;
+    mvals = mth ? (double*)(b + w.mvals) : nullptr;
+    mnn = mth ? (int32_t*)(b + w.mnn) : nullptr;
+    mkeys = mth ? (uint64_t*)(b + w.mkeys) : nullptr;
     const bool paper = P->cfg.mode == VALMOD_MODE_PAPER;
     lbm = paper ? (double*)(b + w.lbm) : nullptr;
     rec = paper ? (int32_t*)(b + w.rec) : nullptr;
@@ -531,7 +557,8 @@ LaneRun::Status LaneRun::advance() {
     LCHECK(launch_convert(series, P->cfg.dtype, n, n + kPad, xs, (int*)&cnt[CNT_ERR], st));
     LCHECK(launch_valmp_init(N0, vnorm, vdist, vlen, vidx, st));
     // partial profiles are used unless every length is forced through a full pass
-    heaps_on = P->cfg.path != VALMOD_PATH_FULL && Ls.l_max > Ls.l_min;
+    // (the m-th discords keep exact top-m lists at every length instead)
+    heaps_on = P->cfg.path != VALMOD_PATH_FULL && Ls.l_max > Ls.l_min && P->cfg.m_discords == 1;
     base = 0;            // base length of the current partial profiles (0: none)
     probe_next = false;  // judge the partial profiles at the first length after a rebuild
     L = Ls.l_min;
@@ -709,9 +736,10 @@ LaneRun::Status LaneRun::advance() {
     }
     probe_next = false;
   }
+  const int md = P->cfg.m_discords;
   if (full) {
     const int32_t* src = prev;
-    if (L == Ls.l_min || (!fp32 && !rebuild)) {
+    if (L == Ls.l_min || (!fp32 && !rebuild && md == 1)) {
       // exact FP64 matrix-profile pass: running best keys seeded from the previous length
       LCHECK(launch_seed_mp(xs, mu, invn, flat, prev, N, L, e, best, thr, thr32, st));
       PassLaunch q = pl;
@@ -722,7 +750,7 @@ LaneRun::Status LaneRun::advance() {
       } else {
         LCHECK(timed_pass(q));
       }
-      if (rebuild) {  // first length: the exact neighbours seed the collecting pass
+      if (rebuild || md > 1) {  // first length: the exact neighbours seed the collecting pass
         LCHECK(launch_keys_to_idx(best, N, pi, st));
         src = pi;
       }
@@ -732,6 +760,9 @@ LaneRun::Status LaneRun::advance() {
       LCHECK(collect(src, p, p, L == Ls.l_min ? 1 : 0));
       base = L;
       probe_next = true;
+    } else if (md > 1) {
+      // exact top-m lists of every owner (Def. m-th best match)
+      LCHECK(collect(src, md, md, 0));
     } else if (fp32 && L > Ls.l_min) {
       // exact neighbours from an FP32 collecting pass seeded by the previous length
       LCHECK(collect(src, 1, 0, 0));
@@ -742,8 +773,19 @@ LaneRun::Status LaneRun::advance() {
                              &cnt[CNT_NREC], part, &cnt[CNT_NPART], st));
     if (paper_split == 1) LCHECK(launch_recompute(xs, A, invn, flat, rec, &cnt[CNT_NREC], N, N, L, e, best, st));
   }
-  if (recompute) LCHECK(launch_recompute(xs, A, invn, flat, fail, &cnt[CNT_NFAIL], N, N, L, e, best, st));
+  if (recompute && md > 1)
+    LCHECK(launch_recompute_topm(xs, A, invn, flat, fail, &cnt[CNT_NFAIL], N, N, L, e, md, p, mkeys, hc, hS, hn, best,
+                                 st));
+  else if (recompute)
+    LCHECK(launch_recompute(xs, A, invn, flat, fail, &cnt[CNT_NFAIL], N, N, L, e, best, st));
   LCHECK(launch_finalize(xs, mu, sig, best, N, L, pd, pi, vnorm, vdist, vlen, vidx, st));
+  if (md > 1) {
+    const int kd = P->cfg.k_discords;
+    const int64_t at = Ls.mdiscord + t * md * kd;
+    LCHECK(launch_mth_values(A, invn, flat, hc, hS, hn, p, md, N, N0, L, mvals, mnn, st));
+    LCHECK(launch_mth_rankings(mvals, mnn, N0, n, L, md, excl_den, kd, o->mdiscord_on + 2 * at, o->mdiscord_d + at,
+                               st));
+  }
   if (paper_split) LCHECK(launch_mark_partial(part, &cnt[CNT_NPART], N, lbm, pd, pi, st));
   LCHECK(launch_fill_tail(N, N0, pd, pi, st));
   LCHECK(launch_record_stats(cnt, o->stats ? o->stats + Ls.stats + t * VALMOD_NSTATS : nullptr, full ? 1 : 0,
@@ -766,6 +808,10 @@ LaneRun::Status LaneRun::advance() {
                               (int)Ls.nlen, Ls.l_min, excl_den, km, kd, o->g_motif_abl + 3 * Ls.g_motif,
                               o->g_motif_d + 2 * Ls.g_motif, o->g_discord_onl + 3 * Ls.g_discord,
                               o->g_discord_d + 2 * Ls.g_discord, st));
+    if (md > 1)
+      LCHECK(launch_mth_global(o->mdiscord_on + 2 * Ls.mdiscord, o->mdiscord_d + Ls.mdiscord, (int)Ls.nlen, Ls.l_min,
+                               md, kd, o->g_mdiscord_onl + 3 * Ls.g_mdiscord, o->g_mdiscord_d + 2 * Ls.g_mdiscord,
+                               st));
     open = false;
     ++si;
   }
@@ -843,6 +889,8 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
   if (!o->prof_dist || !o->prof_idx || !o->valmp_norm || !o->valmp_dist || !o->valmp_len || !o->valmp_idx ||
       !o->motif_ab || !o->motif_d || !o->discord_on || !o->discord_d || !o->g_motif_abl || !o->g_motif_d ||
       !o->g_discord_onl || !o->g_discord_d)
+    return VALMOD_E_ARG;
+  if (P->cfg.m_discords > 1 && (!o->mdiscord_on || !o->mdiscord_d || !o->g_mdiscord_onl || !o->g_mdiscord_d))
     return VALMOD_E_ARG;
   hipStream_t st = (hipStream_t)stream_;
   valmod_status status = VALMOD_OK;
@@ -963,6 +1011,12 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
   so.g_discord_onl += 3 * Ls.g_discord;
   so.g_discord_d += 2 * Ls.g_discord;
   if (so.stats) so.stats += Ls.stats;
+  if (P->cfg.m_discords > 1) {
+    so.mdiscord_on += 2 * Ls.mdiscord;
+    so.mdiscord_d += Ls.mdiscord;
+    so.g_mdiscord_onl += 3 * Ls.g_mdiscord;
+    so.g_mdiscord_d += 2 * Ls.g_mdiscord;
+  }
   const void* sub_series = (const char*)d_series + (size_t)Ls.series * esz;
   double best_ms = -1.0;
   std::pair<int, int32_t> best = {P->tune_hmul, P->tune_R};

@@ -452,6 +452,118 @@ __global__ __launch_bounds__(1024) void k_sum_counts(const uint32_t* __restrict_
   }
 }
 
+// --------------------------------------------------------------------------
+// Top-m row recompute (m-th best matches of the listed owners): round j keeps,
+// for each listed owner, the smallest key strictly above the owner's key of
+// round j - 1, so m rounds give the m best candidates in key order. Same
+// decomposition as k_recompute; out[o * m + j] must be empty before round j.
+__global__ __launch_bounds__(kWave) void k_recompute_round(const double* __restrict__ xs, const double* __restrict__ A,
+                                                           const double* __restrict__ invn,
+                                                           const uint8_t* __restrict__ flat,
+                                                           const int32_t* __restrict__ fail,
+                                                           const unsigned long long* __restrict__ nfail, int64_t N,
+                                                           int L, int64_t e, int m, int j,
+                                                           uint64_t* __restrict__ keys) {
+  const int64_t count = (int64_t)*nfail;
+  const int t = threadIdx.x;
+  const int64_t c0 = ((int64_t)blockIdx.x * kWave + t) * kRecK;
+  for (int64_t w = blockIdx.y; w < count; w += gridDim.y) {
+    const int64_t o = fail[w];
+    const uint64_t floor_key = j > 0 ? keys[o * m + j - 1] : 0;
+    uint64_t kb = kEmptyKey;
+    if (c0 < N && !flat[o] && (j == 0 || floor_key != kEmptyKey)) {
+      double S[kRecK];
+      direct_anchors<kRecK>(xs, o, c0 - o, L, S);
+      const double Ao = A[o], io = invn[o];
+#pragma unroll
+      for (int q = 0; q < kRecK; ++q) {
+        const int64_t c = c0 + q;
+        if (c >= N || iabs64(c - o) <= e || flat[c]) continue;
+        const uint64_t k = make_key(rho_from_sum(S[q], Ao, A[c], L, io, invn[c]), c);
+        if (j > 0 && k <= floor_key) continue;
+        kb = k < kb ? k : kb;
+      }
+    }
+    kb = wave_min_u64(kb);
+    if (t == 0 && kb != kEmptyKey) atomicMin((unsigned long long*)&keys[o * m + j], (unsigned long long)kb);
+  }
+}
+
+// empties the m keys of every listed owner
+__global__ void k_clear_keys(const int32_t* __restrict__ fail, const unsigned long long* __restrict__ nfail, int m,
+                             uint64_t* __restrict__ keys) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= (int64_t)*nfail) return;
+  const int64_t o = fail[w];
+  for (int j = 0; j < m; ++j) keys[o * m + j] = kEmptyKey;
+}
+
+// the recomputed lists become the owners' top-m lists (anchored sums formed directly)
+__global__ void k_topm_store(const double* __restrict__ xs, const int32_t* __restrict__ fail,
+                             const unsigned long long* __restrict__ nfail, int L, int m, int p,
+                             const uint64_t* __restrict__ keys, int32_t* __restrict__ hc, double* __restrict__ hS,
+                             int32_t* __restrict__ hn, uint64_t* __restrict__ best) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= (int64_t)*nfail) return;
+  const int64_t o = fail[w];
+  int cnt = 0;
+  for (int j = 0; j < m; ++j) {
+    const uint64_t k = keys[o * m + j];
+    if (k == kEmptyKey) break;
+    const int64_t c = key_cand(k);
+    hc[o * p + j] = (int32_t)c;
+    hS[o * p + j] = cross_sum(xs, L, o, c);
+    ++cnt;
+  }
+  hn[o] = cnt;
+  best[o] = keys[o * m];
+}
+
+// j-th best-match distances of every owner from its exact top-m list
+// (d = sqrt(2 L (1 - rho)), Eq. 6), column-major: vals[j * N0 + o]
+__global__ void k_mth_values(const double* __restrict__ A, const double* __restrict__ invn,
+                             const uint8_t* __restrict__ flat, const int32_t* __restrict__ hc,
+                             const double* __restrict__ hS, const int32_t* __restrict__ hn, int p, int m, int64_t N,
+                             int64_t N0, int L, double* __restrict__ vals, int32_t* __restrict__ nn) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= N) return;
+  const int cnt = flat[o] ? 0 : hn[o];
+  for (int j = 0; j < m; ++j) {
+    double d = INFINITY;
+    int32_t c = -1;
+    if (j < cnt) {
+      c = hc[o * p + j];
+      const double rho = rho_from_sum(hS[o * p + j], A[o], A[c], L, invn[o], invn[c]);
+      const double u = 1.0 - rho;
+      d = sqrt(2.0 * (double)L * (u > 0.0 ? u : 0.0));
+    }
+    vals[(int64_t)j * N0 + o] = d;
+    nn[(int64_t)j * N0 + o] = c;
+  }
+}
+
+hipError_t launch_recompute_topm(const double* xs, const double* A, const double* invn, const uint8_t* flat,
+                                 const int32_t* fail, const unsigned long long* nfail, int64_t max_listed, int64_t N,
+                                 int L, int64_t e, int m, int p, uint64_t* keys, int32_t* hc, double* hS, int32_t* hn,
+                                 uint64_t* best, hipStream_t st) {
+  if (max_listed <= 0 || N <= 0) return hipSuccess;
+  if (m < 1 || m > p) return hipErrorInvalidValue;
+  k_clear_keys<<<blocks_for(max_listed, 256), 256, 0, st>>>(fail, nfail, m, keys);
+  const dim3 grid(blocks_for(N, kWave * kRecK), (unsigned)(max_listed < 32 ? max_listed : 32));
+  for (int j = 0; j < m; ++j)
+    k_recompute_round<<<grid, kWave, 0, st>>>(xs, A, invn, flat, fail, nfail, N, L, e, m, j, keys);
+  k_topm_store<<<blocks_for(max_listed, 256), 256, 0, st>>>(xs, fail, nfail, L, m, p, keys, hc, hS, hn, best);
+  return hipGetLastError();
+}
+
+hipError_t launch_mth_values(const double* A, const double* invn, const uint8_t* flat, const int32_t* hc,
+                             const double* hS, const int32_t* hn, int p, int m, int64_t N, int64_t N0, int L,
+                             double* vals, int32_t* nn, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  k_mth_values<<<blocks_for(N, 256), 256, 0, st>>>(A, invn, flat, hc, hS, hn, p, m, N, N0, L, vals, nn);
+  return hipGetLastError();
+}
+
 hipError_t launch_seed_append(const double* xs, const double* A, const double* invn, const uint8_t* flat,
                               const int32_t* src, int64_t N, int L, int64_t e, int p, int D, double margin,
                               int best_exact, double* thr, uint32_t* cnt, int32_t* fail, unsigned long long* nfail,

@@ -130,6 +130,20 @@ hipError_t launch_mark_partial(const int32_t* part, const unsigned long long* np
 hipError_t launch_recompute(const double* xs, const double* A, const double* invn, const uint8_t* flat,
                             const int32_t* fail, const unsigned long long* nfail, int64_t max_listed, int64_t N,
                             int L, int64_t e, uint64_t* best, hipStream_t st);
+// m-th best matches: top-m row recompute of the listed owners (keys: scratch of
+// m keys per window), the j-th best-match distances of every owner, their
+// rankings per length and across lengths
+hipError_t launch_recompute_topm(const double* xs, const double* A, const double* invn, const uint8_t* flat,
+                                 const int32_t* fail, const unsigned long long* nfail, int64_t max_listed, int64_t N,
+                                 int L, int64_t e, int m, int p, uint64_t* keys, int32_t* hc, double* hS, int32_t* hn,
+                                 uint64_t* best, hipStream_t st);
+hipError_t launch_mth_values(const double* A, const double* invn, const uint8_t* flat, const int32_t* hc,
+                             const double* hS, const int32_t* hn, int p, int m, int64_t N, int64_t N0, int L,
+                             double* vals, int32_t* nn, hipStream_t st);
+hipError_t launch_mth_rankings(const double* vals, const int32_t* nn, int64_t N0, int64_t n, int L, int m,
+                               int excl_den, int kd, int32_t* on, double* d, hipStream_t st);
+hipError_t launch_mth_global(const int32_t* on, const double* d, int nlen, int l_min, int m, int kd,
+                             int32_t* g_onl, double* g_d, hipStream_t st);
 // copies best keys into an int32 index array (-1 for empty keys)
 hipError_t launch_keys_to_idx(const uint64_t* best, int64_t N, int32_t* idx, hipStream_t st);
 

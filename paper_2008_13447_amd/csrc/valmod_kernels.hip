@@ -339,14 +339,16 @@ __device__ __forceinline__ bool discord_less(const DiscordKey& u, const DiscordK
 
 // Per length t: top-k 1st discords (C15 reading: descending MP over finite
 // entries, ties to the smaller offset, exclusion zone around accepted offsets).
+// (lstep = 0: every block ranks a column of one length, e.g. the j-th best-match
+// distances of the m-th discords.)
 __global__ __launch_bounds__(kRankThreads) void k_topk_discords(
     const double* __restrict__ prof_dist, const int32_t* __restrict__ prof_idx, int64_t N0,
-    int64_t n, int l_min, int excl_den, int k, int32_t* __restrict__ discord_on,
+    int64_t n, int l_min, int lstep, int excl_den, int k, int32_t* __restrict__ discord_on,
     double* __restrict__ discord_d) {
   __shared__ DiscordKey sh[kRankThreads];
   __shared__ int32_t acc_i[kMaxK];
   const int tl = blockIdx.x;
-  const int L = l_min + tl;
+  const int L = l_min + tl * lstep;
   const int64_t N = n - L + 1;
   const int64_t e = excl_zone(L, excl_den);
   const double* dist = prof_dist + (int64_t)tl * N0;
@@ -568,8 +570,54 @@ hipError_t launch_rankings(const double* prof_dist, const int32_t* prof_idx, int
     k_topk_motifs<<<nlen, kRankThreads, 0, st>>>(prof_dist, prof_idx, N0, n, l_min, excl_den, km, motif_ab,
                                                  motif_d);
   if (discord_on && discord_d)
-    k_topk_discords<<<nlen, kRankThreads, 0, st>>>(prof_dist, prof_idx, N0, n, l_min, excl_den, kd, discord_on,
+    k_topk_discords<<<nlen, kRankThreads, 0, st>>>(prof_dist, prof_idx, N0, n, l_min, 1, excl_den, kd, discord_on,
                                                    discord_d);
+  return hipGetLastError();
+}
+
+// m-th discords of one length: columns j = 0..m-1 of vals / nn (stride N0)
+hipError_t launch_mth_rankings(const double* vals, const int32_t* nn, int64_t N0, int64_t n, int L, int m,
+                               int excl_den, int kd, int32_t* on, double* d, hipStream_t st) {
+  if (m <= 0 || kd <= 0 || kd > kMaxK) return hipErrorInvalidValue;
+  k_topk_discords<<<m, kRankThreads, 0, st>>>(vals, nn, N0, n, L, 0, excl_den, kd, on, d);
+  return hipGetLastError();
+}
+
+// Cross-length m-th discords (Alg. UpdateVariableLengthDiscords): for each
+// (j, rank), the largest d / sqrt(L) over the lengths, strictly (shorter wins ties).
+__global__ void k_mth_global(const int32_t* __restrict__ on, const double* __restrict__ d, int nlen, int l_min,
+                             int m, int kd, int32_t* __restrict__ g_onl, double* __restrict__ g_d) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;  // q = j * kd + r
+  if (q >= m * kd) return;
+  const int j = q / kd, r = q % kd;
+  double best = -INFINITY, db = NAN, dnb = NAN;
+  int32_t o = -1, nb = -1, Lb = -1;
+  for (int t = 0; t < nlen; ++t) {
+    const int64_t at = ((int64_t)t * m + j) * kd + r;
+    const double v = d[at];
+    if (!(v == v)) continue;
+    const int L = l_min + t;
+    const double dn = v / sqrt((double)L);
+    if (dn > best) {
+      best = dn;
+      db = v;
+      dnb = dn;
+      o = on[at * 2];
+      nb = on[at * 2 + 1];
+      Lb = L;
+    }
+  }
+  g_onl[q * 3] = o;
+  g_onl[q * 3 + 1] = nb;
+  g_onl[q * 3 + 2] = Lb;
+  g_d[q * 2] = db;
+  g_d[q * 2 + 1] = dnb;
+}
+
+hipError_t launch_mth_global(const int32_t* on, const double* d, int nlen, int l_min, int m, int kd,
+                             int32_t* g_onl, double* g_d, hipStream_t st) {
+  if (m * kd <= 0) return hipSuccess;
+  k_mth_global<<<blocks_for(m * kd, 64), 64, 0, st>>>(on, d, nlen, l_min, m, kd, g_onl, g_d);
   return hipGetLastError();
 }
 

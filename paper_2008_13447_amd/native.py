@@ -54,12 +54,14 @@ class ValmodConfig(ctypes.Structure):
         ("lanes", ctypes.c_int32),
         ("graph", ctypes.c_int32),
         ("mode", ctypes.c_int32),
+        ("m_discords", ctypes.c_int32),
     ]
 
 
 OUTPUT_FIELDS = ["prof_dist", "prof_idx", "valmp_norm", "valmp_dist", "valmp_len", "valmp_idx",
                  "motif_ab", "motif_d", "discord_on", "discord_d", "g_motif_abl", "g_motif_d",
-                 "g_discord_onl", "g_discord_d", "stats"]
+                 "g_discord_onl", "g_discord_d", "stats", "mdiscord_on", "mdiscord_d", "g_mdiscord_onl",
+                 "g_mdiscord_d"]
 
 
 class ValmodOutputs(ctypes.Structure):
@@ -68,13 +70,15 @@ class ValmodOutputs(ctypes.Structure):
 
 class ValmodSizes(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in
-                ["prof", "valmp", "motif", "discord", "g_motif", "g_discord", "stats", "series"]]
+                ["prof", "valmp", "motif", "discord", "g_motif", "g_discord", "stats", "series", "mdiscord",
+                 "g_mdiscord"]]
 
 
 class ValmodLayout(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in
                 ["series", "prof", "valmp", "motif", "discord", "g_motif", "g_discord", "stats",
-                 "n", "n0", "nlen"]] + [("l_min", ctypes.c_int32), ("l_max", ctypes.c_int32)]
+                 "n", "n0", "nlen"]] + [("l_min", ctypes.c_int32), ("l_max", ctypes.c_int32)] + \
+        [("mdiscord", ctypes.c_int64), ("g_mdiscord", ctypes.c_int64)]
 
 
 _lib = None
@@ -130,7 +134,8 @@ def _check(rc: int, where: str):
 def make_config(n: Sequence[int], l_min: Sequence[int], l_max: Sequence[int], p: int = 0,
                 k_motifs: int = 1, k_discords: int = 1, excl_den: int = 4, flat_eps: float = 0.0,
                 dtype: str = "f32", precision: str = "fp64", refresh_R: int = 0, path: str = "auto",
-                device: int = 0, lanes: int = 0, graph: bool = False, mode: str = "exact"):
+                device: int = 0, lanes: int = 0, graph: bool = False, mode: str = "exact",
+                m_discords: int = 1):
     """Build a ValmodConfig; returns (config, keepalive arrays)."""
     S = len(n)
     na = (ctypes.c_int64 * S)(*[int(v) for v in n])
@@ -140,7 +145,8 @@ def make_config(n: Sequence[int], l_min: Sequence[int], l_max: Sequence[int], p:
                        ctypes.cast(lo, ctypes.POINTER(ctypes.c_int32)),
                        ctypes.cast(hi, ctypes.POINTER(ctypes.c_int32)), int(p), int(k_motifs),
                        int(k_discords), int(excl_den), float(flat_eps), DTYPE[dtype], PRECISION[precision],
-                       int(refresh_R), PATH[path], int(device), int(lanes), 1 if graph else 0, MODE[mode])
+                       int(refresh_R), PATH[path], int(device), int(lanes), 1 if graph else 0, MODE[mode],
+                       int(m_discords))
     return cfg, (na, lo, hi)
 
 
@@ -210,7 +216,7 @@ class Valmod:
     def __init__(self, series: Union["torch.Tensor", List["torch.Tensor"]], l_min, l_max, p: int = 0,
                  k_motifs: int = 1, k_discords: int = 1, excl_den: int = 4, flat_eps: float = 0.0,
                  precision: str = "fp64", refresh_R: int = 0, path: str = "auto", lanes: int = 0,
-                 graph: bool = False, mode: str = "exact"):
+                 graph: bool = False, mode: str = "exact", m_discords: int = 1):
         import torch
 
         if isinstance(series, torch.Tensor):
@@ -227,7 +233,9 @@ class Valmod:
         self.torch = torch
         cfg, self._keep = make_config([s.numel() for s in series], lo, hi, p, k_motifs, k_discords,
                                       excl_den, flat_eps, "f32" if dt == torch.float32 else "f64",
-                                      precision, refresh_R, path, self.device.index or 0, lanes, graph, mode)
+                                      precision, refresh_R, path, self.device.index or 0, lanes, graph, mode,
+                                      m_discords)
+        self.m_discords = max(1, int(m_discords))
         self.plan = valmod_plan(cfg)
         self.graph = bool(graph)
         self._stream = None
@@ -256,6 +264,10 @@ class Valmod:
             "g_discord_onl": torch.empty(3 * z["g_discord"], dtype=i32, device=dev),
             "g_discord_d": torch.empty(2 * z["g_discord"], dtype=f64, device=dev),
             "stats": torch.empty(z["stats"], dtype=torch.int64, device=dev),
+            "mdiscord_on": torch.empty(max(1, 2 * z["mdiscord"]), dtype=i32, device=dev),
+            "mdiscord_d": torch.empty(max(1, z["mdiscord"]), dtype=f64, device=dev),
+            "g_mdiscord_onl": torch.empty(max(1, 3 * z["g_mdiscord"]), dtype=i32, device=dev),
+            "g_mdiscord_d": torch.empty(max(1, 2 * z["g_mdiscord"]), dtype=f64, device=dev),
         }
         self._outs = ValmodOutputs(*[self.out[f].data_ptr() for f in OUTPUT_FIELDS])
 
@@ -291,7 +303,7 @@ class Valmod:
         n0, nl = L["n0"], L["nlen"]
         km, kd = self.k_motifs, self.k_discords
         o = {k: v.cpu().numpy() for k, v in self.out.items()}
-        return dict(
+        out = dict(
             prof_dist=o["prof_dist"][L["prof"]:L["prof"] + nl * n0].reshape(nl, n0),
             prof_idx=o["prof_idx"][L["prof"]:L["prof"] + nl * n0].reshape(nl, n0),
             valmp_norm=o["valmp_norm"][L["valmp"]:L["valmp"] + n0],
@@ -308,6 +320,14 @@ class Valmod:
             g_discord_d=o["g_discord_d"][2 * L["g_discord"]:2 * (L["g_discord"] + kd)].reshape(kd, 2),
             stats=o["stats"][L["stats"]:L["stats"] + nl * NSTATS].reshape(nl, NSTATS),
         )
+        m = self.m_discords
+        if m > 1:
+            a, g = L["mdiscord"], L["g_mdiscord"]
+            out["mdiscord_on"] = o["mdiscord_on"][2 * a:2 * (a + nl * m * kd)].reshape(nl, m, kd, 2)
+            out["mdiscord_d"] = o["mdiscord_d"][a:a + nl * m * kd].reshape(nl, m, kd)
+            out["g_mdiscord_onl"] = o["g_mdiscord_onl"][3 * g:3 * (g + m * kd)].reshape(m, kd, 3)
+            out["g_mdiscord_d"] = o["g_mdiscord_d"][2 * g:2 * (g + m * kd)].reshape(m, kd, 2)
+        return out
 
     def close(self):
         if getattr(self, "plan", None):

@@ -78,6 +78,23 @@ def test_plan_validation(lib):
     # paper mode: automatic path only, no graph
     assert _status(mode="paper") == 0
     assert _status(mode="paper", path="full") == -1 and _status(mode="paper", graph=True) == -1
+    # m-th discords: 1 <= m <= 16, m <= p, exact mode, no graph
+    assert _status(m_discords=3) == 0 and _status(m_discords=5) == 0
+    assert _status(m_discords=6) == -1            # p = 5 in _status
+    assert _status(m_discords=17, p=20) == -1
+    assert _status(m_discords=2, mode="paper") == -1 and _status(m_discords=2, graph=True) == -1
+
+
+def test_mth_discord_sizes(lib):
+    cfg, keep = native.make_config([1000, 600], [20, 10], [30, 12], p=5, k_motifs=2, k_discords=3, m_discords=4)
+    plan = native.valmod_plan(cfg)
+    try:
+        z = native.valmod_output_sizes(plan)
+        assert z["mdiscord"] == 4 * 3 * (11 + 3) and z["g_mdiscord"] == 2 * 4 * 3
+        L1 = native.valmod_series_layout(plan, 1)
+        assert L1["mdiscord"] == 4 * 3 * 11 and L1["g_mdiscord"] == 4 * 3
+    finally:
+        native.valmod_plan_free(plan)
 
 
 def test_lanes_split_the_workspace(lib):

@@ -510,3 +510,30 @@ def test_paper_mode_motif_per_length_exact(oracle_mod, precision, p):
     _say(f"paper mode {precision} p={p}: {dict(rep)}; per-length partial {st[:, 10].tolist()}, "
          f"recomputed {st[:, 2].tolist()}, full passes {st[:, 3].tolist()}")
     assert rep["partial_entries"] == int(st[:, 10].sum())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mth_discords_parity(oracle_mod, precision):
+    """Top-k m-th discords (m = 3) per length and across lengths against the
+    oracle: offsets equal except between ties, distances to the FP64 tolerance;
+    the 1st-discord column equals the plain discords."""
+    x = gen.small_random_walk(1600, 97, np.float32)
+    lo, hi, k, m = 24, 30, 3, 3
+    g = run_gpu(x, lo, hi, p=5, k_motifs=2, k_discords=k, m_discords=m, precision=precision)
+    r = oracle_mod.mth_discords(x, lo, hi, k, m)
+    for t in range(hi - lo + 1):
+        L = lo + t
+        for j in range(m):
+            for q in range(k):
+                go, gn = (int(v) for v in g["mdiscord_on"][t, j, q])
+                ro = int(r["on"][t, j, q, 0])
+                gd, rd = g["mdiscord_d"][t, j, q], r["d"][t, j, q]
+                assert abs(gd - rd) <= TOL64 * np.sqrt(L), (L, j, q, gd, rd)
+                if go != ro:  # a tie: the reported owner's (j+1)-th distance equals the oracle's
+                    d_own, _ = oracle_mod.mth_rows(x, L, m, rows=[go])
+                    assert abs(d_own[0, j] - rd) <= TOL64 * np.sqrt(L), (L, j, q)
+                dd, _ = oracle_mod.mth_rows(x, L, m, rows=[go])
+                assert abs(oracle_mod.pair_dist(x, L, go, gn) - dd[0, j]) <= TOL64 * np.sqrt(L)
+        np.testing.assert_allclose(g["mdiscord_d"][t, 0], g["discord_d"][t], rtol=0, atol=TOL64 * np.sqrt(L))
+    np.testing.assert_allclose(g["g_mdiscord_d"], r["g_d"], rtol=0, atol=TOL64)
+    _say(f"m-th discords {precision}: ok, stats recomputed {g['stats'][:, 2].tolist()}")
