@@ -69,6 +69,8 @@ def _load():
     lib.oracle_mth_rows.restype = ctypes.c_int
     lib.oracle_mth_discords.argtypes = [P, I64, I64, I64, I64, D, I64, I64, P, P, P, P]
     lib.oracle_mth_discords.restype = ctypes.c_int
+    lib.oracle_motif_sets.argtypes = [P, I64, I64, P, P, D, I64, D, I64, P, P, P]
+    lib.oracle_motif_sets.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -220,3 +222,20 @@ def mth_discords(x, l_min: int, l_max: int, k: int, m: int, excl_den: int = 4, f
     if rc != 0:
         raise ValueError("oracle_mth_discords: invalid arguments")
     return {"on": on, "d": d, "g_onl": g_onl, "g_d": g_d}
+
+
+def motif_sets(x, pairs_abl, pair_d, D: float, cap: int, excl_den: int = 4, flat_eps: float = FLAT_EPS):
+    """Motif sets grown from the given pairs (a, b, L) with distances d, radius D * d
+    (see the C header): (count[k], off[k, cap], dist[k, cap])."""
+    x = _f64(x)
+    pa = np.ascontiguousarray(np.asarray(pairs_abl, dtype=np.int64).reshape(-1, 3))
+    pd_ = np.ascontiguousarray(np.asarray(pair_d, dtype=np.float64).reshape(-1))
+    k = pa.shape[0]
+    count = np.empty(k, dtype=np.int64)
+    off = np.empty((k, cap), dtype=np.int64)
+    dist = np.empty((k, cap))
+    rc = _load().oracle_motif_sets(_ptr(x), x.shape[0], k, _ptr(pa), _ptr(pd_), float(D), excl_den, flat_eps, cap,
+                                   _ptr(count), _ptr(off), _ptr(dist))
+    if rc != 0:
+        raise ValueError("oracle_motif_sets: invalid arguments")
+    return count, off, dist

@@ -43,7 +43,8 @@
  * flat rule and the greedy top-k rules are definitions of this build: parity
  * unpinned beyond their special cases (top-1 motif = the motif pair, top-1
  * discord = the 1st discord). oracle_mth_rows / oracle_mth_discords follow the
- * definitions of the m-th best match and of the Top-k m-th discord (pinned
+ * definitions of the m-th best match and of the Top-k m-th discord, and
+ * oracle_motif_sets the definition of the data series motif set (both pinned
  * against an independent brute force).
  */
 #include <math.h>
@@ -638,6 +639,96 @@ ORACLE_EXPORT int oracle_mth_discords(const double* x, int64_t n, int64_t l_min,
         }
       }
     }
+  return 0;
+}
+
+/*
+ * Variable-length motif sets (Def. data series motif set; Problem of
+ * variable-length motif sets discovery; Sec. "Finding Motif Sets"): for each
+ * given motif pair (a, b) of length L and distance d, in the given order, the
+ * radius is r = D * d and the candidate members are the windows of length L at
+ * distance < r from a or from b (each with its distance to the nearer of the
+ * two). Members are taken in order of (that distance, offset); a candidate is
+ * dropped if its offset already belongs to an earlier set (the sets are
+ * disjoint by offset) or if it lies within the exclusion zone of a member
+ * already taken for this set (trivial matches removed). Flat windows are never
+ * members. Outputs per set s: count[s] (members), and the first `cap` members
+ * off[s*cap + i] / dist[s*cap + i] (-1 / NaN after the last).
+ */
+typedef struct {
+  double d;
+  int64_t c;
+} mem_t;
+
+static int cmp_mem(const void* p, const void* q) {
+  const mem_t* u = (const mem_t*)p;
+  const mem_t* v = (const mem_t*)q;
+  if (u->d != v->d) return u->d < v->d ? -1 : 1;
+  return u->c < v->c ? -1 : (u->c > v->c ? 1 : 0);
+}
+
+ORACLE_EXPORT int oracle_motif_sets(const double* x, int64_t n, int64_t k, const int64_t* pairs_abl,
+                                    const double* pair_d, double D, int64_t excl_den, double flat_eps, int64_t cap,
+                                    int64_t* count, int64_t* off, double* dist) {
+  if (k < 0 || cap < 1 || excl_den < 1 || !(D >= 0.0)) return -1;
+  uint8_t* taken = (uint8_t*)calloc((size_t)n, 1);
+  for (int64_t s = 0; s < k; s++) {
+    const int64_t a = pairs_abl[3 * s], b = pairs_abl[3 * s + 1], L = pairs_abl[3 * s + 2];
+    count[s] = 0;
+    for (int64_t i = 0; i < cap; i++) {
+      off[s * cap + i] = -1;
+      dist[s * cap + i] = NAN;
+    }
+    if (a < 0 || L < 2 || n - L + 1 < 1) continue;
+    const int64_t N = n - L + 1;
+    const double r = D * pair_d[s];
+    double* mu = (double*)malloc(sizeof(double) * N);
+    double* sg = (double*)malloc(sizeof(double) * N);
+    uint8_t* fl = (uint8_t*)malloc(N);
+    oracle_stats(x, n, L, flat_eps, mu, sg, fl);
+    mem_t* m = (mem_t*)malloc(sizeof(mem_t) * N);
+    int64_t cnt = 0;
+    for (int64_t c = 0; c < N; c++) {
+      if (fl[c]) continue;
+      double best = INFINITY;
+      if (!fl[a]) best = sqrt(sqdist(x, L, a, c, mu, sg));
+      if (!fl[b]) {
+        double db = sqrt(sqdist(x, L, b, c, mu, sg));
+        if (db < best) best = db;
+      }
+      if (best < r) {
+        m[cnt].d = best;
+        m[cnt].c = c;
+        cnt++;
+      }
+    }
+    qsort(m, cnt, sizeof(mem_t), cmp_mem);
+    const int64_t e = excl_zone(L, excl_den);
+    int64_t got = 0;
+    int64_t* acc = (int64_t*)malloc(sizeof(int64_t) * (cnt > 0 ? cnt : 1));
+    for (int64_t q = 0; q < cnt; q++) {
+      const int64_t c = m[q].c;
+      if (taken[c]) continue;
+      int ok = 1;
+      for (int64_t u = 0; u < got && ok; u++)
+        if (iabs64(c - acc[u]) <= e) ok = 0;
+      if (!ok) continue;
+      acc[got] = c;
+      if (got < cap) {
+        off[s * cap + got] = c;
+        dist[s * cap + got] = m[q].d;
+      }
+      got++;
+    }
+    for (int64_t u = 0; u < got; u++) taken[acc[u]] = 1;
+    count[s] = got;
+    free(acc);
+    free(m);
+    free(mu);
+    free(sg);
+    free(fl);
+  }
+  free(taken);
   return 0;
 }
 

@@ -365,3 +365,70 @@ def test_first_discords_special_case(oracle_mod):
     v = oracle_mod.valmod(x, 20, 24, k_motifs=1, k_discords=3)
     np.testing.assert_array_equal(r["on"][:, 0, :, 0], v["discord_on"][:, :, 0])
     np.testing.assert_allclose(r["d"][:, 0], v["discord_d"], rtol=0, atol=1e-12)
+
+
+def test_motif_sets_vs_brute_force(oracle_mod):
+    """Def. data series motif set: windows within radius D * d of either center,
+    taken by (distance to the nearer center, offset), trivial matches of taken
+    members dropped, sets disjoint by offset; checked against an independent
+    brute force and the definition's invariants."""
+    x = gen.small_random_walk(900, 37)
+    lo, hi, k, D, cap = 30, 34, 4, 5.0, 60
+    v = oracle_mod.valmod(x, lo, hi, k_motifs=k, k_discords=1)
+    pairs, pd = v["g_motif_abl"], v["g_motif_d"][:, 0]
+    count, off, dist = oracle_mod.motif_sets(x, pairs, pd, D, cap)
+    taken = set()
+    skipped = 0
+    for s in range(k):
+        a, b, L = (int(t) for t in pairs[s])
+        Dm = _brute_dist_matrix(x, L)
+        np.fill_diagonal(Dm, 0.0)
+        W = _windows(x, L)
+        Z = (W - W.mean(axis=1, keepdims=True)) / W.std(axis=1, keepdims=True)
+        da = np.linalg.norm(Z - Z[a], axis=1)
+        db = np.linalg.norm(Z - Z[b], axis=1)
+        near = np.minimum(da, db)
+        r = D * pd[s]
+        cand = sorted((float(near[c]), c) for c in range(len(near)) if near[c] < r)
+        e = -(-L // 4)
+        acc = []
+        for dnear, c in cand:
+            if any(abs(c - u) <= e for u in acc):
+                continue
+            if c in taken:
+                skipped += 1
+                continue
+            acc.append(c)
+        assert count[s] == len(acc), (s, count[s], len(acc))
+        got = [int(t) for t in off[s, :min(cap, len(acc))]]
+        assert got == acc[:cap]
+        np.testing.assert_allclose(dist[s, :len(got)], [near[c] for c in got], rtol=0, atol=1e-10)
+        assert a in acc or a in taken  # a center is a member of its own set unless an earlier set took it
+        taken.update(acc)
+        # invariants: members within the radius, no two members are trivial matches
+        assert all(near[c] < r for c in acc)
+        assert all(abs(u - w) > e for i, u in enumerate(acc) for w in acc[i + 1:])
+    assert skipped > 0  # the input exercises the disjointness rule
+
+
+def test_motif_sets_special_radii(oracle_mod):
+    """Def. data series motif set with the strict radius: D = 0 gives empty sets;
+    with an unbounded radius every non-flat window is a candidate of the first
+    set, so its members are the greedy non-overlapping cover of the offsets and
+    no offset is farther than the exclusion zone from a member."""
+    x = gen.small_random_walk(400, 35)
+    L = 20
+    v = oracle_mod.valmod(x, L, L, k_motifs=2, k_discords=1)
+    pairs, pd = v["g_motif_abl"], v["g_motif_d"][:, 0]
+    count, off, _ = oracle_mod.motif_sets(x, pairs, pd, 0.0, 8)
+    assert np.all(count == 0) and np.all(off == -1)
+    N = x.shape[0] - L + 1
+    e = -(-L // 4)
+    count, off, dist = oracle_mod.motif_sets(x, pairs[:1], pd[:1], 1e12, N)
+    mem = off[0, :count[0]]
+    assert mem[0] == min(pairs[0, 0], pairs[0, 1]) and dist[0, 0] == 0.0
+    assert np.all(np.diff(dist[0, :count[0]]) >= 0)
+    s = np.sort(mem)
+    assert np.all(np.diff(s) > e)  # pairwise non-trivial
+    gaps = np.abs(np.arange(N)[:, None] - s[None, :]).min(axis=1)
+    assert np.all(gaps <= e)  # maximal: every window is a trivial match of some member
