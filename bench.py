@@ -93,6 +93,10 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"],
                     help="headline path (the other one is timed beside it unless --no-compare)")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--k-motifs", type=int, default=0, help="top-k motif pairs (0: the workload's)")
+    ap.add_argument("--mset", type=float, default=0.0, metavar="D",
+                    help="also grow the motif sets of the global top-k pairs with radius factor D")
+    ap.add_argument("--mset-cap", type=int, default=1024, help="members stored per motif set")
     ap.add_argument("--path", default="auto", choices=["auto", "full", "recompute"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -135,11 +139,14 @@ def main():
         cells = cells_total(w.n, w.l_min, w.l_max)
         name = w.name
 
+    km = args.k_motifs or w.k_motifs
+
     def timed(precision):
         graph = args.graph and precision == "fp64"
-        v = native.Valmod(x, lo, hi, p=w.p, k_motifs=w.k_motifs, k_discords=w.k_discords,
+        v = native.Valmod(x, lo, hi, p=w.p, k_motifs=km, k_discords=w.k_discords,
                           excl_den=w.excl_den, precision=precision, path="full" if graph else args.path,
-                          lanes=args.lanes, graph=graph, mode=args.mode)
+                          lanes=args.lanes, graph=graph, mode=args.mode, mset_radius=args.mset,
+                          mset_cap=args.mset_cap)
         tune = None
         if not args.no_autotune:
             t0 = time.perf_counter()
@@ -172,9 +179,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "n": w.n if batch is None else sum(b.n for b in batch),
                    "l_min": lo if batch is None else min(lo), "l_max": hi if batch is None else max(hi),
-                   "p": w.p, "k": w.k_motifs, "precision": args.precision, "path": args.path,
+                   "p": w.p, "k": km, "precision": args.precision, "path": args.path,
                    "lanes": args.lanes, "graph": bool(args.graph and args.precision == "fp64"),
-                   "mode": args.mode},
+                   "mode": args.mode, "mset_radius": args.mset},
         "roofline": {"bound": "alu", "kernel": f"k_pass<{'double' if args.precision == 'fp64' else 'float'}> "
                      "(diagonal pass)", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": profiled_traffic(args.precision),
@@ -182,6 +189,9 @@ def main():
                      "cells_per_launch": pass_cells / max(launches, 1)},
     }
     out["autotune"] = tune
+    if args.mset > 0:
+        out["motif_sets"] = {"radius_factor": args.mset, "k": km,
+                             "members": [int(c) for c in res["mset_count"]]}
     st = res["stats"].sum(axis=0)
     out["diagnostics"] = {name: int(st[c]) for c, name in enumerate(native.STAT_NAMES)}
     if not args.no_compare:

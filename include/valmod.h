@@ -121,6 +121,10 @@ typedef struct {
   int32_t mode;             /* valmod_mode; VALMOD_MODE_PAPER needs VALMOD_PATH_AUTO and no graph */
   int32_t m_discords;       /* m of the Top-k m-th discords (0 or 1: only the 1st discords); m > 1 needs
                                m <= 16, m <= p, exact mode and no graph, and the mdiscord outputs */
+  double mset_radius;       /* radius factor D of the motif sets (Sec. "Finding Motif Sets"): 0 = no
+                               motif sets; else in (0, 1e6], and the mset outputs are required */
+  int32_t mset_cap;         /* members stored per motif set, in [1, 2^20] when mset_radius > 0 (the
+                               count of members is reported in full) */
 } valmod_config;
 
 typedef struct valmod_plan_s* valmod_plan_t;
@@ -161,6 +165,16 @@ enum {
  *   mdiscord_on[((t * m + j) * k_d + r) * 2 + {0,1}] i32 (offset, (j+1)-th neighbour),
  *   mdiscord_d[(t * m + j) * k_d + r] f64, g_mdiscord_onl[(j * k_d + r) * 3 + {0,1,2}] i32 (offset,
  *   neighbour, L), g_mdiscord_d[(j * k_d + r) * 2 + {0,1}] f64 (d, d/sqrt(L)); unused slots -1 / NaN
+ *   with mset_radius = D > 0 (Def. data series motif set; Problem of variable-length motif sets
+ *   discovery): one set per global motif pair r (a, b, L, d) of g_motif_*, taken in rank order, with
+ *   radius D * d: the windows of length L whose z-normalised distance to a or to b is below the
+ *   radius, in order of (distance to the nearer of a and b, offset), skipping a window that is a
+ *   trivial match of a member already taken for this set or whose offset an earlier set of the
+ *   series already holds (sets are disjoint by offset across lengths). Distances closer than
+ *   D * d * 2^-36 count as equal. Flat windows are never members.
+ *   mset_count[r] i32 (members, also beyond mset_cap), mset_off[r * mset_cap + i] i32 and
+ *   mset_dist[r * mset_cap + i] f64 (raw distance to the nearer pair member) for i < min(count,
+ *   mset_cap), -1 / NaN after; offsets: mset_count at the series' g_motif, the others at its mset
  */
 typedef struct {
   double* prof_dist;
@@ -182,6 +196,9 @@ typedef struct {
   double* mdiscord_d;
   int32_t* g_mdiscord_onl;
   double* g_mdiscord_d;
+  int32_t* mset_count;     /* mset_radius > 0 only (else ignored) */
+  int32_t* mset_off;
+  double* mset_dist;
 } valmod_outputs;
 
 /* Element counts of every output array over the whole batch. */
@@ -196,6 +213,7 @@ typedef struct {
   int64_t series;     /* elements of the concatenated input series */
   int64_t mdiscord;   /* mdiscord_d (mdiscord_on holds 2x); 0 unless m_discords > 1 */
   int64_t g_mdiscord; /* rows of g_mdiscord_* */
+  int64_t mset;       /* mset_off, mset_dist (g_motif * mset_cap); 0 unless mset_radius > 0 */
 } valmod_sizes;
 
 /* Element offsets of series s inside the concatenated input and each output. */
@@ -212,6 +230,7 @@ typedef struct {
   int32_t l_min, l_max;
   int64_t mdiscord;
   int64_t g_mdiscord;
+  int64_t mset;
 } valmod_layout;
 
 /* Validate a configuration and build a plan (host only; touches no GPU). The
@@ -221,7 +240,8 @@ typedef struct {
  * p < 0, k < 1, excl_den < 0, flat_eps < 0, unknown enum, lanes outside
  * [0, 64], graph not 0/1, graph with VALMOD_PATH_RECOMPUTE or with
  * VALMOD_PREC_FP32_REFRESH, unknown mode, paper mode with another path than
- * VALMOD_PATH_AUTO or with graph), VALMOD_E_TOO_SHORT
+ * VALMOD_PATH_AUTO or with graph, m_discords or motif-set fields out of
+ * range), VALMOD_E_TOO_SHORT
  * (n - l_max + 1 <= ceil(l_max / excl_den) + 1: no non-trivial pair),
  * VALMOD_E_LAYOUT (more than VALMOD_MAX_WINDOWS windows), VALMOD_E_NOMEM. */
 VALMOD_API valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* out);
@@ -249,7 +269,7 @@ VALMOD_API valmod_status valmod_series_layout(valmod_plan_t plan, int32_t s, val
  * the same d_series, d_workspace, output pointers and stream replay it. One plan
  * must not be used by two calls at the same time. Errors: VALMOD_E_ARG (null
  * plan/series/workspace/out), VALMOD_E_HIP, VALMOD_E_DEVICE (non-finite input
- * values).
+ * values). The motif sets need the mset outputs (VALMOD_E_ARG without them).
  */
 VALMOD_API valmod_status valmod_run(valmod_plan_t plan, const void* d_series, void* d_workspace,
                          const valmod_outputs* d_out, void* stream);

@@ -25,6 +25,7 @@ struct WsLayout {
   size_t xs, A, B, mu, sig, invn, flat, df, dg, sw32, thr, thr32, best, counters, anc;
   size_t hc, hS, hn, hbound, hsig, acnt, abuf, fail, big, lbm, rec, part, mvals, mnn, mkeys;
   size_t df32, dg32, inv32, bsw_max, bsw_min, bdf_max, bdg_max, delta, hard;
+  size_t ms_keys0, ms_keys1, ms_vals0, ms_vals1, ms_hist, ms_meta, ms_count, ms_taken, ms_bucket;
   size_t total;
 };
 
@@ -181,6 +182,18 @@ static size_t layout_lane(const valmod_plan_s* P, Lane& ln) {
     w.mnn = take(md * wp * 4);
     w.mkeys = take(md * wp * 8);
   }
+  if (P->cfg.mset_radius > 0.0) {
+    const size_t cc = (size_t)P->cfg.k_motifs * (size_t)ln.n0max;
+    w.ms_keys0 = take(cc * 8);
+    w.ms_keys1 = take(cc * 8);
+    w.ms_vals0 = take(cc * 8);
+    w.ms_vals1 = take(cc * 8);
+    w.ms_hist = take(motif_sets_hist_words((int64_t)cc) * 4);
+    w.ms_meta = take(5 * 64 * 8);
+    w.ms_count = take(65 * 4);
+    w.ms_taken = take(((size_t)ln.n0max + 63) / 64 * 8);
+    w.ms_bucket = take(((size_t)ln.n0max / 2 + 2) * 4);
+  }
   if (P->cfg.mode == VALMOD_MODE_PAPER) {
     w.lbm = take(wp * 8);
     w.rec = take(wp * 4);
@@ -250,6 +263,8 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
   if (cfg->m_discords < 0 || cfg->m_discords > 16) return fail(VALMOD_E_ARG);
   if (cfg->m_discords > 1 && (cfg->mode != VALMOD_MODE_EXACT || cfg->graph)) return fail(VALMOD_E_ARG);
   if (cfg->mode == VALMOD_MODE_PAPER && (cfg->path != VALMOD_PATH_AUTO || cfg->graph)) return fail(VALMOD_E_ARG);
+  if (!(cfg->mset_radius >= 0.0) || cfg->mset_radius > 1e6) return fail(VALMOD_E_ARG);
+  if (cfg->mset_radius > 0.0 && (cfg->mset_cap < 1 || cfg->mset_cap > (1 << 20))) return fail(VALMOD_E_ARG);
 
   valmod_plan_s* P = new (std::nothrow) valmod_plan_s();
   if (!P) return fail(VALMOD_E_NOMEM);
@@ -311,6 +326,7 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
     L.stats = z.stats;
     L.mdiscord = z.mdiscord;
     L.g_mdiscord = z.g_mdiscord;
+    L.mset = z.mset;
     L.n = n;
     L.n0 = n0;
     L.nlen = nlen;
@@ -328,6 +344,7 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
       z.mdiscord += nlen * md * kd;
       z.g_mdiscord += md * kd;
     }
+    if (P->cfg.mset_radius > 0.0) z.mset += km * (int64_t)P->cfg.mset_cap;
     for (int64_t Lx = lo; Lx <= hi; ++Lx) cost[s] += (double)(n - Lx + 1) * (double)(n - Lx + 1);
   }
   const size_t pp = (size_t)P->cfg.p;
@@ -466,6 +483,7 @@ struct LaneRun {
   double* mvals;
   uint64_t* mkeys;
   uint32_t* acnt;
+  MotifSetLaunch ms{};
   // state
   size_t si = 0;
   bool open = false;
@@ -523,6 +541,17 @@ struct LaneRun {
     bdg_max = fp32 ? (float*)(b + w.bdg_max) : nullptr;
     delta = fp32 ? (float*)(b + w.delta) : nullptr;
     hard = fp32 ? (int32_t*)(b + w.hard) : nullptr;
+    if (P->cfg.mset_radius > 0.0) {
+      ms.meta = (double*)(b + w.ms_meta);
+      ms.count = (uint32_t*)(b + w.ms_count);
+      ms.keys0 = (uint64_t*)(b + w.ms_keys0);
+      ms.keys1 = (uint64_t*)(b + w.ms_keys1);
+      ms.vals0 = (double*)(b + w.ms_vals0);
+      ms.vals1 = (double*)(b + w.ms_vals1);
+      ms.hist = (uint32_t*)(b + w.ms_hist);
+      ms.taken = (uint64_t*)(b + w.ms_taken);
+      ms.bucket = (uint32_t*)(b + w.ms_bucket);
+    }
   }
 
   bool chk(hipError_t e) {
@@ -808,6 +837,24 @@ LaneRun::Status LaneRun::advance() {
                               (int)Ls.nlen, Ls.l_min, excl_den, km, kd, o->g_motif_abl + 3 * Ls.g_motif,
                               o->g_motif_d + 2 * Ls.g_motif, o->g_discord_onl + 3 * Ls.g_discord,
                               o->g_discord_d + 2 * Ls.g_discord, st));
+    if (P->cfg.mset_radius > 0.0) {
+      // motif sets of the global top-k pairs (Sec. "Finding Motif Sets")
+      ms.xs = xs;
+      ms.n = n;
+      ms.n0 = N0;
+      ms.abl = o->g_motif_abl + 3 * Ls.g_motif;
+      ms.gd = o->g_motif_d + 2 * Ls.g_motif;
+      ms.k = km;
+      ms.D = P->cfg.mset_radius;
+      ms.excl_den = excl_den;
+      ms.flat_eps = P->cfg.flat_eps;
+      ms.cap = P->cfg.mset_cap;
+      ms.cand_cap = (int64_t)km * N0;
+      ms.out_count = o->mset_count + Ls.g_motif;
+      ms.out_off = o->mset_off + Ls.mset;
+      ms.out_dist = o->mset_dist + Ls.mset;
+      LCHECK(launch_motif_sets(ms, st));
+    }
     if (md > 1)
       LCHECK(launch_mth_global(o->mdiscord_on + 2 * Ls.mdiscord, o->mdiscord_d + Ls.mdiscord, (int)Ls.nlen, Ls.l_min,
                                md, kd, o->g_mdiscord_onl + 3 * Ls.g_mdiscord, o->g_mdiscord_d + 2 * Ls.g_mdiscord,
@@ -892,6 +939,7 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
     return VALMOD_E_ARG;
   if (P->cfg.m_discords > 1 && (!o->mdiscord_on || !o->mdiscord_d || !o->g_mdiscord_onl || !o->g_mdiscord_d))
     return VALMOD_E_ARG;
+  if (P->cfg.mset_radius > 0.0 && (!o->mset_count || !o->mset_off || !o->mset_dist)) return VALMOD_E_ARG;
   hipStream_t st = (hipStream_t)stream_;
   valmod_status status = VALMOD_OK;
   int prev_dev = -1;
@@ -1016,6 +1064,11 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
     so.mdiscord_d += Ls.mdiscord;
     so.g_mdiscord_onl += 3 * Ls.g_mdiscord;
     so.g_mdiscord_d += 2 * Ls.g_mdiscord;
+  }
+  if (P->cfg.mset_radius > 0.0) {
+    so.mset_count += Ls.g_motif;
+    so.mset_off += Ls.mset;
+    so.mset_dist += Ls.mset;
   }
   const void* sub_series = (const char*)d_series + (size_t)Ls.series * esz;
   double best_ms = -1.0;

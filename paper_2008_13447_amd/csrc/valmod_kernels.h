@@ -144,6 +144,31 @@ hipError_t launch_mth_rankings(const double* vals, const int32_t* nn, int64_t N0
                                int excl_den, int kd, int32_t* on, double* d, hipStream_t st);
 hipError_t launch_mth_global(const int32_t* on, const double* d, int nlen, int l_min, int m, int kd,
                              int32_t* g_onl, double* g_d, hipStream_t st);
+// motif sets grown from the global top-k motif pairs of one series (valmod_sets.hip)
+struct MotifSetLaunch {
+  const double* xs;       // padded FP64 series
+  int64_t n, n0;          // points, windows at the smallest length
+  const int32_t* abl;     // k rows (a, b, L), a < 0 for an unused rank
+  const double* gd;       // k rows (d, d / sqrt(L))
+  int k;                  // pairs (<= 64)
+  double D;               // radius factor
+  int excl_den;
+  double flat_eps;
+  int64_t cap;            // members stored per set
+  int64_t cand_cap;       // candidate capacity: k * n0
+  double* meta;           // 5 * 64 doubles
+  uint32_t* count;        // 1 + k words: candidate count, then candidates per set
+  uint64_t *keys0, *keys1;
+  double *vals0, *vals1;  // cand_cap each
+  uint32_t* hist;         // motif_sets_hist_words(cand_cap)
+  uint64_t* taken;        // (n0 + 63) / 64 words
+  uint32_t* bucket;       // n0 / 2 + 2 entries
+  int32_t* out_count;     // k
+  int32_t* out_off;       // k * cap
+  double* out_dist;       // k * cap
+};
+size_t motif_sets_hist_words(int64_t cand_cap);
+hipError_t launch_motif_sets(const MotifSetLaunch& m, hipStream_t st);
 // copies best keys into an int32 index array (-1 for empty keys)
 hipError_t launch_keys_to_idx(const uint64_t* best, int64_t N, int32_t* idx, hipStream_t st);
 

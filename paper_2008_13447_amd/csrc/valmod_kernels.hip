@@ -275,13 +275,58 @@ __device__ Key block_reduce(Key v, Less less, Key* sh) {
   return r;
 }
 
+// Endpoints of the accepted pairs, sorted by offset, with each pair's length:
+// a test only visits the endpoints within the widest exclusion zone of x.
+struct PickSet {
+  int32_t pos[2 * kMaxK];
+  int32_t len[2 * kMaxK];
+  int n;
+};
+
+// inserts the two endpoints of an accepted pair (one thread)
+__device__ __forceinline__ void pick_insert(PickSet& ps, int32_t a, int32_t b, int32_t L) {
+  const int32_t v[2] = {a, b};
+  for (int u = 0; u < 2; ++u) {
+    int q = ps.n++;
+    while (q > 0 && ps.pos[q - 1] > v[u]) {
+      ps.pos[q] = ps.pos[q - 1];
+      ps.len[q] = ps.len[q - 1];
+      --q;
+    }
+    ps.pos[q] = v[u];
+    ps.len[q] = L;
+  }
+}
+
+// true if offset x lies within the exclusion zone of an accepted endpoint; the
+// zone of the pair (x's length Lx, endpoint length Lp) is that of the longer
+// length when `longer` is set, else the fixed e; emax bounds every zone
+__device__ __forceinline__ bool near_pick(const PickSet& ps, int64_t x, int64_t emax, bool longer, int64_t Lx,
+                                          int excl_den, int64_t e) {
+  int lo = 0, hi = ps.n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)ps.pos[mid] < x - emax)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  for (int q = lo; q < ps.n && (int64_t)ps.pos[q] <= x + emax; ++q) {
+    const int64_t eq = longer ? excl_zone(Lx > ps.len[q] ? Lx : ps.len[q], excl_den) : e;
+    if (iabs64(x - ps.pos[q]) <= eq) return true;
+  }
+  return false;
+}
+
 // Per length t: motif pairs (C14 reading: sort by (d, min, max), greedy with
 // the exclusion zone on all four endpoint combinations).
 __global__ __launch_bounds__(kRankThreads) void k_topk_motifs(
     const double* __restrict__ prof_dist, const int32_t* __restrict__ prof_idx, int64_t N0,
     int64_t n, int l_min, int excl_den, int k, int32_t* __restrict__ motif_ab, double* __restrict__ motif_d) {
   __shared__ MotifKey sh[kRankThreads];
-  __shared__ int32_t acc_a[kMaxK], acc_b[kMaxK];
+  __shared__ PickSet ps;
+  if (threadIdx.x == 0) ps.n = 0;
+  __syncthreads();
   const int tl = blockIdx.x;
   const int L = l_min + tl;
   const int64_t N = n - L + 1;
@@ -297,21 +342,12 @@ __global__ __launch_bounds__(kRankThreads) void k_topk_motifs(
       if (c < 0 || !(d < INFINITY)) continue;
       MotifKey m{d, (int32_t)(i < c ? i : c), (int32_t)(i < c ? c : i)};
       if (!motif_less(m, best)) continue;
-      bool ok = true;
-      for (int s = 0; s < got; ++s) {
-        if (iabs64(m.a - acc_a[s]) <= e || iabs64(m.a - acc_b[s]) <= e ||
-            iabs64(m.b - acc_a[s]) <= e || iabs64(m.b - acc_b[s]) <= e) {
-          ok = false;
-          break;
-        }
-      }
-      if (ok) best = m;
+      if (!near_pick(ps, m.a, e, false, L, excl_den, e) && !near_pick(ps, m.b, e, false, L, excl_den, e)) best = m;
     }
     best = block_reduce(best, motif_less, sh);
     if (!(best.d < INFINITY)) break;
     if (threadIdx.x == 0) {
-      acc_a[got] = best.a;
-      acc_b[got] = best.b;
+      pick_insert(ps, best.a, best.b, L);
       motif_ab[((int64_t)tl * k + got) * 2] = best.a;
       motif_ab[((int64_t)tl * k + got) * 2 + 1] = best.b;
       motif_d[(int64_t)tl * k + got] = best.d;
@@ -411,7 +447,9 @@ __global__ __launch_bounds__(kRankThreads) void k_global_rank(
     int excl_den, int km, int kd, int32_t* __restrict__ g_motif_abl, double* __restrict__ g_motif_d,
     int32_t* __restrict__ g_discord_onl, double* __restrict__ g_discord_d) {
   __shared__ GMotifKey sh[kRankThreads];
-  __shared__ int32_t acc_a[kMaxK], acc_b[kMaxK], acc_L[kMaxK];
+  __shared__ PickSet ps;
+  if (threadIdx.x == 0) ps.n = 0;
+  __syncthreads();
   if (g_discord_onl && discord_d) {
     for (int r = threadIdx.x; r < kd; r += blockDim.x) {
       double bestdn = -INFINITY;
@@ -439,6 +477,7 @@ __global__ __launch_bounds__(kRankThreads) void k_global_rank(
     }
   }
   if (!g_motif_abl) return;
+  const int64_t emax = excl_zone(l_min + nlen - 1, excl_den);  // zone of the longest length
   int got = 0;
   for (int r = 0; r < km; ++r) {
     GMotifKey best{INFINITY, 0x7fffffff, 0x7fffffff};
@@ -449,27 +488,17 @@ __global__ __launch_bounds__(kRankThreads) void k_global_rank(
       GMotifKey m{dn, valmp_len[i], (int32_t)i};
       if (!gmotif_less(m, best)) continue;
       const int64_t a = i < c ? i : c, b = i < c ? c : i;
-      bool ok = true;
-      for (int s = 0; s < got; ++s) {
-        const int64_t Lm = m.L > acc_L[s] ? m.L : acc_L[s];
-        const int64_t e = excl_zone(Lm, excl_den);
-        if (iabs64(a - acc_a[s]) <= e || iabs64(a - acc_b[s]) <= e || iabs64(b - acc_a[s]) <= e ||
-            iabs64(b - acc_b[s]) <= e) {
-          ok = false;
-          break;
-        }
-      }
-      if (ok) best = m;
+      if (!near_pick(ps, a, emax, true, m.L, excl_den, 0) && !near_pick(ps, b, emax, true, m.L, excl_den, 0))
+        best = m;
     }
     best = block_reduce(best, gmotif_less, sh);
     if (!(best.dn < INFINITY)) break;
     if (threadIdx.x == 0) {
       const int32_t i = best.i, c = valmp_idx[i];
-      acc_a[got] = i < c ? i : c;
-      acc_b[got] = i < c ? c : i;
-      acc_L[got] = best.L;
-      g_motif_abl[got * 3] = acc_a[got];
-      g_motif_abl[got * 3 + 1] = acc_b[got];
+      const int32_t a = i < c ? i : c, b = i < c ? c : i;
+      pick_insert(ps, a, b, best.L);
+      g_motif_abl[got * 3] = a;
+      g_motif_abl[got * 3 + 1] = b;
       g_motif_abl[got * 3 + 2] = best.L;
       g_motif_d[got * 2] = valmp_dist[i];
       g_motif_d[got * 2 + 1] = best.dn;

@@ -55,13 +55,15 @@ class ValmodConfig(ctypes.Structure):
         ("graph", ctypes.c_int32),
         ("mode", ctypes.c_int32),
         ("m_discords", ctypes.c_int32),
+        ("mset_radius", ctypes.c_double),
+        ("mset_cap", ctypes.c_int32),
     ]
 
 
 OUTPUT_FIELDS = ["prof_dist", "prof_idx", "valmp_norm", "valmp_dist", "valmp_len", "valmp_idx",
                  "motif_ab", "motif_d", "discord_on", "discord_d", "g_motif_abl", "g_motif_d",
                  "g_discord_onl", "g_discord_d", "stats", "mdiscord_on", "mdiscord_d", "g_mdiscord_onl",
-                 "g_mdiscord_d"]
+                 "g_mdiscord_d", "mset_count", "mset_off", "mset_dist"]
 
 
 class ValmodOutputs(ctypes.Structure):
@@ -71,14 +73,14 @@ class ValmodOutputs(ctypes.Structure):
 class ValmodSizes(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in
                 ["prof", "valmp", "motif", "discord", "g_motif", "g_discord", "stats", "series", "mdiscord",
-                 "g_mdiscord"]]
+                 "g_mdiscord", "mset"]]
 
 
 class ValmodLayout(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in
                 ["series", "prof", "valmp", "motif", "discord", "g_motif", "g_discord", "stats",
                  "n", "n0", "nlen"]] + [("l_min", ctypes.c_int32), ("l_max", ctypes.c_int32)] + \
-        [("mdiscord", ctypes.c_int64), ("g_mdiscord", ctypes.c_int64)]
+        [("mdiscord", ctypes.c_int64), ("g_mdiscord", ctypes.c_int64), ("mset", ctypes.c_int64)]
 
 
 _lib = None
@@ -135,7 +137,7 @@ def make_config(n: Sequence[int], l_min: Sequence[int], l_max: Sequence[int], p:
                 k_motifs: int = 1, k_discords: int = 1, excl_den: int = 4, flat_eps: float = 0.0,
                 dtype: str = "f32", precision: str = "fp64", refresh_R: int = 0, path: str = "auto",
                 device: int = 0, lanes: int = 0, graph: bool = False, mode: str = "exact",
-                m_discords: int = 1):
+                m_discords: int = 1, mset_radius: float = 0.0, mset_cap: int = 0):
     """Build a ValmodConfig; returns (config, keepalive arrays)."""
     S = len(n)
     na = (ctypes.c_int64 * S)(*[int(v) for v in n])
@@ -146,7 +148,7 @@ def make_config(n: Sequence[int], l_min: Sequence[int], l_max: Sequence[int], p:
                        ctypes.cast(hi, ctypes.POINTER(ctypes.c_int32)), int(p), int(k_motifs),
                        int(k_discords), int(excl_den), float(flat_eps), DTYPE[dtype], PRECISION[precision],
                        int(refresh_R), PATH[path], int(device), int(lanes), 1 if graph else 0, MODE[mode],
-                       int(m_discords))
+                       int(m_discords), float(mset_radius), int(mset_cap))
     return cfg, (na, lo, hi)
 
 
@@ -216,7 +218,8 @@ class Valmod:
     def __init__(self, series: Union["torch.Tensor", List["torch.Tensor"]], l_min, l_max, p: int = 0,
                  k_motifs: int = 1, k_discords: int = 1, excl_den: int = 4, flat_eps: float = 0.0,
                  precision: str = "fp64", refresh_R: int = 0, path: str = "auto", lanes: int = 0,
-                 graph: bool = False, mode: str = "exact", m_discords: int = 1):
+                 graph: bool = False, mode: str = "exact", m_discords: int = 1, mset_radius: float = 0.0,
+                 mset_cap: int = 0):
         import torch
 
         if isinstance(series, torch.Tensor):
@@ -234,8 +237,9 @@ class Valmod:
         cfg, self._keep = make_config([s.numel() for s in series], lo, hi, p, k_motifs, k_discords,
                                       excl_den, flat_eps, "f32" if dt == torch.float32 else "f64",
                                       precision, refresh_R, path, self.device.index or 0, lanes, graph, mode,
-                                      m_discords)
+                                      m_discords, mset_radius, mset_cap)
         self.m_discords = max(1, int(m_discords))
+        self.mset_cap = int(mset_cap) if mset_radius > 0 else 0
         self.plan = valmod_plan(cfg)
         self.graph = bool(graph)
         self._stream = None
@@ -268,6 +272,9 @@ class Valmod:
             "mdiscord_d": torch.empty(max(1, z["mdiscord"]), dtype=f64, device=dev),
             "g_mdiscord_onl": torch.empty(max(1, 3 * z["g_mdiscord"]), dtype=i32, device=dev),
             "g_mdiscord_d": torch.empty(max(1, 2 * z["g_mdiscord"]), dtype=f64, device=dev),
+            "mset_count": torch.empty(max(1, z["g_motif"] if z["mset"] else 0), dtype=i32, device=dev),
+            "mset_off": torch.empty(max(1, z["mset"]), dtype=i32, device=dev),
+            "mset_dist": torch.empty(max(1, z["mset"]), dtype=f64, device=dev),
         }
         self._outs = ValmodOutputs(*[self.out[f].data_ptr() for f in OUTPUT_FIELDS])
 
@@ -327,6 +334,12 @@ class Valmod:
             out["mdiscord_d"] = o["mdiscord_d"][a:a + nl * m * kd].reshape(nl, m, kd)
             out["g_mdiscord_onl"] = o["g_mdiscord_onl"][3 * g:3 * (g + m * kd)].reshape(m, kd, 3)
             out["g_mdiscord_d"] = o["g_mdiscord_d"][2 * g:2 * (g + m * kd)].reshape(m, kd, 2)
+        cap = self.mset_cap
+        if cap:
+            g, a = L["g_motif"], L["mset"]
+            out["mset_count"] = o["mset_count"][g:g + km]
+            out["mset_off"] = o["mset_off"][a:a + km * cap].reshape(km, cap)
+            out["mset_dist"] = o["mset_dist"][a:a + km * cap].reshape(km, cap)
         return out
 
     def close(self):

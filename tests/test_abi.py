@@ -83,6 +83,13 @@ def test_plan_validation(lib):
     assert _status(m_discords=6) == -1            # p = 5 in _status
     assert _status(m_discords=17, p=20) == -1
     assert _status(m_discords=2, mode="paper") == -1 and _status(m_discords=2, graph=True) == -1
+    # motif sets: radius factor 0 (off) or in (0, 1e6] with 1 <= mset_cap <= 2^20
+    assert _status(mset_radius=4.0, mset_cap=10) == 0 and _status(mset_radius=0.0, mset_cap=-3) == 0
+    assert _status(mset_radius=4.0, mset_cap=0) == -1 and _status(mset_radius=4.0, mset_cap=(1 << 20) + 1) == -1
+    assert _status(mset_radius=-1.0, mset_cap=10) == -1 and _status(mset_radius=float("nan"), mset_cap=10) == -1
+    assert _status(mset_radius=2e6, mset_cap=10) == -1
+    assert _status(mset_radius=4.0, mset_cap=10, mode="paper") == 0
+    assert _status(mset_radius=4.0, mset_cap=10, graph=True) == 0
 
 
 def test_mth_discord_sizes(lib):
@@ -95,6 +102,24 @@ def test_mth_discord_sizes(lib):
         assert L1["mdiscord"] == 4 * 3 * 11 and L1["g_mdiscord"] == 4 * 3
     finally:
         native.valmod_plan_free(plan)
+
+
+def test_motif_set_sizes(lib):
+    """One set per global motif rank and series; mset_cap members stored per set;
+    the motif-set buffers only exist when the radius factor is set."""
+    cfg, keep = native.make_config([1000, 600], [20, 10], [30, 12], p=5, k_motifs=3, mset_radius=4.0, mset_cap=7)
+    plan = native.valmod_plan(cfg)
+    cfg0, keep0 = native.make_config([1000, 600], [20, 10], [30, 12], p=5, k_motifs=3)
+    plan0 = native.valmod_plan(cfg0)
+    try:
+        z = native.valmod_output_sizes(plan)
+        assert z["mset"] == 2 * 3 * 7 and native.valmod_output_sizes(plan0)["mset"] == 0
+        L1 = native.valmod_series_layout(plan, 1)
+        assert L1["mset"] == 3 * 7 and L1["g_motif"] == 3
+        assert native.valmod_workspace_bytes(plan) > native.valmod_workspace_bytes(plan0)
+    finally:
+        native.valmod_plan_free(plan)
+        native.valmod_plan_free(plan0)
 
 
 def test_lanes_split_the_workspace(lib):

@@ -537,3 +537,75 @@ def test_mth_discords_parity(oracle_mod, precision):
         np.testing.assert_allclose(g["mdiscord_d"][t, 0], g["discord_d"][t], rtol=0, atol=TOL64 * np.sqrt(L))
     np.testing.assert_allclose(g["g_mdiscord_d"], r["g_d"], rtol=0, atol=TOL64)
     _say(f"m-th discords {precision}: ok, stats recomputed {g['stats'][:, 2].tolist()}")
+
+
+def _check_motif_sets(oracle_mod, x, lo, hi, g, D, cap, k):
+    """Motif sets of the GPU run against the oracle's, grown from the oracle's own
+    top-k pairs (which must equal the GPU's): member counts and offsets equal,
+    member distances within the FP64 tolerance."""
+    r = oracle_mod.valmod(x, lo, hi, k_motifs=k, k_discords=1)
+    np.testing.assert_array_equal(g["g_motif_abl"], r["g_motif_abl"])
+    count, off, dist = oracle_mod.motif_sets(x, r["g_motif_abl"], r["g_motif_d"][:, 0], D, cap)
+    np.testing.assert_array_equal(g["mset_count"], count)
+    np.testing.assert_array_equal(g["mset_off"], off)
+    for s in range(k):
+        L = int(r["g_motif_abl"][s, 2])
+        m = min(int(count[s]), cap)
+        np.testing.assert_allclose(g["mset_dist"][s, :m], dist[s, :m], rtol=0, atol=TOL64 * np.sqrt(L))
+        assert np.all(np.isnan(g["mset_dist"][s, m:]))
+    return count
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("D", [0.5, 5.0])
+def test_motif_sets_parity(oracle_mod, precision, D):
+    """Variable-length motif sets (Def. data series motif set, radius D * d):
+    random walk n=1800, lengths 24..30, top-4 pairs; the sets of later pairs lose
+    the offsets that earlier sets hold."""
+    x = gen.small_random_walk(1800, 41, np.float32)
+    lo, hi, k, cap = 24, 30, 4, 80
+    g = run_gpu(x, lo, hi, p=5, k_motifs=k, k_discords=1, precision=precision, mset_radius=D, mset_cap=cap)
+    count = _check_motif_sets(oracle_mod, x, lo, hi, g, D, cap, k)
+    _say(f"motif sets {precision} D={D}: counts {count.tolist()}")
+
+
+def test_motif_sets_many_candidates(oracle_mod):
+    """A radius that admits every window: about 15 thousand candidates over
+    several sort tiles, members capped below the count."""
+    x = gen.small_random_walk(5000, 42, np.float32)
+    lo, hi, k, cap, D = 30, 31, 3, 300, 1e3
+    g = run_gpu(x, lo, hi, p=5, k_motifs=k, k_discords=1, mset_radius=D, mset_cap=cap)
+    count = _check_motif_sets(oracle_mod, x, lo, hi, g, D, cap, k)
+    assert count[0] > cap
+    _say(f"motif sets, unbounded radius: counts {count.tolist()}")
+
+
+def test_motif_sets_batched_and_graph(oracle_mod):
+    """Two series of different sizes and lengths in one run (per-series output
+    offsets), then the same plan captured in a graph and replayed."""
+    torch = _torch()
+    from paper_2008_13447_amd import native
+
+    xs = [gen.small_random_walk(1500, 43, np.float32), gen.small_random_walk(2100, 44, np.float32)]
+    lo, hi, k, cap, D = [20, 28], [23, 32], 3, 50, 4.0
+    for graph in (False, True):
+        v = native.Valmod([torch.from_numpy(x).cuda() for x in xs], lo, hi, p=5, k_motifs=k, k_discords=1,
+                          mset_radius=D, mset_cap=cap, graph=graph)
+        for rep in range(2 if graph else 1):
+            v.run()
+            torch.cuda.synchronize()
+            for s, x in enumerate(xs):
+                _check_motif_sets(oracle_mod, x, lo[s], hi[s], v.result(s), D, cap, k)
+        v.close()
+    _say("motif sets batched and graph: ok")
+
+
+def test_motif_sets_global_bucket_map(oracle_mod, monkeypatch):
+    """The member bucket map in global memory (used when a set's buckets do not
+    fit in LDS) gives the same sets as the LDS one."""
+    monkeypatch.setenv("VALMOD_MSET_LDS_BUCKETS", "0")
+    x = gen.small_random_walk(1800, 41, np.float32)
+    lo, hi, k, cap, D = 24, 30, 4, 80, 5.0
+    g = run_gpu(x, lo, hi, p=5, k_motifs=k, k_discords=1, mset_radius=D, mset_cap=cap)
+    count = _check_motif_sets(oracle_mod, x, lo, hi, g, D, cap, k)
+    _say(f"motif sets, global bucket map: counts {count.tolist()}")
