@@ -153,8 +153,30 @@ __device__ __forceinline__ float vmin(float a, float b) {
   asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
   return r;
 }
+// max with the IEEE maxNum rule (a NaN operand yields the other operand)
+__device__ __forceinline__ double vmax(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float vmax(float a, float b) {
+  float r;
+  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
 
-template <typename T, int K, int MODE>
+// Subtracts the FP32 rounding bound from loaded column thresholds (collecting
+// mode; the matrix-profile mode runs in FP64 with no bound).
+template <int n, typename T>
+__device__ __forceinline__ void widen(T* th, T delta) {
+#pragma unroll
+  for (int u = 0; u < n; ++u) th[u] -= delta;
+}
+
+// LIST = false: one work item per workgroup over the whole grid. LIST = true:
+// the workgroups walk the device-side item list (item w, w + gridDim.x, ...),
+// so the grid stays small whatever the list length.
+template <typename T, int K, int MODE, bool LIST>
 __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, const T* __restrict__ g_dg,
                                                 const T* __restrict__ g_invn, const T* __restrict__ g_thr,
                                                 const double* __restrict__ g_xs, const double* __restrict__ g_anc,
@@ -170,24 +192,32 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
   __shared__ QVal q_val[kQueue];  // MODE_MP: packed key; MODE_APPEND: candidate index
   const int t = threadIdx.x;
   const int64_t N = a.N;
+  const int64_t nlist = LIST ? (int64_t)*a.nitems : 0;
+  int64_t w = blockIdx.x;
+  for (;;) {
+  {  // one work item (a skipped item jumps to `next`)
   int64_t seg = blockIdx.x, band = blockIdx.y;
-  if (a.items) {
-    // listed items: one per workgroup; the grid is an upper bound of the device count
+  if (LIST) {
+    if (w >= nlist) return;
+    const int64_t id = a.items[w];
+    seg = id / a.bands;
+    band = id % a.bands;
+  } else if (a.items) {  // (not used: listed items take LIST = true)
     if ((unsigned long long)blockIdx.x >= *a.nitems) return;
     const int64_t id = a.items[blockIdx.x];
     seg = id / a.bands;
     band = id % a.bands;
   }
   const int64_t d0 = a.dstart + band * BW;
-  if (d0 > N - 1) return;
+  if (d0 > N - 1) goto next;
   const int64_t i0 = seg * a.H;
   const int64_t rowEnd = N - d0;
-  if (i0 >= rowEnd) return;
+  if (i0 >= rowEnd) goto next;
   // FP32 recurrence: rigorous bound of the rounding of rho over this item
   T delta = (T)0;
   if (a.delta) {
     const float dl_ = a.delta[seg * a.bands + band];
-    if (!(dl_ <= a.delta_max)) return;  // left to the FP64 kernel
+    if (!(dl_ <= a.delta_max)) goto next;  // left to the FP64 kernel
     delta = (T)dl_;
   }
   const int rows = (int)((i0 + a.H < rowEnd ? i0 + a.H : rowEnd) - i0);
@@ -227,6 +257,10 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
     load_run<K>(g_dg + c0 + K, Ydg);
     load_run<K>(g_invn + c0 + K, Yinv);
     load_run<K>(g_thr + c0 + K, Ythr);
+    if (MODE == MODE_APPEND) {
+      widen<K>(Xthr, delta);
+      widen<K>(Ythr, delta);
+    }
   }
   int qn = 0;  // queue fill (wave-uniform)
   unsigned long long ev_steps = 0;
@@ -280,16 +314,36 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
 #pragma unroll
     for (int u = 0; u < K; ++u) {
       const int64_t i = ib + u;
-      // correlation of every cell and the test against both owners' thresholds
-      bool pass = false;
+      // correlation of every cell against both owners' thresholds. FP32: the
+      // sign of rho - min(thr_j, thr_i) with one rounding (fma), reduced by a
+      // max over the lane's cells (no per-cell mask traffic)
+      bool any_pass;
+      if constexpr (sizeof(T) == 4) {
+        T dq[K];
 #pragma unroll
-      for (int q = 0; q < K; ++q) {
-        const int s = (q + u) % K;
-        const T inv = s < u ? Qinv[s] : Pinv[s];
-        const T th = (s < u ? Qthr[s] : Pthr[s]) - delta;
-        pass |= (C[q] * inv) * rinv[u] >= vmin(th, rthr[u]);
+        for (int q = 0; q < K; ++q) {
+          const int s = (q + u) % K;
+          const T inv = s < u ? Qinv[s] : Pinv[s];
+          const T th = s < u ? Qthr[s] : Pthr[s];
+          dq[q] = fma(C[q] * inv, rinv[u], -vmin(th, rthr[u]));
+        }
+#pragma unroll
+        for (int w = 1; w < K; w *= 2)  // pairwise, to keep the dependency chain short
+#pragma unroll
+          for (int q = 0; q + w < K; q += 2 * w) dq[q] = vmax(dq[q], dq[q + w]);
+        any_pass = __builtin_expect(__any(dq[0] >= (T)0), 0);
+      } else {
+        // FP64: per-cell comparisons (this form allocates registers better there)
+        bool pass = false;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          const int s = (q + u) % K;
+          const T inv = s < u ? Qinv[s] : Pinv[s];
+          const T th = s < u ? Qthr[s] : Pthr[s];
+          pass |= (C[q] * inv) * rinv[u] >= vmin(th, rthr[u]);
+        }
+        any_pass = __any(pass);
       }
-      const bool any_pass = __any(pass);
       if (MODE == MODE_MP && any_pass) {
         ++ev_steps;
         // at most K column entries per lane and one row entry per step
@@ -303,7 +357,7 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
           T& th = s < u ? Qthr[s] : Pthr[s];
           const T rho = (C[q] * inv) * rinv[u];
           const bool ok = j < N && rinv[u] > (T)0 && inv > (T)0;
-          const bool col = ok && rho >= th - delta;
+          const bool col = ok && rho >= th;  // (matrix-profile mode: no rounding bound)
           const uint64_t key = col ? make_key((double)rho, i) : kEmptyKey;
           push(col, (int32_t)j, key);
           if (col) {
@@ -331,8 +385,10 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
           const T inv = s < u ? Qinv[s] : Pinv[s];
           const T th = s < u ? Qthr[s] : Pthr[s];
           const T rho = (C[q] * inv) * rinv[u];
-          const bool ok = j < N && rinv[u] > (T)0 && inv > (T)0;
-          mcol[q] = __ballot(ok && rho >= th - delta);
+          // FP32: flat and padded windows have a NaN inverse norm, so rho is NaN
+          // and fails both tests; FP64: zero inverse norms are tested
+          const bool ok = sizeof(T) == 4 || (j < N && rinv[u] > (T)0 && inv > (T)0);
+          mcol[q] = __ballot(ok && rho >= th);  // th already lowered by the bound
           mrow[q] = __ballot(ok && rho >= rthr[u]);
           tot += __popcll(mcol[q]) + __popcll(mrow[q]);
         }
@@ -360,11 +416,13 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
         load_run<HK>(g_dg + cn, Pdg);
         load_run<HK>(g_invn + cn, Pinv);
         load_run<HK>(g_thr + cn, Pthr);
+        if (MODE == MODE_APPEND) widen<HK>(Pthr, delta);
       } else if (u == K - 1) {
         load_run<HK>(g_df + cn + HK, Pdf + HK);
         load_run<HK>(g_dg + cn + HK, Pdg + HK);
         load_run<HK>(g_invn + cn + HK, Pinv + HK);
         load_run<HK>(g_thr + cn + HK, Pthr + HK);
+        if (MODE == MODE_APPEND) widen<HK>(Pthr + HK, delta);
       }
     }
   };
@@ -375,6 +433,11 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
   }
   if (qn > 0) flush();
   if (a.events && t == 0 && ev_steps) atomicAdd(&a.events[0], ev_steps);
+  }
+  next:
+  if (!LIST) return;
+  w += gridDim.x;
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -481,7 +544,9 @@ __global__ void k_to_f32(const double* __restrict__ df, const double* __restrict
   if (i >= n) return;
   df32[i] = (float)df[i];
   dg32[i] = (float)dg[i];
-  inv32[i] = (float)invn[i];
+  // a flat or padded window (zero inverse norm) gets NaN: every correlation
+  // it takes part in is NaN and fails every threshold test of the FP32 pass
+  inv32[i] = invn[i] > 0.0 ? (float)invn[i] : __int_as_float(0x7fc00000);
 }
 
 __global__ void k_thr_to_f32(const double* __restrict__ thr, int64_t n, float* __restrict__ thr32) {
@@ -520,6 +585,8 @@ hipError_t launch_anchor(const double* xs, int64_t n, int L, bool init, int64_t 
   return hipGetLastError();
 }
 
+constexpr int64_t kListGrid = 1024;  // workgroups of a listed-items launch
+
 template <typename T, int K>
 static hipError_t launch_pass_k(const PassLaunch& p, hipStream_t st) {
   const PassGrid g = pass_grid(p.N, p.e, p.dstart, K, p.H);
@@ -543,15 +610,27 @@ static hipError_t launch_pass_k(const PassLaunch& p, hipStream_t st) {
   a.bands = g.bands;
   a.L = p.L;
   if (p.items && (p.nitems <= 0 || !p.nitems_dev)) return p.nitems < 0 ? hipErrorInvalidValue : hipSuccess;
-  const dim3 grid = p.items ? dim3((unsigned)p.nitems, 1) : dim3((unsigned)g.segs, (unsigned)g.bands);
   const T* df = (const T*)(sizeof(T) == 8 ? (const void*)p.df : (const void*)p.df32);
   const T* dg = (const T*)(sizeof(T) == 8 ? (const void*)p.dg : (const void*)p.dg32);
   const T* inv = (const T*)(sizeof(T) == 8 ? (const void*)p.invn : (const void*)p.inv32);
   const T* thr = (const T*)(sizeof(T) == 8 ? (const void*)p.thr : (const void*)p.thr32);
+  if (p.items) {
+    // listed items (the FP64 re-run of FP32 items, collecting mode): a small
+    // grid walks the list, so an empty or short list costs a few microseconds
+    if constexpr (sizeof(T) == 8) {
+      if (!p.append) return hipErrorInvalidValue;
+      const dim3 grid((unsigned)(p.nitems < kListGrid ? p.nitems : kListGrid), 1);
+      k_pass<T, K, MODE_APPEND, true><<<grid, kWave, 0, st>>>(df, dg, inv, thr, p.xs, p.anc, p.A, a);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+  const dim3 grid((unsigned)g.segs, (unsigned)g.bands);
   if (p.append)
-    k_pass<T, K, MODE_APPEND><<<grid, kWave, 0, st>>>(df, dg, inv, thr, p.xs, p.anc, p.A, a);
+    k_pass<T, K, MODE_APPEND, false><<<grid, kWave, 0, st>>>(df, dg, inv, thr, p.xs, p.anc, p.A, a);
   else
-    k_pass<T, K, MODE_MP><<<grid, kWave, 0, st>>>(df, dg, inv, thr, p.xs, p.anc, p.A, a);
+    k_pass<T, K, MODE_MP, false><<<grid, kWave, 0, st>>>(df, dg, inv, thr, p.xs, p.anc, p.A, a);
   return hipGetLastError();
 }
 
