@@ -265,8 +265,12 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
   int qn = 0;  // queue fill (wave-uniform)
   unsigned long long ev_steps = 0;
 
+  // MODE_MP entries: (owner, packed key). MODE_APPEND entries: one per lane and
+  // step, (row i, lane t | cell mask << 6): bit q of the mask appends row i to
+  // column owner i + d0 + K t + q, bit K + q appends that column to row owner i.
   auto flush = [&]() {
     __syncthreads();
+    unsigned long long hits = 0;
     for (int b = 0; b < qn; b += kWave) {
       if (b + t < qn) {
         const int32_t own = q_owner[b + t];
@@ -276,12 +280,28 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
           const double nt = key_threshold(v);
           if (nt > a.thr[own]) a.thr[own] = nt;  // racy but every stored value is a real candidate's bound
         } else {
-          const uint32_t pos = atomicAdd(&a.cnt[own], 1u);
-          if ((int64_t)pos < a.cap) a.buf[(int64_t)own * a.cap + pos] = (int32_t)v;
+          const int64_t j0 = (int64_t)own + d0 + (int64_t)K * (int64_t)(v & 63u);
+          uint32_t m = (uint32_t)(v >> 6);
+          while (m) {
+            const int q = __ffs(m) - 1;
+            m &= m - 1;
+            const bool col = q < K;
+            const int64_t j = j0 + (col ? q : q - K);
+            const int64_t o = col ? j : (int64_t)own;
+            const uint32_t pos = atomicAdd(&a.cnt[o], 1u);
+            if ((int64_t)pos < a.cap) a.buf[o * a.cap + pos] = (int32_t)(col ? (int64_t)own : j);
+            hits += 1;
+          }
         }
       }
     }
-    if (a.events && t == 0) atomicAdd(&a.events[1], (unsigned long long)qn);
+    if (MODE == MODE_MP) {
+      if (a.events && t == 0) atomicAdd(&a.events[1], (unsigned long long)qn);
+    } else if (a.events) {
+#pragma unroll
+      for (int m = kWave / 2; m >= 1; m >>= 1) hits += shfl_xor_u64(hits, m);
+      if (t == 0 && hits) atomicAdd(&a.events[1], hits);
+    }
     __syncthreads();
     qn = 0;
   };
@@ -375,9 +395,8 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
         }
       } else if (MODE == MODE_APPEND && any_pass) {
         ++ev_steps;
-        // up to two entries per cell (column and row owner): count them first
-        uint64_t mcol[K], mrow[K];
-        int tot = 0;
+        // one queue entry per lane with a passing cell: its column and row bits
+        uint32_t mask = 0;
 #pragma unroll
         for (int q = 0; q < K; ++q) {
           const int s = (q + u) % K;
@@ -388,17 +407,11 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
           // FP32: flat and padded windows have a NaN inverse norm, so rho is NaN
           // and fails both tests; FP64: zero inverse norms are tested
           const bool ok = sizeof(T) == 4 || (j < N && rinv[u] > (T)0 && inv > (T)0);
-          mcol[q] = __ballot(ok && rho >= th);  // th already lowered by the bound
-          mrow[q] = __ballot(ok && rho >= rthr[u]);
-          tot += __popcll(mcol[q]) + __popcll(mrow[q]);
+          mask |= (ok && rho >= th) ? (1u << q) : 0u;  // th already lowered by the bound
+          mask |= (ok && rho >= rthr[u]) ? (1u << (K + q)) : 0u;
         }
-        if (qn + tot > kQueue) flush();  // tot <= 2 * kWave * K == kQueue
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
-          const int64_t j = i + dl + q;
-          push_m(mcol[q], (mcol[q] >> t) & 1, (int32_t)j, (uint64_t)i);
-          push_m(mrow[q], (mrow[q] >> t) & 1, (int32_t)i, (uint64_t)j);
-        }
+        if (qn + kWave > kQueue) flush();
+        push(mask != 0, (int32_t)i, (uint64_t)((uint32_t)t | (mask << 6)));
       }
       // advance every diagonal one row: C(i+1, j+1) = C(i, j) + df_i dg_j + df_j dg_i
 #pragma unroll
