@@ -22,7 +22,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
-  size_t xs, A, B, mu, sig, invn, flat, df, dg, sw32, thr, thr32, best, counters, anc;
+  size_t xs, A, B, A2, B2, mu, sig, invn, flat, df, dg, sw32, thr, thr32, best, counters, anc;
   size_t hc, hS, hn, hbound, hsig, acnt, abuf, fail, big, lbm, rec, part, mvals, mnn, mkeys;
   size_t df32, dg32, inv32, bsw_max, bsw_min, bdf_max, bdg_max, delta, hard;
   size_t ms_keys0, ms_keys1, ms_vals0, ms_vals1, ms_hist, ms_meta, ms_count, ms_taken, ms_bucket;
@@ -83,8 +83,8 @@ PassGeom pass_geom(int64_t n, int32_t l_min, int32_t excl_den, bool fp32, int32_
 
 }  // namespace
 
-// A lane runs its series one after another on its own stream (and a second
-// stream for the FP64 re-run of listed FP32 work items); lanes run concurrently.
+// A lane runs its series one after another on its own stream; lanes run
+// concurrently.
 struct Lane {
   std::vector<int> series;  // assigned series, in run order
   size_t base = 0;          // byte offset of the lane's workspace
@@ -92,8 +92,8 @@ struct Lane {
   int64_t nmax = 0, n0max = 0, ancmax = 0, itemmax = 0, total_lengths = 0;
   double cost = 0.0;
   // device resources (created on the plan's device at the first run)
-  hipStream_t st = nullptr, aux = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr, ready = nullptr, done = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t ready = nullptr, done = nullptr;
   unsigned long long* hcnt = nullptr;  // pinned host copy of a few counters
   std::vector<hipEvent_t> ev;         // pass timing
   int64_t nev = 0;                     // events recorded by the last run
@@ -154,6 +154,8 @@ static size_t layout_lane(const valmod_plan_s* P, Lane& ln) {
   w.xs = take(np * 8);
   w.A = take(wp * 8);
   w.B = take(wp * 8);
+  w.A2 = take(wp * 8);  // the anchored sums alternate between two buffers by length
+  w.B2 = take(wp * 8);
   w.mu = take(wp * 8);
   w.sig = take(wp * 8);
   w.invn = take(wp * 8);
@@ -257,7 +259,7 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
   if (cfg->lanes < 0 || cfg->lanes > 64 || (cfg->graph != 0 && cfg->graph != 1)) return fail(VALMOD_E_ARG);
   // a captured run takes no host decisions: partial profiles (which need them) are off
   if (cfg->graph && cfg->path == VALMOD_PATH_RECOMPUTE) return fail(VALMOD_E_ARG);
-  // capture of the FP32 path (second stream per lane, collecting pass and merge) is not supported
+  // capture of the FP32 path is not supported
   if (cfg->graph && cfg->precision == VALMOD_PREC_FP32_REFRESH) return fail(VALMOD_E_ARG);
   if (cfg->mode != VALMOD_MODE_EXACT && cfg->mode != VALMOD_MODE_PAPER) return fail(VALMOD_E_ARG);
   if (cfg->m_discords < 0 || cfg->m_discords > 16) return fail(VALMOD_E_ARG);
@@ -395,14 +397,13 @@ static void release_resources(valmod_plan_s* P) {
   for (Lane& ln : P->lanes) {
     for (hipEvent_t e : ln.ev) (void)hipEventDestroy(e);
     ln.ev.clear();
-    for (hipEvent_t* e : {&ln.fork, &ln.join, &ln.ready, &ln.done})
+    for (hipEvent_t* e : {&ln.ready, &ln.done})
       if (*e) {
         (void)hipEventDestroy(*e);
         *e = nullptr;
       }
     if (ln.st) (void)hipStreamDestroy(ln.st);
-    if (ln.aux) (void)hipStreamDestroy(ln.aux);
-    ln.st = ln.aux = nullptr;
+    ln.st = nullptr;
     if (ln.hcnt) (void)hipHostFree(ln.hcnt);
     ln.hcnt = nullptr;
   }
@@ -446,8 +447,7 @@ static hipError_t ensure_resources(valmod_plan_s* P) {
   ok(hipEventCreate(&P->g1));
   for (Lane& ln : P->lanes) {
     ok(hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking));
-    ok(hipStreamCreateWithFlags(&ln.aux, hipStreamNonBlocking));
-    for (hipEvent_t* ev : {&ln.fork, &ln.join, &ln.ready, &ln.done}) ok(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+    for (hipEvent_t* ev : {&ln.ready, &ln.done}) ok(hipEventCreateWithFlags(ev, hipEventDisableTiming));
     ok(hipHostMalloc((void**)&ln.hcnt, 8 * sizeof(unsigned long long), hipHostMallocDefault));
     for (int64_t i = 0; e == hipSuccess && i < 4 * ln.total_lengths; ++i) {
       hipEvent_t ev;
@@ -474,7 +474,7 @@ struct LaneRun {
   bool capture = false;
   hipError_t err = hipSuccess;
   // workspace
-  double *xs, *A, *B, *mu, *sig, *invn, *df, *dg, *thr, *anc, *hS, *hbound, *hsig, *lbm;
+  double *xs, *A, *B, *A2, *B2, *mu, *sig, *invn, *df, *dg, *thr, *anc, *hS, *hbound, *hsig, *lbm;
   uint8_t* flat;
   float *sw32, *thr32, *df32, *dg32, *inv32, *bsw_max, *bsw_min, *bdf_max, *bdg_max, *delta;
   uint64_t* best;
@@ -502,6 +502,8 @@ struct LaneRun {
     xs = (double*)(b + w.xs);
     A = (double*)(b + w.A);
     B = (double*)(b + w.B);
+    A2 = (double*)(b + w.A2);
+    B2 = (double*)(b + w.B2);
     mu = (double*)(b + w.mu);
     sig = (double*)(b + w.sig);
     invn = (double*)(b + w.invn);
@@ -610,9 +612,39 @@ LaneRun::Status LaneRun::advance() {
 
   const bool sweep = heaps_on && base > 0 && L > Ls.l_min;
   if (phase == 0) {
-    LCHECK(launch_stats(xs, N, L, L == Ls.l_min, P->cfg.flat_eps, A, B, mu, sig, invn, flat, &cnt[CNT_NFLAT], st));
+    // statistics, recurrence inputs and FP32 copies at L; the sums of L go to the
+    // other buffer, which then becomes the current one
+    WindowPrep wpr{};
+    wpr.xs = xs;
+    wpr.N = N;
+    wpr.L = L;
+    wpr.first = L == Ls.l_min ? 1 : 0;
+    wpr.flat_eps = P->cfg.flat_eps;
+    wpr.A_in = A;
+    wpr.B_in = B;
+    wpr.A_out = A2;
+    wpr.B_out = B2;
+    wpr.mu = mu;
+    wpr.sig = sig;
+    wpr.invn = invn;
+    wpr.flat = flat;
+    wpr.nflat = &cnt[CNT_NFLAT];
+    wpr.df = df;
+    wpr.dg = dg;
+    wpr.sw32 = sw32;
+    if (fp32) {
+      wpr.df32 = df32;
+      wpr.dg32 = dg32;
+      wpr.inv32 = inv32;
+      wpr.bsw_max = bsw_max;
+      wpr.bsw_min = bsw_min;
+      wpr.bdf_max = bdf_max;
+      wpr.bdg_max = bdg_max;
+    }
+    LCHECK(launch_window_prep(wpr, st));
+    std::swap(A, A2);
+    std::swap(B, B2);
     if (G.table) LCHECK(launch_anchor(xs, n, L, L == Ls.l_min, G.H, G.dstart, G.segs, G.stride, G.stride, anc, st));
-    LCHECK(launch_prep_f64(xs, mu, sig, invn, N, L, df, dg, sw32, st));
     if (sweep) {
       // Alg. ComputeSubMP: sweep the partial profiles, certify by the lower bound;
       // the choice between row recompute and a full pass needs the counts
@@ -672,17 +704,13 @@ LaneRun::Status LaneRun::advance() {
     return e1;
   };
   bool fp32_ready = false;
-  // FP32 inputs and the per-item rounding bounds at this length; items over
-  // the limit are listed for the FP64 kernel
+  // per-item rounding bounds of the FP32 recurrence at this length (its inputs
+  // come from the window prep); items over the limit are listed for the FP64 kernel
   auto fp32_setup = [&]() -> hipError_t {
     if (fp32_ready) return hipSuccess;
     fp32_ready = true;
-    hipError_t e1 =
-        launch_fp32_prep(sig, invn, df, dg, N, L, df32, dg32, inv32, bsw_max, bsw_min, bdf_max, bdg_max, st);
-    if (e1 == hipSuccess)
-      e1 = launch_fp32_items(bsw_max, bsw_min, bdf_max, bdg_max, N, e, G.dstart, G.K, G.H, delta_max, delta, hard,
+    return launch_fp32_items(bsw_max, bsw_min, bdf_max, bdg_max, N, e, G.dstart, G.K, G.H, delta_max, delta, hard,
                              &cnt[CNT_HARD], st);
-    return e1;
   };
   bool recompute = false;  // process the recompute list (its length is a device counter)
   // collecting pass above per-owner thresholds from the candidates of `src`,
@@ -691,28 +719,25 @@ LaneRun::Status LaneRun::advance() {
     hipError_t e1 = sweep ? launch_zero_counters(&cnt[CNT_NFAIL], 1, st) : hipSuccess;
     if (e1 == hipSuccess)
       e1 = launch_seed_append(xs, A, invn, flat, src, N, L, e, p_eff, p_eff == 1 ? 0 : D, margin, best_exact, thr,
-                              acnt, fail, &cnt[CNT_NFAIL], st);
+                              fp32 ? thr32 : nullptr, acnt, fail, &cnt[CNT_NFAIL], st);
     PassLaunch q = pl;
     q.append = true;
     if (fp32) {
       if (e1 == hipSuccess) e1 = fp32_setup();
-      if (e1 == hipSuccess) e1 = launch_thr_to_f32(thr, N + kPad, thr32, st);
-      // listed items run in FP64 on the second stream, beside the FP32 pass
+      q.fp32 = true;
+      q.delta = delta;
+      q.delta_max = delta_max;
+      if (e1 == hipSuccess) e1 = timed_pass(q);
+      // then the listed items in FP64 (a small grid that walks the device-side
+      // list; on the same stream: a second stream's fork and join cost more
+      // than the overlap gained, since the list is usually empty)
       PassLaunch h = pl;
       h.append = true;
       h.items = hard;
       h.nitems = grid.segs * grid.bands;
       h.nitems_dev = &cnt[CNT_HARD];
-      if (e1 == hipSuccess) e1 = hipEventRecord(ln->fork, st);
-      if (e1 == hipSuccess) e1 = hipStreamWaitEvent(ln->aux, ln->fork, 0);
-      if (e1 == hipSuccess) e1 = launch_pass(h, ln->aux);
-      if (e1 == hipSuccess) e1 = hipEventRecord(ln->join, ln->aux);
+      if (e1 == hipSuccess) e1 = launch_pass(h, st);
       ++passes;
-      q.fp32 = true;
-      q.delta = delta;
-      q.delta_max = delta_max;
-      if (e1 == hipSuccess) e1 = timed_pass(q);
-      if (e1 == hipSuccess) e1 = hipStreamWaitEvent(st, ln->join, 0);
     } else if (e1 == hipSuccess) {
       e1 = timed_pass(q);
     }
@@ -807,7 +832,7 @@ LaneRun::Status LaneRun::advance() {
                                  st));
   else if (recompute)
     LCHECK(launch_recompute(xs, A, invn, flat, fail, &cnt[CNT_NFAIL], N, N, L, e, best, st));
-  LCHECK(launch_finalize(xs, mu, sig, best, N, L, pd, pi, vnorm, vdist, vlen, vidx, st));
+  LCHECK(launch_finalize(xs, mu, sig, best, N, N0, L, pd, pi, vnorm, vdist, vlen, vidx, st));
   if (md > 1) {
     const int kd = P->cfg.k_discords;
     const int64_t at = Ls.mdiscord + t * md * kd;
@@ -816,7 +841,6 @@ LaneRun::Status LaneRun::advance() {
                                st));
   }
   if (paper_split) LCHECK(launch_mark_partial(part, &cnt[CNT_NPART], N, lbm, pd, pi, st));
-  LCHECK(launch_fill_tail(N, N0, pd, pi, st));
   LCHECK(launch_record_stats(cnt, o->stats ? o->stats + Ls.stats + t * VALMOD_NSTATS : nullptr, full ? 1 : 0,
                              nvalid, nswept_fail, paper_split == 1 ? 2 : (recompute ? 1 : 0), passes, st));
   // VALMOD_PROGRESS=k: one line on stderr every k lengths, once the length has run

@@ -60,6 +60,17 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
   return v;
 }
 
+__device__ __forceinline__ double wave_max_f64(double v) {
+#pragma unroll
+  for (int m = kWave / 2; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, kWave));
+  return v;
+}
+__device__ __forceinline__ double wave_min_f64(double v) {
+#pragma unroll
+  for (int m = kWave / 2; m >= 1; m >>= 1) v = fmin(v, __shfl_xor(v, m, kWave));
+  return v;
+}
+
 __device__ __forceinline__ int64_t iabs64(int64_t v) { return v < 0 ? -v : v; }
 
 __host__ __device__ __forceinline__ int64_t excl_zone(int64_t L, int64_t den) {

@@ -95,9 +95,13 @@ __global__ __launch_bounds__(kWave) void k_seed_append(const double* __restrict_
                                                        const uint8_t* __restrict__ flat,
                                                        const int32_t* __restrict__ src, int64_t N, int L, int64_t e,
                                                        int p, int D, double margin, int best_exact,
-                                                       double* __restrict__ thr,
+                                                       double* __restrict__ thr, float* __restrict__ thr32,
                                                        uint32_t* __restrict__ cnt, int32_t* __restrict__ fail,
                                                        unsigned long long* __restrict__ nfail) {
+  auto set_thr = [&](int64_t w, double v) {
+    thr[w] = v;
+    if (thr32) thr32[w] = __double2float_rd(v);
+  };
   constexpr int OPW = kWave / G;  // owners per wavefront
   const int t = threadIdx.x, l = t % G, gb = t - l;
   const int64_t o = (int64_t)blockIdx.x * OPW + t / G;
@@ -136,22 +140,22 @@ __global__ __launch_bounds__(kWave) void k_seed_append(const double* __restrict_
   if (!live) return;
   if (l == 0) cnt[o] = 0;
   if (fl) {
-    if (l == 0) thr[o] = 3.0;  // not an owner
+    if (l == 0) set_thr(o, 3.0);  // not an owner
     return;
   }
   if (mg == 0) {
     if (l == 0) {
-      thr[o] = 3.0;
+      set_thr(o, 3.0);
       if (!best_exact) push_fail(fail, nfail, o);
     }
     return;
   }
   if ((int64_t)p >= N - 1) {
-    if (l == 0) thr[o] = -2.0 - margin;  // a profile can hold every candidate: collect them all
+    if (l == 0) set_thr(o, -2.0 - margin);  // a profile can hold every candidate: collect them all
     return;
   }
   const int want = (p < mg ? p : mg) - 1;
-  if (ok && rank == want) thr[o] = rho - margin;
+  if (ok && rank == want) set_thr(o, rho - margin);
 }
 
 // --------------------------------------------------------------------------
@@ -566,14 +570,14 @@ hipError_t launch_mth_values(const double* A, const double* invn, const uint8_t*
 
 hipError_t launch_seed_append(const double* xs, const double* A, const double* invn, const uint8_t* flat,
                               const int32_t* src, int64_t N, int L, int64_t e, int p, int D, double margin,
-                              int best_exact, double* thr, uint32_t* cnt, int32_t* fail, unsigned long long* nfail,
-                              hipStream_t st) {
+                              int best_exact, double* thr, float* thr32, uint32_t* cnt, int32_t* fail,
+                              unsigned long long* nfail, hipStream_t st) {
   if (N <= 0) return hipSuccess;
   if (D < 0 || 4 * D + 2 > kWave) return hipErrorInvalidValue;
   const int seeds = 4 * D + 2;  // D = 0: the single candidate src[o], one lane per owner
 #define SEED_LAUNCH(G)                                                                                     \
   k_seed_append<G><<<blocks_for(N, kWave / (G)), kWave, 0, st>>>(xs, A, invn, flat, src, N, L, e, p, D, margin, \
-                                                                 best_exact, thr, cnt, fail, nfail)
+                                                                 best_exact, thr, thr32, cnt, fail, nfail)
   if (D == 0)
     SEED_LAUNCH(1);
   else if (seeds <= 8)

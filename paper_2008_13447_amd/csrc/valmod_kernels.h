@@ -64,24 +64,34 @@ hipError_t launch_anchor(const double* xs, int64_t n, int L, bool init, int64_t 
 
 hipError_t launch_convert(const void* in, int dtype, int64_t n, int64_t npad, double* xs, int* err,
                           hipStream_t st);
-hipError_t launch_stats(const double* xs, int64_t N, int L, int first, double flat_eps, double* A,
-                        double* B, double* mu, double* sig, double* invn, uint8_t* flat,
-                        unsigned long long* nflat, hipStream_t st);
-hipError_t launch_prep_f64(const double* xs, const double* mu, const double* sig, const double* invn, int64_t N,
-                           int L, double* df, double* dg, float* sw32, hipStream_t st);
+// per-window inputs of one length: statistics, recurrence inputs and (df32 != null)
+// the FP32 copies and the per-64-window extrema of the FP32 rounding bound
+struct WindowPrep {
+  const double* xs;
+  int64_t N;
+  int L;
+  int first;  // 1: sums formed directly (first length of a series)
+  double flat_eps;
+  const double *A_in, *B_in;  // sums of the previous length (unused when first)
+  double *A_out, *B_out;      // sums of this length
+  double *mu, *sig, *invn;
+  uint8_t* flat;
+  unsigned long long* nflat;
+  double *df, *dg;
+  float* sw32;
+  float *df32, *dg32, *inv32, *bsw_max, *bsw_min, *bdf_max, *bdg_max;  // FP32 path (null: none)
+};
+hipError_t launch_window_prep(const WindowPrep& w, hipStream_t st);
 hipError_t launch_seed_mp(const double* xs, const double* mu, const double* invn, const uint8_t* flat,
                           const int32_t* prev_idx, int64_t N, int L, int64_t e, uint64_t* best,
                           double* thr, float* thr32, hipStream_t st);
 hipError_t launch_pass(const PassLaunch& p, hipStream_t st);
-hipError_t launch_fp32_prep(const double* sig, const double* invn, const double* df, const double* dg, int64_t N,
-                            int L, float* df32, float* dg32, float* inv32, float* bsw_max, float* bsw_min,
-                            float* bdf_max, float* bdg_max, hipStream_t st);
 hipError_t launch_fp32_items(const float* bsw_max, const float* bsw_min, const float* bdf_max, const float* bdg_max,
                              int64_t N, int64_t e, int64_t dstart, int K, int64_t H, float delta_max, float* delta,
                              int32_t* hard, unsigned long long* nhard, hipStream_t st);
-hipError_t launch_thr_to_f32(const double* thr, int64_t n, float* thr32, hipStream_t st);
+// (also writes +inf / -1 to the profile row's entries N .. N0 - 1)
 hipError_t launch_finalize(const double* xs, const double* mu, const double* sig, const uint64_t* best,
-                           int64_t N, int L, double* prof_dist, int32_t* prof_idx, double* valmp_norm,
+                           int64_t N, int64_t N0, int L, double* prof_dist, int32_t* prof_idx, double* valmp_norm,
                            double* valmp_dist, int32_t* valmp_len, int32_t* valmp_idx, hipStream_t st);
 // Writes one stats row (host-known values and the per-length device counters;
 // `recomputed`: 0 none, 1 the recompute list (CNT_NFAIL), 2 the paper-mode list
@@ -93,7 +103,6 @@ hipError_t launch_fill_counters(unsigned long long* p, int n, unsigned long long
 inline hipError_t launch_zero_counters(unsigned long long* p, int n, hipStream_t st) {
   return launch_fill_counters(p, n, 0ull, st);
 }
-hipError_t launch_fill_tail(int64_t from, int64_t to, double* prof_dist, int32_t* prof_idx, hipStream_t st);
 hipError_t launch_valmp_init(int64_t N0, double* norm, double* dist, int32_t* len, int32_t* idx,
                              hipStream_t st);
 hipError_t launch_rankings(const double* prof_dist, const int32_t* prof_idx, int64_t N0, int64_t n, int l_min,
@@ -106,10 +115,11 @@ hipError_t launch_global_rank(const double* valmp_norm, const double* valmp_dist
                               double* g_discord_d, hipStream_t st);
 
 // partial distance profiles (valmod_heap.hip)
+// thr32 (optional): FP32 copy of each written threshold, rounded down
 hipError_t launch_seed_append(const double* xs, const double* A, const double* invn, const uint8_t* flat,
                               const int32_t* src, int64_t N, int L, int64_t e, int p, int D, double margin,
-                              int best_exact, double* thr, uint32_t* cnt, int32_t* fail, unsigned long long* nfail,
-                              hipStream_t st);
+                              int best_exact, double* thr, float* thr32, uint32_t* cnt, int32_t* fail,
+                              unsigned long long* nfail, hipStream_t st);
 hipError_t launch_merge(const double* xs, const double* A, const double* invn, const double* sig, const uint8_t* flat,
                         const double* thr, const uint32_t* cnt, const int32_t* buf, int64_t cap, int64_t N, int L,
                         int p, int keep, double margin, int best_exact, int32_t* hc, double* hS, int32_t* hn,

@@ -27,81 +27,126 @@ __global__ void k_convert(const TIn* __restrict__ in, int64_t n, int64_t npad, d
 }
 
 // --------------------------------------------------------------------------
-// Window statistics at length L (Eq. 6: mean and population deviation).
-// Sums are anchored at the window's first value: A = sum(x - x0),
-// B = sum((x - x0)^2). At the first length they are formed directly; each next
-// length adds one term (the window grows by one point), so the cost is O(1) per
-// window per length and no large-offset cancellation occurs.
-__global__ void k_stats(const double* __restrict__ xs, int64_t N, int L, int first, double flat_eps,
-                        double* __restrict__ A, double* __restrict__ B, double* __restrict__ mu,
-                        double* __restrict__ sig, double* __restrict__ invn,
-                        uint8_t* __restrict__ flat, unsigned long long* __restrict__ nflat) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool fl = false;
-  if (i < N) {
-    const double x0 = xs[i];
-    double a, b;
+// Per-window inputs at length L, in one pass over the windows.
+//
+// Statistics (Eq. 6: mean and population deviation). Sums are anchored at the
+// window's first value: A = sum(x - x0), B = sum((x - x0)^2). At the first
+// length they are formed directly; each next length adds one term (the window
+// grows by one point) to the previous length's sums (A_in, B_in -> A_out,
+// B_out: two buffers, so no window reads a neighbour's updated sum), so the
+// cost is O(1) per window per length and no large-offset cancellation occurs.
+//
+// Co-moment recurrence inputs. With C(i,j) = sum_k (x_{i+k} - mu_i)(x_{j+k} - mu_j),
+// one diagonal step is
+//   C(i+1, j+1) = C(i, j) + df_i * dg_j + df_j * dg_i,
+//   df_i = (x_{i+L} - x_i) / 2,  dg_i = (x_{i+L} - mu_{i+1}) + (x_i - mu_i),
+// which is the mean-centred form of the dot-product update of Alg.
+// ComputeMatrixProfile (no cancellation at large offsets). mu_{i+1} comes from
+// the next lane; the last lane of a wavefront forms it itself.
+//
+// F32: also the FP32 copies of df, dg and the inverse norms for the FP32 pass
+// (nearest rounding: their error is part of the item bound; a flat or padded
+// window, whose inverse norm is zero, gets NaN so that every correlation it
+// enters fails every threshold test), and per block of 64 windows the extrema
+// of sigma sqrt(L), |df| and |dg| that bound the FP32 rounding, rounded outward.
+template <bool F32>
+__global__ __launch_bounds__(256) void k_window_prep(
+    const double* __restrict__ xs, int64_t N, int L, int first, double flat_eps, const double* __restrict__ A_in,
+    const double* __restrict__ B_in, double* __restrict__ A_out, double* __restrict__ B_out, double* __restrict__ mu,
+    double* __restrict__ sig, double* __restrict__ invn, uint8_t* __restrict__ flat,
+    unsigned long long* __restrict__ nflat, double* __restrict__ df, double* __restrict__ dg,
+    float* __restrict__ sw32, float* __restrict__ df32, float* __restrict__ dg32, float* __restrict__ inv32,
+    float* __restrict__ bsw_max, float* __restrict__ bsw_min, float* __restrict__ bdf_max,
+    float* __restrict__ bdg_max) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  // anchored sums of window w at this length
+  auto sums = [&](int64_t w, double& a, double& b) {
+    const double x0 = xs[w];
     if (first) {
       a = 0.0;
       b = 0.0;
       for (int k = 1; k < L; ++k) {
-        double d = xs[i + k] - x0;
+        const double d = xs[w + k] - x0;
         a += d;
         b = fma(d, d, b);
       }
     } else {
-      a = A[i];
-      b = B[i];
-      double d = xs[i + L - 1] - x0;
+      a = A_in[w];
+      b = B_in[w];
+      const double d = xs[w + L - 1] - x0;
       a += d;
       b = fma(d, d, b);
     }
-    A[i] = a;
-    B[i] = b;
+  };
+  const bool live = i < N;
+  bool fl = false;
+  double mval = 0.0, s = 0.0, inv = 0.0;
+  if (live) {
+    double a, b;
+    sums(i, a, b);
+    A_out[i] = a;
+    B_out[i] = b;
     const double m = a / (double)L;
     double v = b / (double)L - m * m;
     v = v > 0.0 ? v : 0.0;
-    const double s = sqrt(v);
-    const double mval = x0 + m;
+    s = sqrt(v);
+    mval = xs[i] + m;
     fl = s <= flat_eps * fmax(1.0, fabs(mval));
-    mu[i] = mval;
-    sig[i] = s;
-    flat[i] = fl ? 1 : 0;
-    invn[i] = fl ? 0.0 : 1.0 / (s * sqrt((double)L));
-  } else if (i < N + kPad) {
-    mu[i] = 0.0;
-    sig[i] = 0.0;
-    flat[i] = 1;
-    invn[i] = 0.0;
+    inv = fl ? 0.0 : 1.0 / (s * sqrt((double)L));
   }
-  unsigned long long m = __ballot(fl);
-  if ((threadIdx.x & (kWave - 1)) == 0 && m) atomicAdd(nflat, (unsigned long long)__popcll(m));
-}
-
-// --------------------------------------------------------------------------
-// Co-moment recurrence inputs at length L. With C(i,j) = sum_k (x_{i+k} - mu_i)
-// (x_{j+k} - mu_j), one diagonal step is
-//   C(i+1, j+1) = C(i, j) + df_i * dg_j + df_j * dg_i,
-//   df_i = (x_{i+L} - x_i) / 2,  dg_i = (x_{i+L} - mu_{i+1}) + (x_i - mu_i),
-// which is the mean-centred form of the dot-product update of Alg.
-// ComputeMatrixProfile (no cancellation at large offsets).
-template <typename T>
-__global__ void k_prep(const double* __restrict__ xs, const double* __restrict__ mu,
-                       const double* __restrict__ sig, const double* __restrict__ invn, int64_t N, int L,
-                       T* __restrict__ df, T* __restrict__ dg, float* __restrict__ sw32) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // the next window's mean (same arithmetic as its own lane)
+  double mnext = __shfl_down(mval, 1, kWave);
+  if (lane == kWave - 1 && i + 1 < N) {
+    double a, b;
+    sums(i + 1, a, b);
+    mnext = xs[i + 1] + a / (double)L;
+  }
+  const unsigned long long fm = __ballot(fl);
+  if (lane == 0 && fm) atomicAdd(nflat, (unsigned long long)__popcll(fm));
   if (i >= N + kPad) return;
+  mu[i] = live ? mval : 0.0;
+  sig[i] = live ? s : 0.0;
+  flat[i] = live ? (fl ? 1 : 0) : 1;
+  invn[i] = inv;
   double f = 0.0, g = 0.0;
-  float w = INFINITY;
   if (i + 1 < N) {
     f = 0.5 * (xs[i + L] - xs[i]);
-    g = (xs[i + L] - mu[i + 1]) + (xs[i] - mu[i]);
+    g = (xs[i + L] - mnext) + (xs[i] - mval);
   }
+  df[i] = f;
+  dg[i] = g;
   // sigma * sqrt(L), rounded down so that filter bounds built from it stay below the exact ones
-  if (i < N && invn[i] > 0.0) w = __double2float_rd(sig[i] * sqrt((double)L));
-  df[i] = (T)f;
-  dg[i] = (T)g;
-  sw32[i] = w;
+  sw32[i] = (live && inv > 0.0) ? __double2float_rd(s * sqrt((double)L)) : INFINITY;
+  if (F32) {
+    df32[i] = (float)f;
+    dg32[i] = (float)g;
+    inv32[i] = inv > 0.0 ? (float)inv : __int_as_float(0x7fc00000);
+    // blocks of 64 windows are whole wavefronts (blockDim is a multiple of 64)
+    const int64_t blk = i / kWave;
+    if (blk * kWave < N) {
+      double smax = 0.0, smin = INFINITY, fmx = 0.0, gmx = 0.0;
+      if (live) {
+        if (inv > 0.0) {
+          const double w = s * sqrt((double)L);
+          smax = w;
+          smin = w;
+        }
+        fmx = fabs(f);
+        gmx = fabs(g);
+      }
+      smax = wave_max_f64(smax);
+      smin = wave_min_f64(smin);
+      fmx = wave_max_f64(fmx);
+      gmx = wave_max_f64(gmx);
+      if (lane == 0) {
+        bsw_max[blk] = smax > 0.0 ? __double2float_ru(smax) : 0.0f;
+        bsw_min[blk] = smin < INFINITY ? __double2float_rd(smin) : INFINITY;
+        bdf_max[blk] = __double2float_ru(fmx);
+        bdg_max[blk] = __double2float_ru(gmx);
+      }
+    }
+  }
 }
 
 // Centred FP64 correlation of windows o and c (both non-flat) at length L.
@@ -163,12 +208,18 @@ __global__ void k_seed_mp(const double* __restrict__ xs, const double* __restric
 // distance wins, so the shorter length keeps ties).
 __global__ void k_finalize(const double* __restrict__ xs, const double* __restrict__ mu,
                            const double* __restrict__ sig, const uint64_t* __restrict__ best,
-                           int64_t N, int L, double* __restrict__ prof_dist,
+                           int64_t N, int64_t N0, int L, double* __restrict__ prof_dist,
                            int32_t* __restrict__ prof_idx, double* __restrict__ valmp_norm,
                            double* __restrict__ valmp_dist, int32_t* __restrict__ valmp_len,
                            int32_t* __restrict__ valmp_idx) {
   int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= N) return;
+  if (o >= N) {
+    if (o < N0) {  // the row's entries past N_L (no window of this length)
+      if (prof_dist) prof_dist[o] = INFINITY;
+      if (prof_idx) prof_idx[o] = -1;
+    }
+    return;
+  }
   const uint64_t key = best[o];
   double d = INFINITY;
   int32_t c32 = -1;
@@ -225,13 +276,6 @@ __global__ void k_fill_counters(unsigned long long* __restrict__ p, int n, unsig
   if ((int)threadIdx.x < n) p[threadIdx.x] = v;
 }
 
-__global__ void k_fill_tail(int64_t from, int64_t to, double* __restrict__ prof_dist,
-                            int32_t* __restrict__ prof_idx) {
-  int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= to) return;
-  if (prof_dist) prof_dist[i] = INFINITY;
-  if (prof_idx) prof_idx[i] = -1;
-}
 
 __global__ void k_valmp_init(int64_t N0, double* __restrict__ norm, double* __restrict__ dist,
                              int32_t* __restrict__ len, int32_t* __restrict__ idx) {
@@ -526,17 +570,16 @@ hipError_t launch_convert(const void* in, int dtype, int64_t n, int64_t npad, do
   return hipGetLastError();
 }
 
-hipError_t launch_stats(const double* xs, int64_t N, int L, int first, double flat_eps, double* A,
-                        double* B, double* mu, double* sig, double* invn, uint8_t* flat,
-                        unsigned long long* nflat, hipStream_t st) {
-  k_stats<<<blocks_for(N + kPad, 256), 256, 0, st>>>(xs, N, L, first, flat_eps, A, B, mu, sig, invn,
-                                                       flat, nflat);
-  return hipGetLastError();
-}
-
-hipError_t launch_prep_f64(const double* xs, const double* mu, const double* sig, const double* invn, int64_t N,
-                           int L, double* df, double* dg, float* sw32, hipStream_t st) {
-  k_prep<double><<<blocks_for(N + kPad, 256), 256, 0, st>>>(xs, mu, sig, invn, N, L, df, dg, sw32);
+hipError_t launch_window_prep(const WindowPrep& w, hipStream_t st) {
+  const unsigned blocks = blocks_for(w.N + kPad, 256);
+  if (w.df32)
+    k_window_prep<true><<<blocks, 256, 0, st>>>(w.xs, w.N, w.L, w.first, w.flat_eps, w.A_in, w.B_in, w.A_out, w.B_out,
+                                                w.mu, w.sig, w.invn, w.flat, w.nflat, w.df, w.dg, w.sw32, w.df32,
+                                                w.dg32, w.inv32, w.bsw_max, w.bsw_min, w.bdf_max, w.bdg_max);
+  else
+    k_window_prep<false><<<blocks, 256, 0, st>>>(w.xs, w.N, w.L, w.first, w.flat_eps, w.A_in, w.B_in, w.A_out,
+                                                 w.B_out, w.mu, w.sig, w.invn, w.flat, w.nflat, w.df, w.dg, w.sw32,
+                                                 nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -548,9 +591,10 @@ hipError_t launch_seed_mp(const double* xs, const double* mu, const double* invn
 }
 
 hipError_t launch_finalize(const double* xs, const double* mu, const double* sig, const uint64_t* best,
-                           int64_t N, int L, double* prof_dist, int32_t* prof_idx, double* valmp_norm,
+                           int64_t N, int64_t N0, int L, double* prof_dist, int32_t* prof_idx, double* valmp_norm,
                            double* valmp_dist, int32_t* valmp_len, int32_t* valmp_idx, hipStream_t st) {
-  k_finalize<<<blocks_for(N, 128), 128, 0, st>>>(xs, mu, sig, best, N, L, prof_dist, prof_idx, valmp_norm,
+  const int64_t n = N0 > N ? N0 : N;
+  k_finalize<<<blocks_for(n, 128), 128, 0, st>>>(xs, mu, sig, best, N, N0, L, prof_dist, prof_idx, valmp_norm,
                                                  valmp_dist, valmp_len, valmp_idx);
   return hipGetLastError();
 }
@@ -580,11 +624,6 @@ hipError_t launch_keys_to_idx(const uint64_t* best, int64_t N, int32_t* idx, hip
   return hipGetLastError();
 }
 
-hipError_t launch_fill_tail(int64_t from, int64_t to, double* prof_dist, int32_t* prof_idx, hipStream_t st) {
-  if (to <= from) return hipSuccess;
-  k_fill_tail<<<blocks_for(to - from, 256), 256, 0, st>>>(from, to, prof_dist, prof_idx);
-  return hipGetLastError();
-}
 
 hipError_t launch_valmp_init(int64_t N0, double* norm, double* dist, int32_t* len, int32_t* idx,
                              hipStream_t st) {

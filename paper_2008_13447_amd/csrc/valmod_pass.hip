@@ -467,7 +467,8 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
 __global__ void k_delta(const float* __restrict__ bsw_max, const float* __restrict__ bsw_min,
                         const float* __restrict__ bdf_max, const float* __restrict__ bdg_max, int64_t nblk,
                         int64_t segs, int64_t bands, int64_t H, int64_t dstart, int64_t BW, int64_t N,
-                        float* __restrict__ delta) {
+                        float delta_max, float* __restrict__ delta, int32_t* __restrict__ hard,
+                        unsigned long long* __restrict__ nhard) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= segs * bands) return;
   const int64_t seg = id / bands, band = id % bands;
@@ -502,78 +503,10 @@ __global__ void k_delta(const float* __restrict__ bsw_max, const float* __restri
   const double eps = 5.9604644775390625e-08;  // 2^-24
   // + 2^-22: the rounding of the FP32 difference threshold - delta (|.| < 4)
   const double d = 2.0 * eps * ((2.0 * R + 1.0) * phi + 4.0 * R * psi + 4.0) + 2.384185791015625e-07;
-  delta[id] = d < 1.0 ? (float)d * 1.0000002f : 1.0f;
-}
-
-// Per-block (64 windows) extrema feeding k_delta: one wavefront per block.
-__device__ __forceinline__ double wave_max_f64(double v) {
-#pragma unroll
-  for (int m = kWave / 2; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, kWave));
-  return v;
-}
-__device__ __forceinline__ double wave_min_f64(double v) {
-#pragma unroll
-  for (int m = kWave / 2; m >= 1; m >>= 1) v = fmin(v, __shfl_xor(v, m, kWave));
-  return v;
-}
-
-__global__ __launch_bounds__(256) void k_block_extrema(const double* __restrict__ sig, const double* __restrict__ invn,
-                                                       const double* __restrict__ df, const double* __restrict__ dg,
-                                                       int64_t N, int L, float* __restrict__ bsw_max,
-                                                       float* __restrict__ bsw_min, float* __restrict__ bdf_max,
-                                                       float* __restrict__ bdg_max, int64_t nblk) {
-  const int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (b >= nblk) return;  // uniform per wavefront
-  const int64_t i = b * kWave + threadIdx.x % kWave;
-  double smax = 0.0, smin = INFINITY, fmx = 0.0, gmx = 0.0;
-  if (i < N) {
-    if (invn[i] > 0.0) {
-      const double w = sig[i] * sqrt((double)L);
-      smax = w;
-      smin = w;
-    }
-    fmx = fabs(df[i]);
-    gmx = fabs(dg[i]);
-  }
-  smax = wave_max_f64(smax);
-  smin = wave_min_f64(smin);
-  fmx = wave_max_f64(fmx);
-  gmx = wave_max_f64(gmx);
-  if (threadIdx.x % kWave == 0) {
-    // rounded outward so that the item bound stays an upper bound
-    bsw_max[b] = smax > 0.0 ? __double2float_ru(smax) : 0.0f;
-    bsw_min[b] = smin < INFINITY ? __double2float_rd(smin) : INFINITY;
-    bdf_max[b] = __double2float_ru(fmx);
-    bdg_max[b] = __double2float_ru(gmx);
-  }
-}
-
-// FP32 copies of the recurrence inputs (nearest rounding; their error is part
-// of the item bound) and of the thresholds (rounded down).
-__global__ void k_to_f32(const double* __restrict__ df, const double* __restrict__ dg,
-                         const double* __restrict__ invn, int64_t n, float* __restrict__ df32,
-                         float* __restrict__ dg32, float* __restrict__ inv32) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  df32[i] = (float)df[i];
-  dg32[i] = (float)dg[i];
-  // a flat or padded window (zero inverse norm) gets NaN: every correlation
-  // it takes part in is NaN and fails every threshold test of the FP32 pass
-  inv32[i] = invn[i] > 0.0 ? (float)invn[i] : __int_as_float(0x7fc00000);
-}
-
-__global__ void k_thr_to_f32(const double* __restrict__ thr, int64_t n, float* __restrict__ thr32) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  thr32[i] = __double2float_rd(thr[i]);
-}
-
-// Items whose FP32 bound exceeds the limit, for the FP64 kernel.
-__global__ void k_hard_items(const float* __restrict__ delta, int64_t nitems, float delta_max,
-                             int32_t* __restrict__ items, unsigned long long* __restrict__ count) {
-  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= nitems) return;
-  if (delta[id] > delta_max) items[atomicAdd(count, 1ull)] = (int32_t)id;
+  const float df_ = d < 1.0 ? (float)d * 1.0000002f : 1.0f;
+  delta[id] = df_;
+  // items whose bound exceeds the limit are listed for the FP64 kernel
+  if (df_ > delta_max) hard[atomicAdd(nhard, 1ull)] = (int32_t)id;
 }
 
 PassGrid pass_grid(int64_t N, int64_t e, int64_t dstart, int K, int64_t H) {
@@ -658,17 +591,6 @@ hipError_t launch_pass(const PassLaunch& p, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_fp32_prep(const double* sig, const double* invn, const double* df, const double* dg, int64_t N,
-                            int L, float* df32, float* dg32, float* inv32, float* bsw_max, float* bsw_min,
-                            float* bdf_max, float* bdg_max, hipStream_t st) {
-  const int64_t n = N + kPad;
-  k_to_f32<<<blocks_for(n, 256), 256, 0, st>>>(df, dg, invn, n, df32, dg32, inv32);
-  const int64_t nblk = (N + 63) / 64;
-  k_block_extrema<<<blocks_for(nblk, 4), 256, 0, st>>>(sig, invn, df, dg, N, L, bsw_max, bsw_min, bdf_max, bdg_max,
-                                                       nblk);
-  return hipGetLastError();
-}
-
 hipError_t launch_fp32_items(const float* bsw_max, const float* bsw_min, const float* bdf_max, const float* bdg_max,
                              int64_t N, int64_t e, int64_t dstart, int K, int64_t H, float delta_max, float* delta,
                              int32_t* hard, unsigned long long* nhard, hipStream_t st) {
@@ -677,13 +599,7 @@ hipError_t launch_fp32_items(const float* bsw_max, const float* bsw_min, const f
   if (nitems == 0) return hipSuccess;
   const int64_t nblk = (N + 63) / 64;
   k_delta<<<blocks_for(nitems, 256), 256, 0, st>>>(bsw_max, bsw_min, bdf_max, bdg_max, nblk, g.segs, g.bands, H,
-                                                   dstart, (int64_t)kWave * K, N, delta);
-  k_hard_items<<<blocks_for(nitems, 256), 256, 0, st>>>(delta, nitems, delta_max, hard, nhard);
-  return hipGetLastError();
-}
-
-hipError_t launch_thr_to_f32(const double* thr, int64_t n, float* thr32, hipStream_t st) {
-  k_thr_to_f32<<<blocks_for(n, 256), 256, 0, st>>>(thr, n, thr32);
+                                                   dstart, (int64_t)kWave * K, N, delta_max, delta, hard, nhard);
   return hipGetLastError();
 }
 
