@@ -41,6 +41,26 @@ __device__ __forceinline__ double cross_sum(const double* __restrict__ xs, int L
   return s;
 }
 
+// the terms k in [kb, ke) of the anchored cross sum (a chunk of cross_sum)
+__device__ __forceinline__ double cross_sum_range(const double* __restrict__ xs, int64_t o, int64_t c, int kb,
+                                                  int ke) {
+  const double xo = xs[o], xc = xs[c];
+  double s = 0.0;
+  int k = kb;
+  for (; k + 8 <= ke; k += 8) {
+    double a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = xs[o + k + u];
+      b[u] = xs[c + k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s = fma(a[u] - xo, b[u] - xc, s);
+  }
+  for (; k < ke; ++k) s = fma(xs[o + k] - xo, xs[c + k] - xc, s);
+  return s;
+}
+
 __device__ __forceinline__ double rho_from_sum(double S, double Ao, double Ac, int L, double io, double ic) {
   return (S - Ao * Ac / (double)L) * io * ic;
 }
@@ -170,9 +190,10 @@ __global__ __launch_bounds__(kWave) void k_seed_append(const double* __restrict_
 // matrix-profile pass ran at this length), so an owner whose profile cannot be
 // built keeps it instead of going to the recompute list.
 //
-// k_merge_small takes a group of kSmallG lanes per owner and one candidate per
-// lane; owners with more candidates are listed for k_merge_big (one wavefront
-// per owner, candidates in LDS).
+// k_merge_small takes a group of kSmallG lanes per owner and up to kSmallG
+// candidates (the group's lanes split the terms of the candidates' sums when
+// there are fewer); owners with more candidates are listed for k_merge_big (one
+// wavefront per owner, candidates in LDS).
 constexpr int kMergeCap = 512;
 constexpr int kSmallG = 8;
 
@@ -199,12 +220,30 @@ __global__ __launch_bounds__(kWave) void k_merge_small(
     skip = flat[o] || thr[o] >= 2.0;  // not an owner, or already queued for recompute by the seeding
   }
   const bool ok = live && !skip && m <= kSmallG && l < m;
+  // the group's lanes share the candidates' sums: R = 8 / P lanes per candidate
+  // (P = m rounded up to a power of two), each summing a chunk of the terms
+  const int P = m <= 1 ? 1 : (m <= 2 ? 2 : (m <= 4 ? 4 : 8));
+  const int R = kSmallG / P;
+  double part = 0.0;
+  if (live && !skip && m >= 1 && m <= kSmallG) {
+    const int ci = l / R, r = l % R;
+    if (ci < m) {
+      const int kb = 1 + (int)((int64_t)(L - 1) * r / R), ke = 1 + (int)((int64_t)(L - 1) * (r + 1) / R);
+      part = cross_sum_range(xs, o, (int64_t)buf[o * cap + ci], kb, ke);
+    }
+  }
+#pragma unroll
+  for (int msk = kSmallG / 2; msk >= 1; msk >>= 1) {
+    const double v = __shfl_xor(part, msk, kWave);
+    if (msk < R) part += v;
+  }
+  const double Sg = __shfl(part, gb + (l * R < kSmallG ? l * R : 0), kWave);  // candidate l's sum
   int64_t c = -1;
   double rho = -2.0, S = 0.0;
   uint64_t key = kEmptyKey;
   if (ok) {
     c = buf[o * cap + l];
-    S = cross_sum(xs, L, o, c);
+    S = Sg;
     rho = rho_from_sum(S, A[o], A[c], L, invn[o], invn[c]);
     key = make_key(rho, c);
   }
@@ -438,6 +477,7 @@ __global__ __launch_bounds__(kWave) void k_recompute(const double* __restrict__ 
   }
 }
 
+
 // total of per-owner counts (one atomic per workgroup)
 __global__ __launch_bounds__(1024) void k_sum_counts(const uint32_t* __restrict__ v, int64_t n,
                                                      unsigned long long* __restrict__ out) {
@@ -602,7 +642,9 @@ hipError_t launch_merge(const double* xs, const double* A, const double* invn, c
   k_merge_small<<<blocks_for(N, kWave / kSmallG), kWave, 0, st>>>(xs, A, invn, sig, flat, thr, cnt, buf, cap, N, L, p,
                                                                    keep, margin, best_exact, hc, hS, hn, hbound, hsig,
                                                                    best, fail, nfail, big, nbig);
-  k_merge_big<<<(unsigned)(N < 65536 ? N : 65536), kWave, (size_t)cap * 3 * sizeof(double), st>>>(
+  // a wavefront per listed owner; 4,096 workgroups fill the chip (the list is
+  // walked in a grid-stride loop, so a short list costs little to dispatch)
+  k_merge_big<<<(unsigned)(N < 4096 ? N : 4096), kWave, (size_t)cap * 3 * sizeof(double), st>>>(
       xs, A, invn, sig, thr, cnt, buf, cap, L, p, keep, margin, hc, hS, hn, hbound, hsig, best, big, nbig);
   k_sum_counts<<<64, 1024, 0, st>>>(cnt, N, nappend);
   return hipGetLastError();
