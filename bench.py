@@ -24,15 +24,24 @@ FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed)
 FLOP_PER_CELL = 6         # 2 FMA co-moment update + 2 MUL normalisation
 
 
+def kernel_code(path):
+    """The source text without comments and blank lines: edits to comments do
+    not make the profiled counters stale."""
+    import re
+
+    lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in open(path).read().splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
 def profiled_traffic(precision):
     """HBM bytes per pass launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
-    scaled by a 1 GiB device-copy calibration) for the current kernel source; None
-    when the summary is missing or was taken on a different kernel source."""
+    scaled by a 1 GiB device-copy calibration) for the current kernel code; None
+    when the summary is missing or was taken on different kernel code."""
     import glob
     import hashlib
 
     src = os.path.join(ROOT, "paper_2008_13447_amd", "csrc", "valmod_pass.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = hashlib.sha256(kernel_code(src).encode()).hexdigest()[:16]
     for path in glob.glob(os.path.join(ROOT, "profiles", f"k_pass_{precision}_*.md")):
         fields = dict(line.split(": ", 1) for line in open(path) if ": " in line and not line.startswith(("-", "|")))
         if fields.get("kernel_source_sha256_16", "").strip() == sha and "traffic_bytes_per_launch" in fields:

@@ -55,14 +55,13 @@ __global__ void k_anchor_grow(const double* __restrict__ xs, int64_t n, int L, i
 // segment's first row. Every cell (i, j) is seen once and serves two owners by
 // symmetry: row owner i (candidate j) and column owner j (candidate i).
 //
-// The per-cell work is two FMAs and one compare. The compare is a filter in
-// co-moment space: for owner thresholds thr (in correlation units) the cell can
-// matter only if rho = C / (sw_i sw_j) >= min(thr_i, thr_j), with
-// sw = sigma * sqrt(L). Over a block of K rows the filter uses
-//   tau_j = min(thr_j, min_rows thr_i) * sw_j * min_rows sw_i   (times 1 - 1e-12),
-// which is never larger than the exact per-cell bound, so no qualifying cell is
-// skipped. Cells that pass go to a slow path that evaluates rho exactly and
-// applies the mode's action:
+// The per-cell work is the two-FMA update and a test against both owners'
+// thresholds (correlation units): the cell can matter only if
+// rho = C invn_i invn_j >= min(thr_i, thr_j), with invn = 1 / (sigma sqrt L).
+// The FP32 pass tests the sign of fma(C invn_j, invn_i, -min(thr_j, thr_i)) and
+// reduces it over the lane's K cells with a max; the FP64 pass compares per
+// cell. A step whose wavefront has a passing cell goes to a slow path that
+// evaluates rho and applies the mode's action:
 //   MODE_MP     : running best of each owner as a packed (distance, index) key
 //                 updated by 64-bit atomic min; thr = the running best's bound.
 //   MODE_APPEND : thr is a fixed per-owner threshold; every candidate with
@@ -134,8 +133,8 @@ __device__ __forceinline__ void load_run(const float* p, float* dst) {
 // loads, and a write inside a data-dependent branch makes every later wait
 // drain all prefetches); the queue is flushed to global memory when it could
 // overflow at the next step and at the end of the work item.
-// Queue capacity of a wavefront: one collecting step (two entries per cell) fits
-// an empty queue.
+// Queue capacity of a wavefront: 2 * 64 * K entries (a matrix-profile step adds
+// at most 64 K + 1, a collecting step at most 64).
 template <int K>
 struct PassQueue {
   static constexpr int size = 2 * kWave * K;
