@@ -609,3 +609,22 @@ def test_motif_sets_global_bucket_map(oracle_mod, monkeypatch):
     g = run_gpu(x, lo, hi, p=5, k_motifs=k, k_discords=1, mset_radius=D, mset_cap=cap)
     count = _check_motif_sets(oracle_mod, x, lo, hi, g, D, cap, k)
     _say(f"motif sets, global bucket map: counts {count.tolist()}")
+
+
+def test_motif_sets_flats_and_missing_pairs(oracle_mod):
+    """Motif sets next to constant stretches at a 1e4 offset (flat windows are
+    never members), and on a short series where the ranking finds fewer pairs
+    than asked for (the missing ranks get empty sets)."""
+    x = gen.small_random_walk(2500, 20) + 1.0e4
+    x[300:700] = x[300]
+    x[1500:1560] = x[1500]
+    x = x.astype(np.float32)
+    g = run_gpu(x, 24, 32, p=5, k_motifs=4, k_discords=1, precision="fp32", mset_radius=6.0, mset_cap=100)
+    count = _check_motif_sets(oracle_mod, x, 24, 32, g, 6.0, 100, 4)
+    mem = g["mset_off"][g["mset_off"] >= 0]
+    assert not np.any((mem >= 300) & (mem <= 700 - 24))
+    y = gen.small_random_walk(90, 21, np.float32)
+    g2 = run_gpu(y, 20, 21, p=5, k_motifs=8, k_discords=1, mset_radius=3.0, mset_cap=16)
+    c2 = _check_motif_sets(oracle_mod, y, 20, 21, g2, 3.0, 16, 8)
+    assert np.all(c2[g2["g_motif_abl"][:, 0] < 0] == 0)
+    _say(f"motif sets with flats {count.tolist()}, short series {c2.tolist()}")
