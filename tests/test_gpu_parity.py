@@ -549,7 +549,7 @@ def _check_motif_sets(oracle_mod, x, lo, hi, g, D, cap, k):
     np.testing.assert_array_equal(g["mset_count"], count)
     np.testing.assert_array_equal(g["mset_off"], off)
     for s in range(k):
-        L = int(r["g_motif_abl"][s, 2])
+        L = max(int(r["g_motif_abl"][s, 2]), 1)  # (-1 for a rank without a pair: empty set)
         m = min(int(count[s]), cap)
         np.testing.assert_allclose(g["mset_dist"][s, :m], dist[s, :m], rtol=0, atol=TOL64 * np.sqrt(L))
         assert np.all(np.isnan(g["mset_dist"][s, m:]))
