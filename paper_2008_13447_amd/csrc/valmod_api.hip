@@ -488,6 +488,7 @@ struct LaneRun {
   size_t si = 0;
   bool open = false;
   int L = 0, phase = 0, base = 0;
+  int anc_len = 0;  // length the anchor table holds (0: not formed for this series)
   bool heaps_on = false, probe_next = false;
   int64_t evi = 0;
 
@@ -593,6 +594,7 @@ LaneRun::Status LaneRun::advance() {
     base = 0;            // base length of the current partial profiles (0: none)
     probe_next = false;  // judge the partial profiles at the first length after a rebuild
     L = Ls.l_min;
+    anc_len = 0;
     phase = 0;
     open = true;
   }
@@ -644,7 +646,12 @@ LaneRun::Status LaneRun::advance() {
     LCHECK(launch_window_prep(wpr, st));
     std::swap(A, A2);
     std::swap(B, B2);
-    if (G.table) LCHECK(launch_anchor(xs, n, L, L == Ls.l_min, G.H, G.dstart, G.segs, G.stride, G.stride, anc, st));
+    // the anchor table at L: formed at the first length, else moved on by one
+    // term unless the last pass of the previous length did so
+    if (G.table && anc_len != L) {
+      LCHECK(launch_anchor(xs, n, L, L == Ls.l_min, G.H, G.dstart, G.segs, G.stride, G.stride, anc, st));
+      anc_len = L;
+    }
     if (sweep) {
       // Alg. ComputeSubMP: sweep the partial profiles, certify by the lower bound;
       // the choice between row recompute and a full pass needs the counts
@@ -713,6 +720,7 @@ LaneRun::Status LaneRun::advance() {
                              &cnt[CNT_HARD], st);
   };
   bool recompute = false;  // process the recompute list (its length is a device counter)
+  bool grow_collect = false;  // the collecting pass is the length's last and moves the anchor table on
   // collecting pass above per-owner thresholds from the candidates of `src`,
   // then the exact merge (top-`keep` partial profiles and best keys)
   auto collect = [&](const int32_t* src, int p_eff, int keep, int best_exact) -> hipError_t {
@@ -722,6 +730,7 @@ LaneRun::Status LaneRun::advance() {
                               fp32 ? thr32 : nullptr, acnt, fail, &cnt[CNT_NFAIL], st);
     PassLaunch q = pl;
     q.append = true;
+    q.grow = grow_collect;
     if (fp32) {
       if (e1 == hipSuccess) e1 = fp32_setup();
       q.fp32 = true;
@@ -736,6 +745,7 @@ LaneRun::Status LaneRun::advance() {
       h.items = hard;
       h.nitems = grid.segs * grid.bands;
       h.nitems_dev = &cnt[CNT_HARD];
+      h.grow = grow_collect;  // the items the FP32 pass left (disjoint anchors)
       if (e1 == hipSuccess) e1 = launch_pass(h, st);
       ++passes;
     } else if (e1 == hipSuccess) {
@@ -793,11 +803,17 @@ LaneRun::Status LaneRun::advance() {
   const int md = P->cfg.m_discords;
   if (full) {
     const int32_t* src = prev;
+    // the last pass of the length (the collecting pass if one runs) also moves
+    // the anchor table on to L + 1
+    const bool collects = rebuild || md > 1 || (fp32 && L > Ls.l_min);
+    const bool grow = G.table && anc_len == L && L < Ls.l_max;
+    grow_collect = grow && collects;
     if (L == Ls.l_min || (!fp32 && !rebuild && md == 1)) {
       // exact FP64 matrix-profile pass: running best keys seeded from the previous length
       LCHECK(launch_seed_mp(xs, mu, invn, flat, prev, N, L, e, best, thr, thr32, st));
       PassLaunch q = pl;
       q.append = false;
+      q.grow = grow && !collects;
       if (fp32) {
         LCHECK(launch_pass(q, st));
         ++passes;
@@ -821,6 +837,7 @@ LaneRun::Status LaneRun::advance() {
       // exact neighbours from an FP32 collecting pass seeded by the previous length
       LCHECK(collect(src, 1, 0, 0));
     }
+    if (grow) anc_len = L + 1;
   }
   if (paper_split) {
     LCHECK(launch_split_fail(fail, &cnt[CNT_NFAIL], N, lbm, &cnt[CNT_MINDIST], paper_split == 2 ? 1 : 0, rec,

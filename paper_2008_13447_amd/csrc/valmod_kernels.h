@@ -51,6 +51,7 @@ struct PassLaunch {
   int L;
   int K;  // diagonals per lane: 8 (FP64 also 4)
   bool append;
+  bool grow;  // the pass also moves the anchor table on to length L + 1 (its last read at L)
 };
 
 struct PassGrid {

@@ -206,13 +206,34 @@ __global__ void k_seed_mp(const double* __restrict__ xs, const double* __restric
 // form, exact near d = 0), in a canonical (min, max) order so d(i, j) = d(j, i)
 // bit for bit. Also applies Alg. updateVALMP (strictly smaller normalised
 // distance wins, so the shorter length keeps ties).
-__global__ void k_finalize(const double* __restrict__ xs, const double* __restrict__ mu,
-                           const double* __restrict__ sig, const uint64_t* __restrict__ best,
-                           int64_t N, int64_t N0, int L, double* __restrict__ prof_dist,
-                           int32_t* __restrict__ prof_idx, double* __restrict__ valmp_norm,
-                           double* __restrict__ valmp_dist, int32_t* __restrict__ valmp_len,
-                           int32_t* __restrict__ valmp_idx) {
-  int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int kFinG = 8;  // lanes per owner in k_finalize, each summing every kFinG-th term
+
+__global__ __launch_bounds__(128) void k_finalize(const double* __restrict__ xs, const double* __restrict__ mu,
+                                                  const double* __restrict__ sig, const uint64_t* __restrict__ best,
+                                                  int64_t N, int64_t N0, int L, double* __restrict__ prof_dist,
+                                                  int32_t* __restrict__ prof_idx, double* __restrict__ valmp_norm,
+                                                  double* __restrict__ valmp_dist, int32_t* __restrict__ valmp_len,
+                                                  int32_t* __restrict__ valmp_idx) {
+  const int r = threadIdx.x % kFinG;
+  const int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kFinG;
+  const uint64_t key = o < N ? best[o] : kEmptyKey;
+  // the group's lanes split the sum of squared differences (adjacent lanes,
+  // adjacent terms); every lane reaches the reduction
+  double acc = 0.0;
+  int64_t c = -1;
+  if (key != kEmptyKey) {
+    c = key_cand(key);
+    const int64_t a = o < c ? o : c, b = o < c ? c : o;
+    const double ma = mu[a], mb = mu[b];
+    const double ia = 1.0 / sig[a], ib = 1.0 / sig[b];
+    for (int k = r; k < L; k += kFinG) {
+      const double z = (xs[a + k] - ma) * ia - (xs[b + k] - mb) * ib;
+      acc = fma(z, z, acc);
+    }
+  }
+#pragma unroll
+  for (int m = kFinG / 2; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, kWave);
+  if (r != 0) return;
   if (o >= N) {
     if (o < N0) {  // the row's entries past N_L (no window of this length)
       if (prof_dist) prof_dist[o] = INFINITY;
@@ -220,22 +241,8 @@ __global__ void k_finalize(const double* __restrict__ xs, const double* __restri
     }
     return;
   }
-  const uint64_t key = best[o];
-  double d = INFINITY;
-  int32_t c32 = -1;
-  if (key != kEmptyKey) {
-    const int64_t c = key_cand(key);
-    const int64_t a = o < c ? o : c, b = o < c ? c : o;
-    const double ma = mu[a], mb = mu[b];
-    const double ia = 1.0 / sig[a], ib = 1.0 / sig[b];
-    double acc = 0.0;
-    for (int k = 0; k < L; ++k) {
-      const double z = (xs[a + k] - ma) * ia - (xs[b + k] - mb) * ib;
-      acc = fma(z, z, acc);
-    }
-    d = sqrt(acc);
-    c32 = (int32_t)c;
-  }
+  const double d = key != kEmptyKey ? sqrt(acc) : INFINITY;
+  const int32_t c32 = (int32_t)c;
   if (prof_dist) prof_dist[o] = d;
   if (prof_idx) prof_idx[o] = c32;
   if (valmp_norm) {
@@ -594,8 +601,8 @@ hipError_t launch_finalize(const double* xs, const double* mu, const double* sig
                            int64_t N, int64_t N0, int L, double* prof_dist, int32_t* prof_idx, double* valmp_norm,
                            double* valmp_dist, int32_t* valmp_len, int32_t* valmp_idx, hipStream_t st) {
   const int64_t n = N0 > N ? N0 : N;
-  k_finalize<<<blocks_for(n, 128), 128, 0, st>>>(xs, mu, sig, best, N, N0, L, prof_dist, prof_idx, valmp_norm,
-                                                 valmp_dist, valmp_len, valmp_idx);
+  k_finalize<<<blocks_for(n * kFinG, 128), 128, 0, st>>>(xs, mu, sig, best, N, N0, L, prof_dist, prof_idx,
+                                                         valmp_norm, valmp_dist, valmp_len, valmp_idx);
   return hipGetLastError();
 }
 

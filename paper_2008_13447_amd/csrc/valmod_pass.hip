@@ -18,7 +18,9 @@ static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n
 // are excursions from each window's first point (no large-offset
 // cancellation); the pass turns them into co-moments with C = S - A_i A_j / L.
 // k_anchor_init forms them directly (L FMAs each); when the length grows by one
-// k_anchor_grow adds the single new term, so later lengths cost O(1) per anchor.
+// the single new term is added, so later lengths cost O(1) per anchor: by the
+// last pass of a length as it reads the anchors, or by k_anchor_grow when a
+// length runs no pass.
 __global__ void k_anchor_init(const double* __restrict__ xs, int64_t n, int L, int64_t H, int64_t dstart,
                               int64_t stride, int64_t ncols, double* __restrict__ anc) {
   const int64_t seg = blockIdx.y;
@@ -58,9 +60,9 @@ __global__ void k_anchor_grow(const double* __restrict__ xs, int64_t n, int L, i
 // The per-cell work is the two-FMA update and a test against both owners'
 // thresholds (correlation units): the cell can matter only if
 // rho = C invn_i invn_j >= min(thr_i, thr_j), with invn = 1 / (sigma sqrt L).
-// The FP32 pass tests the sign of fma(C invn_j, invn_i, -min(thr_j, thr_i)) and
-// reduces it over the lane's K cells with a max; the FP64 pass compares per
-// cell. A step whose wavefront has a passing cell goes to a slow path that
+// The FP32 pass reduces fma(C invn_j, invn_i, -min(thr_j, thr_i)) over the
+// lane's K cells with a max and compares it with minus the rounding bound of
+// the work item; the FP64 pass compares per cell. A step whose wavefront has a passing cell goes to a slow path that
 // evaluates rho and applies the mode's action:
 //   MODE_MP     : running best of each owner as a packed (distance, index) key
 //                 updated by 64-bit atomic min; thr = the running best's bound.
@@ -85,6 +87,7 @@ struct PassArgs {
   const float* delta;          // FP32 recurrence: bound of |rho32 - rho| per work item (null: none)
   float delta_max;             // FP32 recurrence: items with a larger bound are left to the FP64 kernel
   int64_t anc_stride;  // anchor-table row length (diagonals per segment row)
+  double* anc_next;    // optional: the item's anchors are moved on to length L + 1 in place
   int64_t bands;       // bands of the grid (decodes item ids)
   int64_t N, e, H, dstart;
   int L;
@@ -152,24 +155,25 @@ __device__ __forceinline__ float vmin(float a, float b) {
   asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
   return r;
 }
-// max with the IEEE maxNum rule (a NaN operand yields the other operand)
-__device__ __forceinline__ double vmax(double a, double b) {
-  double r;
-  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
-__device__ __forceinline__ float vmax(float a, float b) {
-  float r;
-  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
 
-// Subtracts the FP32 rounding bound from loaded column thresholds (collecting
-// mode; the matrix-profile mode runs in FP64 with no bound).
-template <int n, typename T>
-__device__ __forceinline__ void widen(T* th, T delta) {
+// One more term of the anchor sums of an item (lane t: diagonals d0 + K t + q):
+// the table then holds length L + 1 for the diagonals with a window there
+// (j < N - 1). Every anchor belongs to one item and is read only by it, so
+// the entries are still those of length L. Kept out of line so that the
+// addresses it needs are not held in registers across the rows.
+template <int K>
+__device__ __attribute__((noinline)) void grow_anchors(const double* __restrict__ xs, double* __restrict__ row,
+                                                       int64_t i0, int64_t d0, int64_t N, int L) {
+  const int64_t dl = d0 + (int64_t)K * threadIdx.x;
+  double* an = row + dl;
+  double S[K], xj[K], xjl[K];
+  load_run<K>(an, S);
+  load_run<K>(xs + i0 + dl, xj);
+  load_run<K>(xs + i0 + dl + L, xjl);
+  const double xr = xs[i0 + L] - xs[i0];
 #pragma unroll
-  for (int u = 0; u < n; ++u) th[u] -= delta;
+  for (int q = 0; q < K; ++q)
+    if (i0 + dl + q < N - 1) an[q] = fma(xr, xjl[q] - xj[q], S[q]);
 }
 
 // LIST = false: one work item per workgroup over the whole grid. LIST = true:
@@ -256,10 +260,6 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
     load_run<K>(g_dg + c0 + K, Ydg);
     load_run<K>(g_invn + c0 + K, Yinv);
     load_run<K>(g_thr + c0 + K, Ythr);
-    if (MODE == MODE_APPEND) {
-      widen<K>(Xthr, delta);
-      widen<K>(Ythr, delta);
-    }
   }
   int qn = 0;  // queue fill (wave-uniform)
   unsigned long long ev_steps = 0;
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
       rdf[u] = g_df[ib + u];
       rdg[u] = g_dg[ib + u];
       rinv[u] = g_invn[ib + u];
-      rthr[u] = g_thr[ib + u] - delta;
+      rthr[u] = g_thr[ib + u];
     }
     const int64_t cn = ib + dl + 2 * K;  // first column entering during the next block
     // Every block runs all K steps: rows past the segment or the series only meet
@@ -334,8 +334,12 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
     for (int u = 0; u < K; ++u) {
       const int64_t i = ib + u;
       // correlation of every cell against both owners' thresholds. FP32: the
-      // sign of rho - min(thr_j, thr_i) with one rounding (fma), reduced by a
-      // max over the lane's cells (no per-cell mask traffic)
+      // difference rho - min(thr_j, thr_i) with one rounding (fma), reduced by a
+      // max over the lane's cells (no per-cell mask traffic) and compared with
+      // -delta: fl(x) >= -delta whenever x >= -delta, so the filter keeps every
+      // cell whose FP32 correlation reaches the threshold lowered by the bound.
+      // The thresholds are never NaN (NaN-propagating minimum is exact here);
+      // the max ignores the NaN of flat and padded windows.
       bool any_pass;
       if constexpr (sizeof(T) == 4) {
         T dq[K];
@@ -344,15 +348,16 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
           const int s = (q + u) % K;
           const T inv = s < u ? Qinv[s] : Pinv[s];
           const T th = s < u ? Qthr[s] : Pthr[s];
-          dq[q] = fma(C[q] * inv, rinv[u], -vmin(th, rthr[u]));
+          dq[q] = fma(C[q] * inv, rinv[u], -__builtin_elementwise_minimum(th, rthr[u]));
         }
 #pragma unroll
         for (int w = 1; w < K; w *= 2)  // pairwise, to keep the dependency chain short
 #pragma unroll
-          for (int q = 0; q + w < K; q += 2 * w) dq[q] = vmax(dq[q], dq[q + w]);
-        any_pass = __builtin_expect(__any(dq[0] >= (T)0), 0);
+          for (int q = 0; q + w < K; q += 2 * w) dq[q] = __builtin_fmaxf(dq[q], dq[q + w]);
+        any_pass = __builtin_expect(__any(dq[0] >= -delta), 0);
       } else {
-        // FP64: per-cell comparisons (this form allocates registers better there)
+        // FP64: per-cell comparisons (this form allocates registers better
+        // there); the FP64 recurrence carries no rounding bound (delta = 0)
         bool pass = false;
 #pragma unroll
         for (int q = 0; q < K; ++q) {
@@ -401,13 +406,13 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
           const int s = (q + u) % K;
           const int64_t j = i + dl + q;
           const T inv = s < u ? Qinv[s] : Pinv[s];
-          const T th = s < u ? Qthr[s] : Pthr[s];
+          const T th = (s < u ? Qthr[s] : Pthr[s]) - delta;  // lowered by the rounding bound
           const T rho = (C[q] * inv) * rinv[u];
           // FP32: flat and padded windows have a NaN inverse norm, so rho is NaN
           // and fails both tests; FP64: zero inverse norms are tested
           const bool ok = sizeof(T) == 4 || (j < N && rinv[u] > (T)0 && inv > (T)0);
-          mask |= (ok && rho >= th) ? (1u << q) : 0u;  // th already lowered by the bound
-          mask |= (ok && rho >= rthr[u]) ? (1u << (K + q)) : 0u;
+          mask |= (ok && rho >= th) ? (1u << q) : 0u;
+          mask |= (ok && rho >= rthr[u] - delta) ? (1u << (K + q)) : 0u;
         }
         if (qn + kWave > kQueue) flush();
         push(mask != 0, (int32_t)i, (uint64_t)((uint32_t)t | (mask << 6)));
@@ -428,13 +433,11 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
         load_run<HK>(g_dg + cn, Pdg);
         load_run<HK>(g_invn + cn, Pinv);
         load_run<HK>(g_thr + cn, Pthr);
-        if (MODE == MODE_APPEND) widen<HK>(Pthr, delta);
       } else if (u == K - 1) {
         load_run<HK>(g_df + cn + HK, Pdf + HK);
         load_run<HK>(g_dg + cn + HK, Pdg + HK);
         load_run<HK>(g_invn + cn + HK, Pinv + HK);
         load_run<HK>(g_thr + cn + HK, Pthr + HK);
-        if (MODE == MODE_APPEND) widen<HK>(Pthr + HK, delta);
       }
     }
   };
@@ -445,6 +448,8 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
   }
   if (qn > 0) flush();
   if (a.events && t == 0 && ev_steps) atomicAdd(&a.events[0], ev_steps);
+  // after the rows, so that no store precedes the loop's loads
+  if (a.anc_next) grow_anchors<K>(g_xs, a.anc_next + seg * a.anc_stride - a.dstart, i0, d0, N, a.L);
   }
   next:
   if (!LIST) return;
@@ -530,7 +535,7 @@ hipError_t launch_anchor(const double* xs, int64_t n, int L, bool init, int64_t 
   return hipGetLastError();
 }
 
-constexpr int64_t kListGrid = 1024;  // workgroups of a listed-items launch
+constexpr int64_t kListGrid = 256;  // workgroups of a listed-items launch
 
 template <typename T, int K>
 static hipError_t launch_pass_k(const PassLaunch& p, hipStream_t st) {
@@ -552,6 +557,7 @@ static hipError_t launch_pass_k(const PassLaunch& p, hipStream_t st) {
   a.H = p.H;
   a.dstart = p.dstart;
   a.anc_stride = p.anc_stride;
+  a.anc_next = p.anc && p.grow ? const_cast<double*>(p.anc) : nullptr;
   a.bands = g.bands;
   a.L = p.L;
   if (p.items && (p.nitems <= 0 || !p.nitems_dev)) return p.nitems < 0 ? hipErrorInvalidValue : hipSuccess;
