@@ -535,7 +535,7 @@ hipError_t launch_anchor(const double* xs, int64_t n, int L, bool init, int64_t 
   return hipGetLastError();
 }
 
-constexpr int64_t kListGrid = 256;  // workgroups of a listed-items launch
+constexpr int64_t kListGrid = 1024;  // workgroups of a listed-items launch
 
 template <typename T, int K>
 static hipError_t launch_pass_k(const PassLaunch& p, hipStream_t st) {
