@@ -300,9 +300,10 @@ VALMOD_API const char* valmod_status_str(int status);
 /* Milliseconds spent in the diagonal-pass kernel of the plan's precision during
  * the last valmod_run (full-grid launches only: FP64 mode, every pass; FP32
  * mode, the FP32 collecting passes, not the FP64 pass of the first length nor
- * the FP64 re-runs of listed work items), measured with HIP events on the
- * lanes' streams, and the number of those launches and of the cells they
- * covered. In graph mode: the time of the whole replay, as one launch. */
+ * the FP64 re-runs of listed work items), measured with HIP events that each
+ * launch records itself at kernel start and end on its lane's stream, and the
+ * number of those launches and of the cells they covered. In graph mode: the
+ * time of the whole replay, as one launch. */
 VALMOD_API valmod_status valmod_last_pass_timing(valmod_plan_t plan, double* ms, int64_t* launches,
                                       int64_t* cells);
 

@@ -698,13 +698,17 @@ LaneRun::Status LaneRun::advance() {
   pl.buf = abuf;
   pl.cap = P->cap;
   int64_t passes = 0;
-  // full-grid launch of the plan's own pass kernel: bracketed by events
+  // full-grid launch of the plan's own pass kernel, timed by events that the
+  // launch records itself (kernel start and end)
   auto timed_pass = [&](const PassLaunch& q) -> hipError_t {
     const bool tm = !capture && evi + 2 <= (int64_t)ln->ev.size();
-    hipError_t e1 = tm ? hipEventRecord(ln->ev[evi], st) : hipSuccess;
-    if (e1 == hipSuccess) e1 = launch_pass(q, st);
-    if (e1 == hipSuccess && tm) e1 = hipEventRecord(ln->ev[evi + 1], st);
-    if (tm) evi += 2;
+    PassLaunch qt = q;
+    if (tm) {
+      qt.ev_start = ln->ev[evi];
+      qt.ev_stop = ln->ev[evi + 1];
+      evi += 2;
+    }
+    const hipError_t e1 = launch_pass(qt, st);
     P->pass_launches += 1;
     P->pass_cells += grid.cells;
     ++passes;

@@ -52,6 +52,9 @@ struct PassLaunch {
   int K;  // diagonals per lane: 8 (FP64 also 4)
   bool append;
   bool grow;  // the pass also moves the anchor table on to length L + 1 (its last read at L)
+  // optional: events recorded by the full-grid launch itself (start and end of
+  // the kernel), so timing it adds no marker between it and its neighbours
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
 };
 
 struct PassGrid {

@@ -3,6 +3,7 @@
 #include "valmod_common.h"
 #include "valmod_kernels.h"
 
+#include <hip/hip_ext.h>
 #include <math.h>
 #include <type_traits>
 
@@ -540,7 +541,11 @@ constexpr int64_t kListGrid = 1024;  // workgroups of a listed-items launch
 template <typename T, int K>
 static hipError_t launch_pass_k(const PassLaunch& p, hipStream_t st) {
   const PassGrid g = pass_grid(p.N, p.e, p.dstart, K, p.H);
-  if (g.bands == 0) return hipSuccess;
+  if (g.bands == 0) {  // nothing to launch: the timing events still mark an (empty) interval
+    hipError_t e = p.ev_start ? hipEventRecord(p.ev_start, st) : hipSuccess;
+    if (e == hipSuccess && p.ev_stop) e = hipEventRecord(p.ev_stop, st);
+    return e;
+  }
   PassArgs a;
   a.thr = p.thr;
   a.events = p.events;
@@ -578,10 +583,18 @@ static hipError_t launch_pass_k(const PassLaunch& p, hipStream_t st) {
     }
   }
   const dim3 grid((unsigned)g.segs, (unsigned)g.bands);
-  if (p.append)
+  if (p.ev_start || p.ev_stop) {
+    if (p.append)
+      hipExtLaunchKernelGGL(k_pass<T, K, MODE_APPEND, false>, grid, dim3(kWave), 0, st, p.ev_start, p.ev_stop, 0, df,
+                            dg, inv, thr, p.xs, p.anc, p.A, a);
+    else
+      hipExtLaunchKernelGGL(k_pass<T, K, MODE_MP, false>, grid, dim3(kWave), 0, st, p.ev_start, p.ev_stop, 0, df, dg,
+                            inv, thr, p.xs, p.anc, p.A, a);
+  } else if (p.append) {
     k_pass<T, K, MODE_APPEND, false><<<grid, kWave, 0, st>>>(df, dg, inv, thr, p.xs, p.anc, p.A, a);
-  else
+  } else {
     k_pass<T, K, MODE_MP, false><<<grid, kWave, 0, st>>>(df, dg, inv, thr, p.xs, p.anc, p.A, a);
+  }
   return hipGetLastError();
 }
 
