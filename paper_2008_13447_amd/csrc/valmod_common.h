@@ -77,31 +77,46 @@ __host__ __device__ __forceinline__ int64_t excl_zone(int64_t L, int64_t den) {
   return (L + den - 1) / den;
 }
 
-// Anchored cross sums formed directly: S[q] = sum_{k<L} (x_{i0+k} - x_{i0}) (x_{j+k} - x_j)
-// for the K consecutive windows j = i0 + dl + q (dl may be negative). The lane's K consecutive windows share a
-// register window of K values that slides by one element per k.
+// Anchored cross sums formed directly: S[q] = sum_{k<L} (x_{i0+k} - x_{i0}) (x_{c0+q+k} - x_{c0+q})
+// for the K consecutive windows c0 + q. The lane's K windows share a register
+// window of K values that slides by one element per k; every load is issued one
+// block of K steps before its use (the window's entering values and the row
+// values of the next block), so the steps do not wait on memory. Reads reach
+// x_{c0 + L + 3K} and x_{i0 + L + 2K} (inside the series padding).
 template <int K>
-__device__ __forceinline__ void direct_anchors(const double* __restrict__ xs, int64_t i0, int64_t dl, int L,
-                                               double* S) {
+__device__ __forceinline__ void direct_sums_ahead(const double* __restrict__ xs, int64_t i0, int64_t c0, int L,
+                                                  double* S) {
   const double xi = xs[i0];
-  const double* xc = xs + i0 + dl;
-  double base[K], w[K];
+  const double* xc = xs + c0;
+  const double* xr = xs + i0;
+  double base[K], w[K], nx[K], r[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) {
     base[q] = xc[q];
     w[q] = base[q];
+    nx[q] = xc[K + q];  // enters slot q during the first block
+    r[q] = xr[q];
     S[q] = 0.0;
   }
-  // at step k, slot (q + k) mod K holds x_{j0 + q + k}
   for (int kb = 0; kb < L; kb += K) {
+    double nn[K], rn[K];
 #pragma unroll
     for (int u = 0; u < K; ++u) {
-      const int k = kb + u;
-      if (k >= L) break;
-      const double r = xs[i0 + k] - xi;
+      nn[u] = xc[2 * K + kb + u];  // enters during the next block
+      rn[u] = xr[K + kb + u];
+    }
 #pragma unroll
-      for (int q = 0; q < K; ++q) S[q] = fma(r, w[(q + u) % K] - base[q], S[q]);
-      w[u] = xc[K + k];  // the slot of x_{j0 + k} takes x_{j0 + K + k}
+    for (int u = 0; u < K; ++u) {
+      if (kb + u >= L) break;
+      const double rv = r[u] - xi;
+#pragma unroll
+      for (int q = 0; q < K; ++q) S[q] = fma(rv, w[(q + u) % K] - base[q], S[q]);
+      w[u] = nx[u];  // the slot of x_{c0 + kb + u} takes x_{c0 + K + kb + u}
+    }
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      nx[u] = nn[u];
+      r[u] = rn[u];
     }
   }
 }

@@ -448,48 +448,6 @@ __global__ void k_mark_partial(const int32_t* __restrict__ part, const unsigned 
 // that the listing kernel has set to empty.
 constexpr int kRecK = 8;
 
-// Anchored cross sums S[q] = sum_{k<L} (x_{i0+k} - x_{i0}) (x_{c0+q+k} - x_{c0+q}),
-// q < K, with one sliding register window as in direct_anchors, but every load
-// is issued one block of K steps before its use (the window's entering values
-// and the row values of the next block), so the steps do not wait on memory.
-// Reads reach x_{c0 + L + 3K} and x_{i0 + L + 2K} (inside the series padding).
-template <int K>
-__device__ __forceinline__ void direct_sums_ahead(const double* __restrict__ xs, int64_t i0, int64_t c0, int L,
-                                                  double* S) {
-  const double xi = xs[i0];
-  const double* xc = xs + c0;
-  const double* xr = xs + i0;
-  double base[K], w[K], nx[K], r[K];
-#pragma unroll
-  for (int q = 0; q < K; ++q) {
-    base[q] = xc[q];
-    w[q] = base[q];
-    nx[q] = xc[K + q];  // enters slot q during the first block
-    r[q] = xr[q];
-    S[q] = 0.0;
-  }
-  for (int kb = 0; kb < L; kb += K) {
-    double nn[K], rn[K];
-#pragma unroll
-    for (int u = 0; u < K; ++u) {
-      nn[u] = xc[2 * K + kb + u];  // enters during the next block
-      rn[u] = xr[K + kb + u];
-    }
-#pragma unroll
-    for (int u = 0; u < K; ++u) {
-      if (kb + u >= L) break;
-      const double rv = r[u] - xi;
-#pragma unroll
-      for (int q = 0; q < K; ++q) S[q] = fma(rv, w[(q + u) % K] - base[q], S[q]);
-      w[u] = nx[u];  // the slot of x_{c0 + kb + u} takes x_{c0 + K + kb + u}
-    }
-#pragma unroll
-    for (int u = 0; u < K; ++u) {
-      nx[u] = nn[u];
-      r[u] = rn[u];
-    }
-  }
-}
 
 __global__ __launch_bounds__(kWave) void k_recompute(const double* __restrict__ xs, const double* __restrict__ A,
                                                      const double* __restrict__ invn,

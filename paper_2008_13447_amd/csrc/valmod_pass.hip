@@ -234,7 +234,7 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
     if (g_anc)
       load_run<K>(g_anc + seg * a.anc_stride + (dl - a.dstart), S);
     else
-      direct_anchors<K>(g_xs, i0, dl, a.L, S);
+      direct_sums_ahead<K>(g_xs, i0, i0 + dl, a.L, S);
     load_run<K>(g_A + i0 + dl, Aj);
     const double Ai = g_A[i0] / (double)a.L;
 #pragma unroll
