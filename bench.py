@@ -33,10 +33,10 @@ def kernel_code(path):
     return "\n".join(ln for ln in lines if ln)
 
 
-def profiled_traffic(precision):
+def profiled_traffic(precision, workload):
     """HBM bytes per pass launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
-    scaled by a 1 GiB device-copy calibration) for the current kernel code; None
-    when the summary is missing or was taken on different kernel code."""
+    scaled by a 1 GiB device-copy calibration) for the current kernel code on this
+    workload; None when no summary was taken on this workload and kernel code."""
     import glob
     import hashlib
 
@@ -44,7 +44,8 @@ def profiled_traffic(precision):
     sha = hashlib.sha256(kernel_code(src).encode()).hexdigest()[:16]
     for path in glob.glob(os.path.join(ROOT, "profiles", f"k_pass_{precision}_*.md")):
         fields = dict(line.split(": ", 1) for line in open(path) if ": " in line and not line.startswith(("-", "|")))
-        if fields.get("kernel_source_sha256_16", "").strip() == sha and "traffic_bytes_per_launch" in fields:
+        if (fields.get("kernel_source_sha256_16", "").strip() == sha and fields.get("workload", "").strip() == workload
+                and "traffic_bytes_per_launch" in fields):
             return float(fields["traffic_bytes_per_launch"])
     return None
 
@@ -193,7 +194,7 @@ def main():
                    "mode": args.mode, "mset_radius": args.mset},
         "roofline": {"bound": "alu", "kernel": f"k_pass<{'double' if args.precision == 'fp64' else 'float'}> "
                      "(diagonal pass)", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": profiled_traffic(args.precision),
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": profiled_traffic(args.precision, name),
                      "avg_launch_ms": avg_ms, "launches_per_step": launches,
                      "cells_per_launch": pass_cells / max(launches, 1)},
     }
