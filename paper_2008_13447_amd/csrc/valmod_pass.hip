@@ -536,7 +536,9 @@ hipError_t launch_anchor(const double* xs, int64_t n, int L, bool init, int64_t 
   return hipGetLastError();
 }
 
-constexpr int64_t kListGrid = 1024;  // workgroups of a listed-items launch
+// workgroups of a listed-items launch: two wavefronts per SIMD of the 256 CUs,
+// as many as the FP64 collecting kernel keeps resident (229 VGPRs)
+constexpr int64_t kListGrid = 2048;
 
 template <typename T, int K>
 static hipError_t launch_pass_k(const PassLaunch& p, hipStream_t st) {
