@@ -54,9 +54,21 @@ def cells_total(n, lo, hi):
     return sum((n - L + 1) * (n - L) // 2 for L in range(lo, hi + 1))
 
 
-def cpu_baseline(x, L, excl_den, gpu_prof_d, gpu_prof_i, target_s, seed=0):
-    """The oracle on a bounded sample of owners at one length, timed on the
-    host cores; the same owners are compared with the GPU result."""
+def cpu_model():
+    """Model name of the host CPU (first entry of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(x, l_min, lengths, excl_den, gpu_prof_d, gpu_prof_i, rows_per_len, seed=0):
+    """The oracle on a bounded sample: `rows_per_len` random owners (full distance
+    profiles) at each of the given lengths, timed on the host cores; the same
+    owners are compared with the GPU result."""
     import numpy as np
 
     import oracle
@@ -64,34 +76,37 @@ def cpu_baseline(x, L, excl_den, gpu_prof_d, gpu_prof_i, target_s, seed=0):
 
     oracle.build(force=False)
     n = x.shape[0]
-    N = n - L + 1
     threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count() or 1
-    rows = compare.sample_rows(N, N, seed)  # a random permutation
-    probe = rows[:4 * threads]
-    oracle.profile(x, L, rows=probe[:threads], excl_den=excl_den, nthreads=threads)  # warm
-    t0 = time.perf_counter()
-    oracle.profile(x, L, rows=probe, excl_den=excl_den, nthreads=threads)
-    dt = max(time.perf_counter() - t0, 1e-6)
-    m = int(min(N, max(len(probe), len(probe) * target_s / dt)))
-    sel = np.sort(rows[:m])
-    t0 = time.perf_counter()
-    d, i = oracle.profile(x, L, rows=sel, excl_den=excl_den, nthreads=threads)
-    dt = time.perf_counter() - t0
-    rep = compare.check_profile_rows(x, L, sel, gpu_prof_d[sel], gpu_prof_i[sel].astype(np.int64), d, i,
-                                     1e-9, excl_den)
-    cells = m * (N - 1) / 2.0  # each owner row is half of its pairs' share of the N(N-1)/2 cells
-    return dict(value=cells / dt, unit="cells/s", cores=threads, kind="oracle",
-                sample=f"{m} random owners at L={L} (full distance profiles, {m}/{N} of one length), "
-                       f"{dt:.1f} s", parity_rows=m, parity_max_dn_err=rep.get("max_dn_err", 0.0),
-                parity_idx_ties=rep.get("idx_mismatch", 0))
+    oracle.profile(x, lengths[0], rows=np.arange(threads), excl_den=excl_den, nthreads=threads)  # warm
+    cells = 0.0
+    dt = 0.0
+    worst = 0.0
+    ties = 0
+    for L in lengths:
+        t = L - l_min
+        N = n - L + 1
+        sel = np.sort(compare.sample_rows(N, rows_per_len, seed + L))
+        t0 = time.perf_counter()
+        d, i = oracle.profile(x, L, rows=sel, excl_den=excl_den, nthreads=threads)
+        dt += time.perf_counter() - t0
+        rep = compare.check_profile_rows(x, L, sel, gpu_prof_d[t][sel], gpu_prof_i[t][sel].astype(np.int64), d, i,
+                                         1e-9, excl_den)
+        worst = max(worst, rep.get("max_dn_err", 0.0))
+        ties += rep.get("idx_mismatch", 0)
+        cells += len(sel) * (N - 1) / 2.0  # an owner row is half of its pairs' share of the N(N-1)/2 cells
+    dt = max(dt, 1e-6)
+    return dict(value=cells / dt, unit="cells/s", cores=threads, kind="oracle", cpu=cpu_model(),
+                sample=f"{rows_per_len} random owners (full distance profiles) at each of L={list(lengths)}, "
+                       f"{dt:.1f} s on {threads} threads",
+                parity_rows=rows_per_len * len(lengths), parity_max_dn_err=worst, parity_idx_ties=ties)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4, 5],
                     help="workload; 4 is the batched one (--batch-count series in one plan)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--lanes", type=int, default=0, help="series run concurrently (0: library default)")
@@ -103,12 +118,15 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"],
                     help="headline path (the other one is timed beside it unless --no-compare)")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--compare-steps", type=int, default=1,
+                    help="timed steps of the other precision (after its autotuning, no warm-up)")
     ap.add_argument("--k-motifs", type=int, default=0, help="top-k motif pairs (0: the workload's)")
     ap.add_argument("--mset", type=float, default=0.0, metavar="D",
                     help="also grow the motif sets of the global top-k pairs with radius factor D")
     ap.add_argument("--mset-cap", type=int, default=1024, help="members stored per motif set")
     ap.add_argument("--path", default="auto", choices=["auto", "full", "recompute"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-rows", type=int, default=512,
+                    help="oracle owners per length (at l_min, the middle length and l_max)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
@@ -151,7 +169,7 @@ def main():
 
     km = args.k_motifs or w.k_motifs
 
-    def timed(precision):
+    def timed(precision, steps, warmup):
         graph = args.graph and precision == "fp64"
         v = native.Valmod(x, lo, hi, p=w.p, k_motifs=km, k_discords=w.k_discords,
                           excl_den=w.excl_den, precision=precision, path="full" if graph else args.path,
@@ -163,22 +181,22 @@ def main():
             H, K = v.autotune()
             tune = {"segment_rows": H, "diagonals_per_lane": K, "ms": (time.perf_counter() - t0) * 1e3}
             print(f"bench: {precision} autotune {tune}", file=sys.stderr, flush=True)
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             v.run()
             print(f"bench: {precision} warm-up step done", file=sys.stderr, flush=True)
         torch.cuda.synchronize(dev)
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             v.run()
         torch.cuda.synchronize(dev)
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ms = (time.perf_counter() - t0) * 1e3 / steps
         print(f"bench: {precision} {ms:.1f} ms per step", file=sys.stderr, flush=True)
         timing = v.pass_timing()
         res = v.result(0)
         v.close()
         return ms, timing, res, tune
 
-    ms, (pass_ms, launches, pass_cells), res, tune = timed(args.precision)
+    ms, (pass_ms, launches, pass_cells), res, tune = timed(args.precision, args.steps, args.warmup)
     avg_ms = pass_ms / max(launches, 1)
     achieved = (pass_cells / max(launches, 1)) * FLOP_PER_CELL / (avg_ms * 1e-3) / 1e12
     peak = FP64_PEAK_TFLOPS if args.precision == "fp64" else FP32_PEAK_TFLOPS
@@ -207,21 +225,20 @@ def main():
     if not args.no_compare:
         # the other precision on the same input: throughput and output agreement (first series)
         other = "fp64" if args.precision == "fp32" else "fp32"
-        ms2, _, res2, _ = timed(other)
+        ms2, _, res2, _ = timed(other, args.compare_steps, 0)
         L = np.arange(w.l_min, w.l_max + 1)[:, None]
         a, b = res["prof_dist"] / np.sqrt(L), res2["prof_dist"] / np.sqrt(L)
         fin = np.isfinite(a) & np.isfinite(b)
         out[f"{other}_path"] = {
-            "value": cells / (ms2 * 1e-3), "ms_per_step": ms2,
+            "value": cells / (ms2 * 1e-3), "ms_per_step": ms2, "steps": args.compare_steps, "warmup": 0,
             "speedup_of_headline": ms2 / ms,
             "max_abs_dn_diff": float(np.max(np.abs(a[fin] - b[fin]))) if fin.any() else 0.0,
             "idx_diff": int(np.sum(res["prof_idx"] != res2["prof_idx"])),
         }
     if not args.no_cpu and batch is None:
-        Lc = (w.l_min + w.l_max) // 2  # a length the per-length update computes, not the first one
-        t = Lc - w.l_min
-        out["cpu_baseline"] = cpu_baseline(w.x, Lc, w.excl_den, res["prof_dist"][t], res["prof_idx"][t],
-                                           args.cpu_seconds)
+        lengths = sorted({w.l_min, (w.l_min + w.l_max) // 2, w.l_max})
+        out["cpu_baseline"] = cpu_baseline(w.x, w.l_min, lengths, w.excl_den, res["prof_dist"], res["prof_idx"],
+                                           args.cpu_rows)
     print(json.dumps(out), flush=True)
 
 

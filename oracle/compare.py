@@ -96,11 +96,18 @@ def check_valmp(x, l_min, gpu, ref, tol, excl_den=4, rep=None) -> Report:
 
 
 def check_rankings(x, l_min, gpu, ref, tol, excl_den=4, rep=None) -> Report:
+    """Rankings per length and across lengths. Every index that differs from the
+    oracle's must be a tie under the oracle's own distances: the reported pair
+    (or offset and neighbour) is legal and its oracle distance is within `tol`
+    (normalised) of the oracle's value at that rank."""
     rep = rep if rep is not None else Report()
+    x = np.asarray(x, dtype=np.float64)
     nl = ref["motif_d"].shape[0]
+    n = x.shape[0]
     for t in range(nl):
         L = l_min + t
         sq = np.sqrt(L)
+        e = _excl(L, excl_den)
         for key_d, key_i, kind in (("motif_d", "motif_ab", "motif"), ("discord_d", "discord_on", "discord")):
             dg, dr = gpu[key_d][t], ref[key_d][t]
             assert np.array_equal(np.isnan(dg), np.isnan(dr)), f"{kind} L={L}: filled slots differ"
@@ -112,13 +119,19 @@ def check_rankings(x, l_min, gpu, ref, tol, excl_den=4, rep=None) -> Report:
             ig, ir = gpu[key_i][t], ref[key_i][t]
             for r in np.nonzero(ok)[0]:
                 if kind == "motif" and not np.array_equal(ig[r], ir[r]):
-                    d = pair_dists(x, L, [ig[r]])[0]
+                    a, b = int(ig[r][0]), int(ig[r][1])
+                    assert 0 <= a < b < n - L + 1 and b - a > e, f"motif L={L} rank {r}: illegal pair {ig[r]}"
+                    d = pair_dists(x, L, [[a, b]])[0]
                     assert abs(d - dr[r]) / sq <= tol, f"motif L={L} rank {r}: {ig[r]} vs {ir[r]}"
                     rep["rank_tie_swaps"] = rep.get("rank_tie_swaps", 0) + 1
-                if kind == "discord" and ig[r][0] != ir[r][0]:
-                    # the reported offset's own profile value must tie the oracle's
-                    assert abs(gpu["prof_dist"][t, ig[r][0]] - dr[r]) / sq <= tol, \
-                        f"discord L={L} rank {r}: {ig[r]} vs {ir[r]}"
+                if kind == "discord" and not np.array_equal(ig[r], ir[r]):
+                    o, nn = int(ig[r][0]), int(ig[r][1])
+                    assert abs(o - nn) > e, f"discord L={L} rank {r}: trivial neighbour {ig[r]}"
+                    # the offset's exact profile value and the neighbour's distance both tie
+                    d_o = ref["prof_dist"][t, o]
+                    assert abs(d_o - dr[r]) / sq <= tol, f"discord L={L} rank {r}: {ig[r]} vs {ir[r]}"
+                    d_nn = pair_dists(x, L, [[o, nn]])[0]
+                    assert abs(d_nn - d_o) / sq <= tol, f"discord L={L} rank {r}: neighbour {nn} is not nearest"
                     rep["rank_tie_swaps"] = rep.get("rank_tie_swaps", 0) + 1
     for key_d, key_i, kind in (("g_motif_d", "g_motif_abl", "g_motif"), ("g_discord_d", "g_discord_onl", "g_discord")):
         dg, dr = gpu[key_d], ref[key_d]
@@ -128,8 +141,24 @@ def check_rankings(x, l_min, gpu, ref, tol, excl_den=4, rep=None) -> Report:
             err = np.abs(dg[ok, 1] - dr[ok, 1])
             rep.merge_max(f"{kind}_dn_err", err.max())
             assert err.max() <= tol, f"{kind}: normalised distances differ by {err.max():.3e}"
-            if not np.array_equal(gpu[key_i][ok], ref[key_i][ok]):
-                rep["rank_tie_swaps"] = rep.get("rank_tie_swaps", 0) + 1
+        ig, ir = gpu[key_i], ref[key_i]
+        for r in np.nonzero(ok)[0]:
+            if np.array_equal(ig[r], ir[r]):
+                continue
+            u, v, L = (int(w) for w in ig[r])
+            assert l_min <= L < l_min + nl, f"{kind} rank {r}: length {L} outside the range"
+            sq = np.sqrt(L)
+            e = _excl(L, excl_den)
+            if kind == "g_motif":
+                assert 0 <= u < v < n - L + 1 and v - u > e, f"{kind} rank {r}: illegal pair {ig[r]}"
+                dn = pair_dists(x, L, [[u, v]])[0] / sq
+            else:
+                assert abs(u - v) > e, f"{kind} rank {r}: trivial neighbour {ig[r]}"
+                dn = ref["prof_dist"][L - l_min, u] / sq
+                d_nn = pair_dists(x, L, [[u, v]])[0] / sq
+                assert abs(d_nn - dn) <= tol, f"{kind} rank {r}: neighbour {v} is not nearest"
+            assert abs(dn - dr[r, 1]) <= tol, f"{kind} rank {r}: {ig[r]} vs {ir[r]} is not a tie ({dn} vs {dr[r, 1]})"
+            rep["rank_tie_swaps"] = rep.get("rank_tie_swaps", 0) + 1
     return rep
 
 
