@@ -22,7 +22,10 @@
  *   - trivial match iff |i - j| <= ceil(L / excl_den) (exclusion zone; the text
  *     says l/2, the workloads use l/4);
  *   - a window is flat iff sigma <= flat_eps * max(1, |mu|); flat windows are
- *     neither owners nor candidates (distance +inf, index -1);
+ *     neither owners nor candidates (distance +inf, index -1); the flat rule is
+ *     a reporting convention, so the lower bound of a window that is flat at the
+ *     base length still uses its real correlation there (0 only when it is
+ *     exactly constant);
  *   - ties in a distance profile go to the smallest candidate index;
  *   - the VALMP update compares length-normalised distances, strictly;
  *   - top-k motifs per length: pairs (i, IP[i]) sorted by (d, min, max), accepted
@@ -234,7 +237,10 @@ ORACLE_EXPORT double oracle_lb(const double* x, int64_t n, int64_t o, int64_t c,
   } else if (fl[o]) {
     out = 0.0;
   } else {
-    double q = fl[c] ? 0.0 : pearson(x, b, o, c, mu, sg);
+    /* Eq. lowerBoundFinalFormula holds for any candidate shape: a window that
+     * the flat rule excludes still has a correlation unless it is exactly
+     * constant (then the minimising constant vector gives rho+ = 0) */
+    double q = sg[c] > 0.0 ? pearson(x, b, o, c, mu, sg) : 0.0;
     double qp = q > 0.0 ? q : 0.0;
     double base = 1.0 - qp * qp;
     if (base < 0.0) base = 0.0;
@@ -739,7 +745,10 @@ ORACLE_EXPORT int oracle_motif_sets(const double* x, int64_t n, int64_t k, const
  * with the largest correlation at b (ties to the smaller index; equivalently the
  * p smallest lower bounds). The bound for every candidate not stored uses the
  * largest correlation among them (the (p+1)-th overall, clamped at 0; no such
- * candidate: +inf bound). Valid iff the smallest exact distance at L among the
+ * candidate: +inf bound). Windows flat at b are not stored; each one that is a
+ * candidate at L (non-flat, non-trivial) contributes its own bound, from its
+ * real correlation at b (0 only for an exactly constant window), and the bound
+ * of the owner is the smallest of these. Valid iff the smallest exact distance at L among the
  * stored candidates that are still eligible at L is strictly below that bound.
  * valid_out[o] is 1/0 for owners o < N_L that are non-flat at L, 2 otherwise.
  */
@@ -778,11 +787,21 @@ ORACLE_EXPORT int64_t oracle_valid_fraction(const double* x, int64_t n, int64_t 
       valid_out[o] = 0;
       continue;
     }
-    int64_t m = 0, nflatc = 0;
+    int64_t m = 0;
+    double flat_lb = INFINITY;
     for (int64_t c = 0; c < Nb; c++) {
       if (iabs64(c - o) <= eb) continue;
       if (flb[c]) {
-        nflatc++;
+        /* never stored; its own bound (with its real base correlation) joins the
+         * bound of the candidates not stored when it is a candidate at L */
+        if (c < NL && !flL[c] && iabs64(c - o) > eL) {
+          double q = sgb[c] > 0.0 ? pearson(x, b, o, c, mub, sgb) : 0.0;
+          if (q < 0.0) q = 0.0;
+          double base = 1.0 - q * q;
+          if (base < 0.0) base = 0.0;
+          double lbc = sqrt((double)b * base) * sgb[o] / sgL[o];
+          if (lbc < flat_lb) flat_lb = lbc;
+        }
         continue;
       }
       list[m].r = pearson(x, b, o, c, mub, sgb);
@@ -791,14 +810,14 @@ ORACLE_EXPORT int64_t oracle_valid_fraction(const double* x, int64_t n, int64_t 
     }
     qsort(list, m, sizeof(rc_t), cmp_rc);
     int64_t stored = m < p ? m : p;
-    double bound = INFINITY;
-    if (m > p || nflatc > 0) {
-      /* a flat candidate at b is never stored and counts with correlation 0 */
-      double q = m > p ? list[p].r : 0.0;
+    double bound = flat_lb;
+    if (m > p) {
+      double q = list[p].r;
       if (q < 0.0) q = 0.0;
       double base = 1.0 - q * q;
       if (base < 0.0) base = 0.0;
-      bound = sqrt((double)b * base) * sgb[o] / sgL[o];
+      double lbn = sqrt((double)b * base) * sgb[o] / sgL[o];
+      if (lbn < bound) bound = lbn;
     }
     double md = INFINITY;
     for (int64_t s = 0; s < stored; s++) {

@@ -210,4 +210,22 @@ def small_sine_with_discord(n: int, seed: int, period: int, length: int,
     return x, c
 
 
+def flat_at_base_copy(n: int, seed: int, b: int, L: int, flat_eps: float = 2.0 ** -20,
+                      near_noise: float = 0.1) -> Tuple[np.ndarray, int, int, int]:
+    """Random walk with one owner window o of length L, a scaled copy of it at c
+    whose deviation over the first b points lies just under the flat threshold
+    (|mean| < 1) while its last L - b points make it non-flat, and a noisy copy
+    of o at m (a close candidate that is not flat). Returns (x, o, c, m)."""
+    g = _rng(SEED_BASE + 400 + seed)
+    x = np.cumsum(g.standard_normal(n))
+    w = g.standard_normal(L)
+    w[:b] = (w[:b] - w[:b].mean()) / w[:b].std()
+    w[b:] = 3.0 * np.where(g.standard_normal(L - b) >= 0.0, 1.0, -1.0)
+    o, m, c = n // 5, 2 * n // 5, 3 * n // 5
+    x[o:o + L] = x[o] + w
+    x[m:m + L] = x[m] + w + g.normal(0.0, near_noise, L)
+    x[c:c + L] = 0.9 * flat_eps * w
+    return x, o, c, m
+
+
 WORKLOADS = {1: config1, 2: config2, 3: config3, 5: config5}

@@ -432,3 +432,51 @@ def test_motif_sets_special_radii(oracle_mod):
     assert np.all(np.diff(s) > e)  # pairwise non-trivial
     gaps = np.abs(np.arange(N)[:, None] - s[None, :]).min(axis=1)
     assert np.all(gaps <= e)  # maximal: every window is a trivial match of some member
+
+
+def test_lb_of_candidate_flat_at_base(oracle_mod):
+    """Eq. lowerBoundFinalFormula for a candidate that the flat rule excludes at
+    the base length but not at L: the bound uses its real base correlation and
+    stays below the true distance, while the correlation-0 convention of an
+    exactly constant window would exceed it (the fixture is a scaled copy of
+    the owner whose deviation at b lies just under the flat threshold)."""
+    b, Lmax = 24, 30
+    x, o, c, m = gen.flat_at_base_copy(600, 0, b, Lmax)
+    _, sgb, flb = oracle_mod.stats(x, b)
+    assert flb[c] and not flb[o]
+    for L in range(b + 1, Lmax + 1):
+        _, sgL, flL = oracle_mod.stats(x, L)
+        assert not flL[c]
+        d = oracle_mod.pair_dist(x, L, o, c)
+        dp, ip = oracle_mod.profile(x, L, rows=[o])
+        assert ip[0] == c and dp[0] == d and d < 1e-9
+        assert oracle_mod.lb(x, o, c, b, L) <= d + 1e-12
+        assert np.sqrt(b) * sgb[o] / sgL[o] > 1.0  # what correlation 0 would claim
+
+
+def test_valid_heaps_exact_with_candidates_flat_at_base(oracle_mod):
+    """Soundness of the heap test with windows that are flat at b and candidates
+    at L: every valid owner's heap minimum is its true profile value (heaps hold
+    the p best non-flat candidates at b, found here with numpy)."""
+    b = 24
+    x, o, c, m = gen.flat_at_base_copy(600, 0, b, 30)
+    _, sgb, flb = oracle_mod.stats(x, b)
+    W = _windows(x, b)
+    Z = (W - W.mean(1, keepdims=True)) / W.std(1, keepdims=True)
+    R = Z @ Z.T / b
+    eb = -(-b // 4)
+    for L in (25, 28, 30):
+        dL, _ = oracle_mod.profile(x, L)
+        _, _, DL = _brute_mp(x, L)
+        _, _, flL = oracle_mod.stats(x, L)
+        DL[:, flL] = np.inf
+        for p in (1, 5):
+            v, nv = oracle_mod.valid_fraction(x, b, L, p)
+            assert v[o] == 0  # the copy flat at b is not covered by any certified bound
+            for w in np.nonzero(v == 1)[0]:
+                r = R[w].copy()
+                r[np.abs(np.arange(r.shape[0]) - w) <= eb] = -np.inf
+                r[flb] = -np.inf
+                order = np.lexsort((np.arange(r.shape[0]), -r))[:p]
+                order = order[order < DL.shape[0]]
+                assert np.isclose(DL[w, order].min(), dL[w], rtol=1e-9, atol=1e-12), (L, p, w)
