@@ -187,7 +187,8 @@ def main():
         torch.cuda.synchronize(dev)
         t0 = time.perf_counter()
         for _ in range(steps):
-            v.run()
+            v.run(sync=False)  # enqueued back to back; the status read below waits for the last one
+        v.status()
         torch.cuda.synchronize(dev)
         ms = (time.perf_counter() - t0) * 1e3 / steps
         print(f"bench: {precision} {ms:.1f} ms per step", file=sys.stderr, flush=True)

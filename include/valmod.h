@@ -32,11 +32,12 @@
  * workspace, outputs); the plan owns host metadata and, from its first
  * valmod_run, per-lane HIP streams and events, a few bytes of pinned host
  * memory per lane and (graph mode) the instantiated graph, all released by
- * valmod_plan_free. No function of this library allocates device memory. Return values are valmod_status codes; no
- * exception crosses the ABI. Argument errors are reported synchronously by
- * valmod_plan / valmod_run; errors found on the device (non-finite input,
- * internal capacity exceeded and not recoverable) are reported by valmod_run
- * as VALMOD_E_DEVICE.
+ * valmod_plan_free. No function of this library allocates device memory.
+ * Return values are valmod_status codes; no exception crosses the ABI.
+ * Argument errors are reported synchronously by valmod_plan / valmod_run;
+ * errors found on the device (non-finite input) are written to a device status
+ * word that valmod_run_status reads after the run has completed
+ * (VALMOD_E_DEVICE).
  *
  * Threading: a plan may be used by one host thread and one stream at a time.
  */
@@ -61,7 +62,7 @@ typedef enum {
   VALMOD_E_NOMEM = -3,     /* host allocation failed */
   VALMOD_E_HIP = -4,       /* a HIP runtime call failed */
   VALMOD_E_LAYOUT = -5,    /* sizes exceed the supported index range */
-  VALMOD_E_DEVICE = -6     /* error reported by a kernel (see valmod_last_device_error) */
+  VALMOD_E_DEVICE = -6     /* error reported by a kernel (returned by valmod_run_status) */
 } valmod_status;
 
 typedef enum { VALMOD_F32 = 0, VALMOD_F64 = 1 } valmod_dtype;
@@ -71,8 +72,9 @@ typedef enum { VALMOD_F32 = 0, VALMOD_F64 = 1 } valmod_dtype;
  * return the same exact results: the FP32 recurrence only selects candidates,
  * with a threshold widened by a rigorous bound of its rounding error per work
  * item; work items whose bound exceeds a limit run in FP64, and every selected
- * candidate is re-evaluated in FP64. The first length of each series is an FP64
- * matrix-profile pass in both modes. */
+ * candidate is re-evaluated in FP64. The FP64 recurrence selects the same way,
+ * with its own bound. The first length of each series starts with an FP64
+ * matrix-profile pass whose neighbours seed its collecting pass. */
 typedef enum {
   VALMOD_PREC_FP64 = 0,        /* recurrence in FP64 */
   VALMOD_PREC_FP32_REFRESH = 1 /* recurrence in FP32, restarted from FP64 dot products every R rows */
@@ -109,8 +111,10 @@ typedef struct {
   double flat_eps;          /* flat-window threshold; 0 = default 2^-20 */
   int32_t dtype;            /* valmod_dtype of the input series */
   int32_t precision;        /* valmod_precision */
-  int32_t refresh_R;        /* FP32 refresh interval R in rows: 0 = default 512, else a multiple
-                               of 16 in [64, 8192]; the rounding bound grows linearly with R */
+  int32_t refresh_R;        /* FP32 refresh interval R in rows: 0 = default (256, doubled up to 1024
+                               while the anchor table exceeds its memory budget; valmod_autotune may
+                               pick 256, 512 or 1024), else a multiple of 16 in [64, 8192]; the
+                               rounding bound grows linearly with R */
   int32_t path;             /* valmod_path */
   int32_t device;           /* HIP device ordinal the plan runs on */
   int32_t lanes;            /* series processed concurrently (streams), 0 = default min(num_series, 4),
@@ -146,8 +150,12 @@ enum {
 };
 
 /*
- * Output buffers (device pointers, caller-allocated; a NULL pointer skips that
- * output). For series s with N0 = n_s - l_min_s + 1 and nlen = l_max_s - l_min_s + 1,
+ * Output buffers (device pointers, caller-allocated). A NULL pointer skips that
+ * output (nothing is written there; what the run needs of it internally lives in
+ * the workspace), except that the m-th discord outputs are required when
+ * m_discords > 1 and the motif-set outputs when mset_radius > 0. Skipping
+ * prof_dist / prof_idx saves n0 * nlen * 12 bytes per series.
+ * For series s with N0 = n_s - l_min_s + 1 and nlen = l_max_s - l_min_s + 1,
  * element offsets come from valmod_series_layout; inside one series:
  *   prof_dist[t * N0 + i]  f64  MP_L[i] for L = l_min + t (+inf if none; +inf for i >= N_L)
  *   prof_idx [t * N0 + i]  i32  IP_L[i] (-1 if none; paper mode: -2 if not computed, and then
@@ -233,7 +241,10 @@ typedef struct {
   int64_t mset;
 } valmod_layout;
 
-/* Validate a configuration and build a plan (host only; touches no GPU). The
+/* Validate a configuration and build a plan (host only; touches no GPU): the
+ * inputs of Problem "Variable-Length Motif Pair Discovery" (series, l_min,
+ * l_max, k) and of Problem "Variable-Length Top-k m-th Discord Discovery" (k, m),
+ * plus the partial-profile size p of Alg. ComputeMatrixProfile. The
  * series are assigned to `lanes` by longest processing time first on the sum
  * over lengths of N_L^2; each lane runs its series one after another.
  * Errors: VALMOD_E_ARG (null pointers, num_series < 1, l_min < 4, l_max < l_min,
@@ -246,33 +257,59 @@ typedef struct {
  * VALMOD_E_LAYOUT (more than VALMOD_MAX_WINDOWS windows), VALMOD_E_NOMEM. */
 VALMOD_API valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* out);
 
-/* Device workspace the caller must pass to valmod_run (bytes, 256-aligned base). */
+/* Device workspace the caller must pass to valmod_run (bytes, 256-aligned base):
+ * statistics, recurrence inputs, anchor table, partial profiles (Alg.
+ * ComputeMatrixProfile, Alg. ComputeSubMP) and the last profile rows of each
+ * lane. 0 for a NULL plan. */
 VALMOD_API size_t valmod_workspace_bytes(valmod_plan_t plan);
 
-/* Output element counts; VALMOD_E_ARG if plan or out is NULL. */
+/* Output element counts of the whole batch (the outputs of Problems "Variable-Length
+ * Motif Pair Discovery" and "Variable-Length Top-k m-th Discord Discovery");
+ * VALMOD_E_ARG if plan or out is NULL. */
 VALMOD_API valmod_status valmod_output_sizes(valmod_plan_t plan, valmod_sizes* out);
 
-/* Offsets of series s (0 <= s < num_series); VALMOD_E_ARG otherwise. */
+/* Element offsets of series s (0 <= s < num_series) inside the concatenated input
+ * and every output; VALMOD_E_ARG otherwise. */
 VALMOD_API valmod_status valmod_series_layout(valmod_plan_t plan, int32_t s, valmod_layout* out);
 
 /*
- * Run the plan. d_series: device array of the concatenated series in the
- * configured dtype (series s starts at element valmod_layout.series).
- * d_workspace: device buffer of valmod_workspace_bytes(plan) bytes, 256-byte
- * aligned, contents irrelevant on entry. d_out: struct (host memory) of device
- * pointers. stream: a hipStream_t (passed as void*; NULL = default stream).
- * The lanes' streams start after the work already on `stream` and `stream`
- * waits for all of them; the call synchronises with `stream` before returning
- * (per-length decisions of the partial-profile path read device counters), so
- * all outputs are complete on return. In graph mode the first call captures
- * the run (lanes included) into a HIP graph and launches it; later calls with
- * the same d_series, d_workspace, output pointers and stream replay it. One plan
- * must not be used by two calls at the same time. Errors: VALMOD_E_ARG (null
- * plan/series/workspace/out), VALMOD_E_HIP, VALMOD_E_DEVICE (non-finite input
- * values). The motif sets need the mset outputs (VALMOD_E_ARG without them).
+ * Run the plan (Alg. VALMOD over every series: the matrix profile at l_min by
+ * Alg. ComputeMatrixProfile, the longer lengths by Alg. ComputeSubMP, VALMP by
+ * Alg. updateVALMP, the rankings of Sec. "Comparing Motifs of Different Lengths"
+ * and Alg. UpdateVariableLengthDiscords). d_series: device array of the
+ * concatenated series in the configured dtype (series s starts at element
+ * valmod_layout.series). d_workspace: device buffer of valmod_workspace_bytes(plan)
+ * bytes, 256-byte aligned, contents irrelevant on entry. d_out: struct (host
+ * memory) of device pointers; NULL members skip their output. stream: a
+ * hipStream_t (passed as void*; NULL = default stream).
+ * The call enqueues the run on `stream` and returns without waiting for it to
+ * finish: the lanes' streams start after the work already on `stream`, and
+ * `stream` waits for all of them. Plans with partial profiles (path AUTO or
+ * RECOMPUTE, or paper mode) wait inside the call at lengths whose next step
+ * depends on device counters (the number of windows whose bound test failed);
+ * full-path and graph plans never wait. The outputs are complete, and the run's
+ * device status is known, once valmod_run_status has returned. In graph mode the
+ * first call captures the run (lanes included) into a HIP graph and launches it;
+ * later calls with the same d_series, d_workspace, output pointers and stream
+ * replay it. One plan must not be used by two calls at the same time, and a
+ * second run of a plan may be enqueued before the first one's status is read
+ * (valmod_run_status then reports the last one). Errors (synchronous):
+ * VALMOD_E_ARG (null plan/series/workspace/out, unaligned workspace, missing
+ * m-th discord or motif-set outputs), VALMOD_E_HIP (a launch or runtime call
+ * failed).
  */
 VALMOD_API valmod_status valmod_run(valmod_plan_t plan, const void* d_series, void* d_workspace,
                          const valmod_outputs* d_out, void* stream);
+
+/*
+ * Wait for the last run enqueued by valmod_run on this plan (synchronising
+ * `stream` first when it is not NULL) and return its status: VALMOD_OK,
+ * VALMOD_E_DEVICE (the input held non-finite values; the device status word of a
+ * lane was set) or VALMOD_E_HIP. Also makes valmod_last_pass_timing reflect that
+ * run. Without a pending run it returns the status of the last one read
+ * (VALMOD_OK before any). VALMOD_E_ARG for a NULL plan.
+ */
+VALMOD_API valmod_status valmod_run_status(valmod_plan_t plan, void* stream);
 
 /*
  * Autotuner: choose the diagonal-pass geometry empirically, on the series with
@@ -282,8 +319,8 @@ VALMOD_API valmod_status valmod_run(valmod_plan_t plan, const void* d_series, vo
  * second run is timed and the fastest candidate whose workspace fits in
  * valmod_workspace_bytes (as it was before the call) is kept. The plan's
  * workspace requirement can only shrink. Results do not depend on the choice
- * (exact mode). Arguments are those of valmod_run (same buffers); the outputs of
- * the tuned series are overwritten and are complete only after a valmod_run.
+ * (exact mode). Arguments are those of valmod_run (same buffers; d_out may be
+ * NULL: the tuning runs write no output). The call waits for its runs.
  * chosen (optional, host int32[2]): segment height and diagonals per lane of the
  * tuned series; zeros when there was nothing to tune (fixed refresh_R or
  * VALMOD_PASS_H set). Errors: those of valmod_run.
@@ -291,10 +328,12 @@ VALMOD_API valmod_status valmod_run(valmod_plan_t plan, const void* d_series, vo
 VALMOD_API valmod_status valmod_autotune(valmod_plan_t plan, const void* d_series, void* d_workspace,
                                          const valmod_outputs* d_out, void* stream, int32_t* chosen);
 
-/* Release a plan (NULL is ignored). */
+/* Release a plan and the streams, events, pinned words and graph it holds
+ * (NULL is ignored). The plan's last run must have completed. */
 VALMOD_API void valmod_plan_free(valmod_plan_t plan);
 
-/* Human-readable name of a status code (static string). */
+/* Human-readable name of a status code (static string; "unknown status" for
+ * codes outside valmod_status). */
 VALMOD_API const char* valmod_status_str(int status);
 
 /* Milliseconds spent in the diagonal-pass kernel of the plan's precision during
@@ -302,10 +341,28 @@ VALMOD_API const char* valmod_status_str(int status);
  * mode, the FP32 collecting passes, not the FP64 pass of the first length nor
  * the FP64 re-runs of listed work items), measured with HIP events that each
  * launch records itself at kernel start and end on its lane's stream, and the
- * number of those launches and of the cells they covered. In graph mode: the
- * time of the whole replay, as one launch. */
+ * number of those launches and of the cells they covered, as of the last
+ * valmod_run_status. In graph mode: the time of the whole replay, as one launch.
+ * Measurement hook of the diagonal pass of Alg. ComputeMatrixProfile. */
 VALMOD_API valmod_status valmod_last_pass_timing(valmod_plan_t plan, double* ms, int64_t* launches,
                                       int64_t* cells);
+
+/*
+ * Rounding bound used by the diagonal pass for one work item, in correlation
+ * units: the largest |rho computed - rho| of the recurrence (the dot-product
+ * update of Alg. ComputeMatrixProfile in co-moment form) over an item of H rows
+ * at length L, in FP32 (precision VALMOD_PREC_FP32_REFRESH; includes the
+ * rounding of the FP32 filter's own difference) or FP64 (VALMOD_PREC_FP64),
+ * with phi = (max sw / min sw)_rows (max sw / min sw)_cols and psi =
+ * (max|df|_rows max|dg|_cols + max|dg|_rows max|df|_cols) / (min sw_rows min sw_cols)
+ * and xi = (max|df|_rows + max|df|_cols) max|mu| / (min sw_rows min sw_cols)
+ * over the item's windows (sw = sigma sqrt(L); df, dg the recurrence inputs
+ * df_i = (x_{i+L} - x_i) / 2, dg_i = (x_{i+L} - mu_{i+1}) + (x_i - mu_i)).
+ * Host function (no device work); NaN for H < 1, L < 1, negative phi, psi or
+ * xi, or an unknown precision.
+ */
+VALMOD_API double valmod_rounding_bound(int32_t precision, int64_t H, int32_t L, double phi, double psi,
+                                        double xi);
 
 #ifdef __cplusplus
 }

@@ -18,14 +18,22 @@ using namespace valmod;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int64_t kRingRows = 32;
+constexpr int kErrSlot = 7;  // slot of a lane's pinned host words that receives its device error flag  // profile rows kept in the workspace (rankings run per group of rows)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
   size_t xs, A, B, A2, B2, mu, sig, invn, flat, df, dg, sw32, thr, thr32, best, counters, anc;
-  size_t hc, hS, hn, hbound, hsig, acnt, abuf, fail, big, lbm, rec, part, mvals, mnn, mkeys;
-  size_t df32, dg32, inv32, bsw_max, bsw_min, bdf_max, bdg_max, delta, hard;
+  size_t hc, hS, hn, hbound, hsig, hflat, acnt, abuf, fail, big, lbm, rec, part, mvals, mnn, mkeys;
+  size_t df32, dg32, inv32, bsw_max, bsw_min, bdf_max, bdg_max, bmu_max, delta64, delta, hard;
   size_t ms_keys0, ms_keys1, ms_vals0, ms_vals1, ms_hist, ms_meta, ms_count, ms_taken, ms_bucket;
+  // the last ring_rows profile rows (distance, index; stride N0 of the series):
+  // seeds of the next length and input of the per-length rankings
+  size_t ring_d, ring_i;
+  int64_t ring_rows;
+  // stand-ins for outputs the caller skips but the run reads back
+  size_t sub_vn, sub_vd, sub_vl, sub_vi, sub_mab, sub_md, sub_don, sub_dd, sub_gab, sub_gd, sub_gdon, sub_gdd;
   size_t total;
 };
 
@@ -89,7 +97,7 @@ struct Lane {
   std::vector<int> series;  // assigned series, in run order
   size_t base = 0;          // byte offset of the lane's workspace
   WsLayout ws;              // offsets relative to base
-  int64_t nmax = 0, n0max = 0, ancmax = 0, itemmax = 0, total_lengths = 0;
+  int64_t nmax = 0, n0max = 0, ancmax = 0, itemmax = 0, total_lengths = 0, nlenmax = 0;
   double cost = 0.0;
   // device resources (created on the plan's device at the first run)
   hipStream_t st = nullptr;
@@ -118,6 +126,9 @@ struct valmod_plan_s {
   hipStream_t key_stream = nullptr;
   valmod_outputs key_out;
   int64_t graph_cells = 0;
+  hipEvent_t finished = nullptr;  // end of the last enqueued run (after its error-flag copies)
+  bool run_pending = false;       // a run was enqueued and valmod_run_status has not read it yet
+  valmod_status last_status = VALMOD_OK;
   // autotuned geometry: FP64 segment-height multiplier, FP32 refresh interval (0: default)
   int tune_hmul = 1;
   int32_t tune_R = 0;
@@ -174,6 +185,7 @@ static size_t layout_lane(const valmod_plan_s* P, Lane& ln) {
   w.hn = take(wp * 4);
   w.hbound = take(wp * 8);
   w.hsig = take(wp * 8);
+  w.hflat = take(wp);
   w.acnt = take(wp * 4);
   w.abuf = take((size_t)ln.n0max * (size_t)P->cap * 4);
   w.fail = take(wp * 4);
@@ -201,18 +213,37 @@ static size_t layout_lane(const valmod_plan_s* P, Lane& ln) {
     w.rec = take(wp * 4);
     w.part = take(wp * 4);
   }
+  // per-64-window extrema and per-item rounding bounds of the recurrence (both precisions)
+  const size_t nb = wp / 64 + 2;
+  w.bsw_max = take(nb * 4);
+  w.bsw_min = take(nb * 4);
+  w.bdf_max = take(nb * 4);
+  w.bdg_max = take(nb * 4);
+  w.bmu_max = take(nb * 4);
+  w.delta64 = take((size_t)ln.itemmax * 4);
   if (P->cfg.precision == VALMOD_PREC_FP32_REFRESH) {
     w.df32 = take(wp * 4);
     w.dg32 = take(wp * 4);
     w.inv32 = take(wp * 4);
-    const size_t nb = wp / 64 + 2;
-    w.bsw_max = take(nb * 4);
-    w.bsw_min = take(nb * 4);
-    w.bdf_max = take(nb * 4);
-    w.bdg_max = take(nb * 4);
     w.delta = take((size_t)ln.itemmax * 4);
     w.hard = take((size_t)ln.itemmax * 4);
   }
+  w.ring_rows = std::min<int64_t>(ln.nlenmax, kRingRows);
+  w.ring_d = take((size_t)(w.ring_rows * ln.n0max + kPad) * 8);
+  w.ring_i = take((size_t)(w.ring_rows * ln.n0max + kPad) * 4);
+  const size_t km = (size_t)P->cfg.k_motifs, kd = (size_t)P->cfg.k_discords, nl = (size_t)ln.nlenmax;
+  w.sub_vn = take(wp * 8);
+  w.sub_vd = take(wp * 8);
+  w.sub_vl = take(wp * 4);
+  w.sub_vi = take(wp * 4);
+  w.sub_mab = take(nl * km * 2 * 4);
+  w.sub_md = take(nl * km * 8);
+  w.sub_don = take(nl * kd * 2 * 4);
+  w.sub_dd = take(nl * kd * 8);
+  w.sub_gab = take(km * 3 * 4);
+  w.sub_gd = take(km * 2 * 8);
+  w.sub_gdon = take(kd * 3 * 4);
+  w.sub_gdd = take(kd * 2 * 8);
   w.total = off;
   return off;
 }
@@ -235,6 +266,7 @@ static void build_layout(valmod_plan_s* P) {
       if (gg.table) ln.ancmax = std::max(ln.ancmax, gg.segs * gg.stride);
       ln.itemmax = std::max(ln.itemmax, gg.segs * gg.bands);
       ln.total_lengths += P->lay[s].nlen;
+      ln.nlenmax = std::max(ln.nlenmax, P->lay[s].nlen);
     }
     ln.base = off;
     off += align_up(layout_lane(P, ln));
@@ -392,6 +424,9 @@ extern "C" valmod_status valmod_series_layout(valmod_plan_t P, int32_t s, valmod
 }
 
 static void release_resources(valmod_plan_s* P) {
+  // a run still in flight writes into the pinned words and records the events
+  if (P->run_pending && P->finished) (void)hipEventSynchronize(P->finished);
+  P->run_pending = false;
   if (P->exec) (void)hipGraphExecDestroy(P->exec);
   P->exec = nullptr;
   for (Lane& ln : P->lanes) {
@@ -407,7 +442,7 @@ static void release_resources(valmod_plan_s* P) {
     if (ln.hcnt) (void)hipHostFree(ln.hcnt);
     ln.hcnt = nullptr;
   }
-  for (hipEvent_t* e : {&P->start, &P->g0, &P->g1})
+  for (hipEvent_t* e : {&P->start, &P->g0, &P->g1, &P->finished})
     if (*e) {
       (void)hipEventDestroy(*e);
       *e = nullptr;
@@ -445,6 +480,7 @@ static hipError_t ensure_resources(valmod_plan_s* P) {
   ok(hipEventCreateWithFlags(&P->start, hipEventDisableTiming));
   ok(hipEventCreate(&P->g0));
   ok(hipEventCreate(&P->g1));
+  ok(hipEventCreateWithFlags(&P->finished, hipEventDisableTiming));
   for (Lane& ln : P->lanes) {
     ok(hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking));
     for (hipEvent_t* ev : {&ln.ready, &ln.done}) ok(hipEventCreateWithFlags(ev, hipEventDisableTiming));
@@ -476,13 +512,20 @@ struct LaneRun {
   // workspace
   double *xs, *A, *B, *A2, *B2, *mu, *sig, *invn, *df, *dg, *thr, *anc, *hS, *hbound, *hsig, *lbm;
   uint8_t* flat;
-  float *sw32, *thr32, *df32, *dg32, *inv32, *bsw_max, *bsw_min, *bdf_max, *bdg_max, *delta;
+  float *sw32, *thr32, *df32, *dg32, *inv32, *bsw_max, *bsw_min, *bdf_max, *bdg_max, *bmu_max, *delta64, *delta;
+  uint8_t* hflat;
   uint64_t* best;
   unsigned long long* cnt;
   int32_t *hc, *hn, *abuf, *fail, *big, *hard, *rec, *part, *mnn;
   double* mvals;
   uint64_t* mkeys;
   uint32_t* acnt;
+  double* ring_d;
+  int32_t* ring_i;
+  int64_t ring_rows = 1;
+  // stand-ins for skipped outputs
+  double *sub_vn, *sub_vd, *sub_md, *sub_dd, *sub_gd, *sub_gdd;
+  int32_t *sub_vl, *sub_vi, *sub_mab, *sub_don, *sub_gab, *sub_gdon;
   MotifSetLaunch ms{};
   // state
   size_t si = 0;
@@ -538,10 +581,28 @@ struct LaneRun {
     df32 = fp32 ? (float*)(b + w.df32) : nullptr;
     dg32 = fp32 ? (float*)(b + w.dg32) : nullptr;
     inv32 = fp32 ? (float*)(b + w.inv32) : nullptr;
-    bsw_max = fp32 ? (float*)(b + w.bsw_max) : nullptr;
-    bsw_min = fp32 ? (float*)(b + w.bsw_min) : nullptr;
-    bdf_max = fp32 ? (float*)(b + w.bdf_max) : nullptr;
-    bdg_max = fp32 ? (float*)(b + w.bdg_max) : nullptr;
+    bsw_max = (float*)(b + w.bsw_max);
+    bsw_min = (float*)(b + w.bsw_min);
+    bdf_max = (float*)(b + w.bdf_max);
+    bdg_max = (float*)(b + w.bdg_max);
+    bmu_max = (float*)(b + w.bmu_max);
+    delta64 = (float*)(b + w.delta64);
+    hflat = (uint8_t*)(b + w.hflat);
+    ring_d = (double*)(b + w.ring_d);
+    ring_i = (int32_t*)(b + w.ring_i);
+    ring_rows = w.ring_rows;
+    sub_vn = (double*)(b + w.sub_vn);
+    sub_vd = (double*)(b + w.sub_vd);
+    sub_vl = (int32_t*)(b + w.sub_vl);
+    sub_vi = (int32_t*)(b + w.sub_vi);
+    sub_mab = (int32_t*)(b + w.sub_mab);
+    sub_md = (double*)(b + w.sub_md);
+    sub_don = (int32_t*)(b + w.sub_don);
+    sub_dd = (double*)(b + w.sub_dd);
+    sub_gab = (int32_t*)(b + w.sub_gab);
+    sub_gd = (double*)(b + w.sub_gd);
+    sub_gdon = (int32_t*)(b + w.sub_gdon);
+    sub_gdd = (double*)(b + w.sub_gdd);
     delta = fp32 ? (float*)(b + w.delta) : nullptr;
     hard = fp32 ? (int32_t*)(b + w.hard) : nullptr;
     if (P->cfg.mset_radius > 0.0) {
@@ -580,10 +641,20 @@ LaneRun::Status LaneRun::advance() {
   const int esz = P->cfg.dtype == VALMOD_F32 ? 4 : 8;
   const int excl_den = P->cfg.excl_den;
   const bool fp32 = P->cfg.precision == VALMOD_PREC_FP32_REFRESH;
-  double* vnorm = o->valmp_norm + Ls.valmp;
-  double* vdist = o->valmp_dist + Ls.valmp;
-  int32_t* vlen = o->valmp_len + Ls.valmp;
-  int32_t* vidx = o->valmp_idx + Ls.valmp;
+  // the series' outputs; those the caller skips (null) but the run reads back
+  // live in the workspace
+  double* vnorm = o->valmp_norm ? o->valmp_norm + Ls.valmp : sub_vn;
+  double* vdist = o->valmp_dist ? o->valmp_dist + Ls.valmp : sub_vd;
+  int32_t* vlen = o->valmp_len ? o->valmp_len + Ls.valmp : sub_vl;
+  int32_t* vidx = o->valmp_idx ? o->valmp_idx + Ls.valmp : sub_vi;
+  int32_t* mot_ab = o->motif_ab ? o->motif_ab + 2 * Ls.motif : sub_mab;
+  double* mot_d = o->motif_d ? o->motif_d + Ls.motif : sub_md;
+  int32_t* dis_on = o->discord_on ? o->discord_on + 2 * Ls.discord : sub_don;
+  double* dis_d = o->discord_d ? o->discord_d + Ls.discord : sub_dd;
+  int32_t* g_mab = o->g_motif_abl ? o->g_motif_abl + 3 * Ls.g_motif : sub_gab;
+  double* g_md = o->g_motif_d ? o->g_motif_d + 2 * Ls.g_motif : sub_gd;
+  int32_t* g_don = o->g_discord_onl ? o->g_discord_onl + 3 * Ls.g_discord : sub_gdon;
+  double* g_dd = o->g_discord_d ? o->g_discord_d + 2 * Ls.g_discord : sub_gdd;
   if (!open) {
     const char* series = d_series + (size_t)Ls.series * esz;
     LCHECK(launch_convert(series, P->cfg.dtype, n, n + kPad, xs, (int*)&cnt[CNT_ERR], st));
@@ -602,15 +673,19 @@ LaneRun::Status LaneRun::advance() {
   const float delta_max = (float)(env_int("VALMOD_FP32_DELTA_MAX_E6", 5000) * 1.0e-6);
   const int p = P->cfg.p;
   const int D = p < 15 ? p : 15;
-  const double margin = 1.0e-11;  // pass rounding of the FP64 correlation
+  // rounding bound of a correlation evaluated directly from anchored sums
+  const double margin = direct_bound(L);
   const double rec_factor = env_int("VALMOD_RECOMPUTE_FACTOR_X100", 80) / 100.0;
   const int64_t t = L - Ls.l_min;
   const int64_t N = n - L + 1;
   const int64_t e = excl_zone(L, excl_den);
   const PassGrid grid = pass_grid(N, e, G.dstart, G.K, G.H);
-  double* pd = o->prof_dist + Ls.prof + t * N0;
-  int32_t* pi = o->prof_idx + Ls.prof + t * N0;
-  const int32_t* prev = L > Ls.l_min ? pi - N0 : nullptr;
+  // this length's profile row in the ring (and in the outputs unless skipped)
+  double* rd = ring_d + (t % ring_rows) * N0;
+  int32_t* ri = ring_i + (t % ring_rows) * N0;
+  double* pd = o->prof_dist ? o->prof_dist + Ls.prof + t * N0 : nullptr;
+  int32_t* pi = o->prof_idx ? o->prof_idx + Ls.prof + t * N0 : nullptr;
+  const int32_t* prev = L > Ls.l_min ? ring_i + ((t - 1) % ring_rows) * N0 : nullptr;
 
   const bool sweep = heaps_on && base > 0 && L > Ls.l_min;
   if (phase == 0) {
@@ -638,10 +713,16 @@ LaneRun::Status LaneRun::advance() {
       wpr.df32 = df32;
       wpr.dg32 = dg32;
       wpr.inv32 = inv32;
-      wpr.bsw_max = bsw_max;
-      wpr.bsw_min = bsw_min;
-      wpr.bdf_max = bdf_max;
-      wpr.bdg_max = bdg_max;
+    }
+    wpr.bsw_max = bsw_max;
+    wpr.bsw_min = bsw_min;
+    wpr.bdf_max = bdf_max;
+    wpr.bdg_max = bdg_max;
+    wpr.bmu_max = bmu_max;
+    if (sweep) {  // windows flat at the base length that are candidates at L
+      wpr.hflat = hflat;
+      wpr.hsig = hsig;
+      wpr.rflat = &cnt[CNT_RFLAT];
     }
     LCHECK(launch_window_prep(wpr, st));
     std::swap(A, A2);
@@ -656,7 +737,8 @@ LaneRun::Status LaneRun::advance() {
       // Alg. ComputeSubMP: sweep the partial profiles, certify by the lower bound;
       // the choice between row recompute and a full pass needs the counts
       if (lbm) LCHECK(launch_fill_counters(&cnt[CNT_MINDIST], 2, 0x7FF0000000000000ull, st));  // +inf
-      LCHECK(launch_sweep(xs, A, invn, sig, flat, N, L, e, p, base, hc, hS, hn, hbound, hsig, best, fail,
+      LCHECK(launch_sweep(xs, A, invn, sig, flat, N, L, e, p, base, hc, hS, hn, hbound, hsig, &cnt[CNT_RFLAT], margin,
+                          best, fail,
                           &cnt[CNT_NFAIL], &cnt[CNT_VALID], lbm, lbm ? &cnt[CNT_MINDIST] : nullptr,
                           lbm ? &cnt[CNT_MINLB] : nullptr, st));
       if (capture) {
@@ -714,29 +796,35 @@ LaneRun::Status LaneRun::advance() {
     ++passes;
     return e1;
   };
-  bool fp32_ready = false;
-  // per-item rounding bounds of the FP32 recurrence at this length (its inputs
-  // come from the window prep); items over the limit are listed for the FP64 kernel
-  auto fp32_setup = [&]() -> hipError_t {
-    if (fp32_ready) return hipSuccess;
-    fp32_ready = true;
-    return launch_fp32_items(bsw_max, bsw_min, bdf_max, bdg_max, N, e, G.dstart, G.K, G.H, delta_max, delta, hard,
-                             &cnt[CNT_HARD], st);
+  bool bounds_ready = false;
+  // per-item rounding bounds of the recurrence at this length (their inputs come
+  // from the window prep): FP64 always; FP32 items over the limit are listed for
+  // the FP64 kernel
+  auto bounds_setup = [&]() -> hipError_t {
+    if (bounds_ready) return hipSuccess;
+    bounds_ready = true;
+    return launch_item_bounds(bsw_max, bsw_min, bdf_max, bdg_max, bmu_max, N, e, G.dstart, G.K, G.H, L, delta_max,
+                              delta64,
+                              fp32 ? delta : nullptr, hard, &cnt[CNT_HARD], st);
   };
   bool recompute = false;  // process the recompute list (its length is a device counter)
   bool grow_collect = false;  // the collecting pass is the length's last and moves the anchor table on
   // collecting pass above per-owner thresholds from the candidates of `src`,
   // then the exact merge (top-`keep` partial profiles and best keys)
   auto collect = [&](const int32_t* src, int p_eff, int keep, int best_exact) -> hipError_t {
-    hipError_t e1 = sweep ? launch_zero_counters(&cnt[CNT_NFAIL], 1, st) : hipSuccess;
+    // the wavefront-per-owner merge list is rebuilt by every collecting pass (a
+    // length may run two); the recompute list keeps the owners listed so far at
+    // this length, except after a sweep, whose list the collecting pass replaces
+    hipError_t e1 = launch_zero_counters(&cnt[CNT_BIG], 1, st);
+    if (e1 == hipSuccess && sweep) e1 = launch_zero_counters(&cnt[CNT_NFAIL], 1, st);
     if (e1 == hipSuccess)
       e1 = launch_seed_append(xs, A, invn, flat, src, N, L, e, p_eff, p_eff == 1 ? 0 : D, margin, best_exact, thr,
                               fp32 ? thr32 : nullptr, acnt, fail, &cnt[CNT_NFAIL], st);
     PassLaunch q = pl;
     q.append = true;
     q.grow = grow_collect;
+    if (e1 == hipSuccess) e1 = bounds_setup();
     if (fp32) {
-      if (e1 == hipSuccess) e1 = fp32_setup();
       q.fp32 = true;
       q.delta = delta;
       q.delta_max = delta_max;
@@ -750,14 +838,19 @@ LaneRun::Status LaneRun::advance() {
       h.nitems = grid.segs * grid.bands;
       h.nitems_dev = &cnt[CNT_HARD];
       h.grow = grow_collect;  // the items the FP32 pass left (disjoint anchors)
+      h.delta = delta64;
+      h.delta_max = INFINITY;
       if (e1 == hipSuccess) e1 = launch_pass(h, st);
       ++passes;
     } else if (e1 == hipSuccess) {
+      q.delta = delta64;
+      q.delta_max = INFINITY;
       e1 = timed_pass(q);
     }
     if (e1 == hipSuccess)
       e1 = launch_merge(xs, A, invn, sig, flat, thr, acnt, abuf, P->cap, N, L, p, keep, margin, best_exact, hc, hS,
-                        hn, hbound, hsig, best, fail, &cnt[CNT_NFAIL], big, &cnt[CNT_BIG], &cnt[CNT_APPENDS], st);
+                        hn, hbound, hsig, hflat, best, fail, &cnt[CNT_NFAIL], big, &cnt[CNT_BIG], &cnt[CNT_APPENDS],
+                        st);
     recompute = true;
     return e1;
   };
@@ -807,38 +900,42 @@ LaneRun::Status LaneRun::advance() {
   const int md = P->cfg.m_discords;
   if (full) {
     const int32_t* src = prev;
-    // the last pass of the length (the collecting pass if one runs) also moves
-    // the anchor table on to L + 1
-    const bool collects = rebuild || md > 1 || (fp32 && L > Ls.l_min);
+    // Every length's neighbours come from a collecting pass: the recurrence (in
+    // either precision) only selects the candidates that its rounding bound
+    // cannot exclude, and the merge evaluates them directly. At the first length
+    // an FP64 matrix-profile pass (running best keys) provides the seeds. The
+    // collecting pass is the length's last and moves the anchor table on to L + 1.
     const bool grow = G.table && anc_len == L && L < Ls.l_max;
-    grow_collect = grow && collects;
-    if (L == Ls.l_min || (!fp32 && !rebuild && md == 1)) {
-      // exact FP64 matrix-profile pass: running best keys seeded from the previous length
-      LCHECK(launch_seed_mp(xs, mu, invn, flat, prev, N, L, e, best, thr, thr32, st));
+    grow_collect = grow;
+    if (L == Ls.l_min) {
+      LCHECK(launch_seed_mp(xs, mu, invn, flat, nullptr, N, L, e, best, thr, thr32, st));
       PassLaunch q = pl;
       q.append = false;
-      q.grow = grow && !collects;
-      if (fp32) {
-        LCHECK(launch_pass(q, st));
-        ++passes;
-      } else {
-        LCHECK(timed_pass(q));
-      }
-      if (rebuild || md > 1) {  // first length: the exact neighbours seed the collecting pass
-        LCHECK(launch_keys_to_idx(best, N, pi, st));
-        src = pi;
+      q.grow = false;
+      LCHECK(launch_pass(q, st));
+      ++passes;
+      LCHECK(launch_keys_to_idx(best, N, ri, st));
+      src = ri;
+      if (rebuild) {
+        // exact neighbours first (a list of one threshold rarely overflows), so
+        // that the owners whose partial-profile list overflows keep them
+        grow_collect = false;
+        LCHECK(collect(src, 1, 0, 0));
+        LCHECK(launch_keys_to_idx(best, N, ri, st));
+        grow_collect = grow;
       }
     }
     if (rebuild) {
-      // new partial profiles at base L (Alg. ComputeMatrixProfile)
+      // new partial profiles at base L (Alg. ComputeMatrixProfile); at the first
+      // length `best` already holds the exact neighbours
       LCHECK(collect(src, p, p, L == Ls.l_min ? 1 : 0));
       base = L;
       probe_next = true;
     } else if (md > 1) {
       // exact top-m lists of every owner (Def. m-th best match)
       LCHECK(collect(src, md, md, 0));
-    } else if (fp32 && L > Ls.l_min) {
-      // exact neighbours from an FP32 collecting pass seeded by the previous length
+    } else {
+      // exact neighbours, seeded by the previous length (or the first length's pass)
       LCHECK(collect(src, 1, 0, 0));
     }
     if (grow) anc_len = L + 1;
@@ -853,7 +950,7 @@ LaneRun::Status LaneRun::advance() {
                                  st));
   else if (recompute)
     LCHECK(launch_recompute(xs, A, invn, flat, fail, &cnt[CNT_NFAIL], N, N, L, e, best, st));
-  LCHECK(launch_finalize(xs, mu, sig, best, N, N0, L, pd, pi, vnorm, vdist, vlen, vidx, st));
+  LCHECK(launch_finalize(xs, mu, sig, best, N, N0, L, rd, ri, pd, pi, vnorm, vdist, vlen, vidx, st));
   if (md > 1) {
     const int kd = P->cfg.k_discords;
     const int64_t at = Ls.mdiscord + t * md * kd;
@@ -861,7 +958,18 @@ LaneRun::Status LaneRun::advance() {
     LCHECK(launch_mth_rankings(mvals, mnn, N0, n, L, md, excl_den, kd, o->mdiscord_on + 2 * at, o->mdiscord_d + at,
                                st));
   }
-  if (paper_split) LCHECK(launch_mark_partial(part, &cnt[CNT_NPART], N, lbm, pd, pi, st));
+  if (paper_split) {
+    LCHECK(launch_mark_partial(part, &cnt[CNT_NPART], N, lbm, rd, ri, st));
+    if (pd || pi) LCHECK(launch_mark_partial(part, &cnt[CNT_NPART], N, lbm, pd, pi, st));
+  }
+  // per-length rankings of the ring's rows, a group of lengths at a time (one
+  // workgroup per length)
+  if (t % ring_rows == ring_rows - 1 || L == Ls.l_max) {
+    const int64_t t0 = t - t % ring_rows;
+    const int km = P->cfg.k_motifs, kd = P->cfg.k_discords;
+    LCHECK(launch_rankings(ring_d, ring_i, N0, n, (int)(Ls.l_min + t0), (int)(t - t0 + 1), excl_den, km, kd,
+                           mot_ab + 2 * t0 * km, mot_d + t0 * km, dis_on + 2 * t0 * kd, dis_d + t0 * kd, st));
+  }
   LCHECK(launch_record_stats(cnt, o->stats ? o->stats + Ls.stats + t * VALMOD_NSTATS : nullptr, full ? 1 : 0,
                              nvalid, nswept_fail, paper_split == 1 ? 2 : (recompute ? 1 : 0), passes, st));
   // VALMOD_PROGRESS=k: one line on stderr every k lengths, once the length has run
@@ -875,20 +983,15 @@ LaneRun::Status LaneRun::advance() {
   phase = 0;
   if (++L > Ls.l_max) {
     const int km = P->cfg.k_motifs, kd = P->cfg.k_discords;
-    LCHECK(launch_rankings(o->prof_dist + Ls.prof, o->prof_idx + Ls.prof, N0, n, Ls.l_min, (int)Ls.nlen, excl_den,
-                           km, kd, o->motif_ab + 2 * Ls.motif, o->motif_d + Ls.motif, o->discord_on + 2 * Ls.discord,
-                           o->discord_d + Ls.discord, st));
-    LCHECK(launch_global_rank(vnorm, vdist, vlen, vidx, N0, o->discord_on + 2 * Ls.discord, o->discord_d + Ls.discord,
-                              (int)Ls.nlen, Ls.l_min, excl_den, km, kd, o->g_motif_abl + 3 * Ls.g_motif,
-                              o->g_motif_d + 2 * Ls.g_motif, o->g_discord_onl + 3 * Ls.g_discord,
-                              o->g_discord_d + 2 * Ls.g_discord, st));
+    LCHECK(launch_global_rank(vnorm, vdist, vlen, vidx, N0, dis_on, dis_d, (int)Ls.nlen, Ls.l_min, excl_den, km, kd,
+                              g_mab, g_md, g_don, g_dd, st));
     if (P->cfg.mset_radius > 0.0) {
       // motif sets of the global top-k pairs (Sec. "Finding Motif Sets")
       ms.xs = xs;
       ms.n = n;
       ms.n0 = N0;
-      ms.abl = o->g_motif_abl + 3 * Ls.g_motif;
-      ms.gd = o->g_motif_d + 2 * Ls.g_motif;
+      ms.abl = g_mab;
+      ms.gd = g_md;
       ms.k = km;
       ms.D = P->cfg.mset_radius;
       ms.excl_den = excl_den;
@@ -978,15 +1081,10 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
                                     const valmod_outputs* o, void* stream_) {
   if (!P || !d_series || !d_ws || !o) return VALMOD_E_ARG;
   if (((uintptr_t)d_ws) % kAlign) return VALMOD_E_ARG;
-  if (!o->prof_dist || !o->prof_idx || !o->valmp_norm || !o->valmp_dist || !o->valmp_len || !o->valmp_idx ||
-      !o->motif_ab || !o->motif_d || !o->discord_on || !o->discord_d || !o->g_motif_abl || !o->g_motif_d ||
-      !o->g_discord_onl || !o->g_discord_d)
-    return VALMOD_E_ARG;
   if (P->cfg.m_discords > 1 && (!o->mdiscord_on || !o->mdiscord_d || !o->g_mdiscord_onl || !o->g_mdiscord_d))
     return VALMOD_E_ARG;
   if (P->cfg.mset_radius > 0.0 && (!o->mset_count || !o->mset_off || !o->mset_dist)) return VALMOD_E_ARG;
   hipStream_t st = (hipStream_t)stream_;
-  valmod_status status = VALMOD_OK;
   int prev_dev = -1;
   if (hipGetDevice(&prev_dev) != hipSuccess) return VALMOD_E_HIP;
   if (hipSetDevice(P->cfg.device) != hipSuccess) return VALMOD_E_HIP;
@@ -995,6 +1093,7 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
   P->pass_ms = 0.0;
   P->pass_launches = 0;
   P->pass_cells = 0;
+  P->run_pending = false;
   if (e == hipSuccess && P->cfg.graph) {
     // one captured graph per set of buffers and stream, replayed on later calls
     const bool same = P->exec && P->key_series == d_series && P->key_ws == d_ws && P->key_stream == st &&
@@ -1022,22 +1121,36 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
     if (e == hipSuccess) e = hipEventRecord(P->g0, st);
     if (e == hipSuccess) e = hipGraphLaunch(P->exec, st);
     if (e == hipSuccess) e = hipEventRecord(P->g1, st);
-    if (e == hipSuccess) e = hipEventSynchronize(P->g1);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, P->g0, P->g1);
+  } else if (e == hipSuccess) {
+    e = enqueue_run(P, ws, o, (const char*)d_series, st, false);
+  }
+  // device error flags of every lane, read by valmod_run_status
+  for (Lane& ln : P->lanes)
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&ln.hcnt[kErrSlot], ws + ln.base + ln.ws.counters + CNT_ERR * 8, 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipEventRecord(P->finished, st);
+  if (e == hipSuccess) P->run_pending = true;
+  (void)hipSetDevice(prev_dev);
+  return e == hipSuccess ? VALMOD_OK : VALMOD_E_HIP;
+}
+
+extern "C" valmod_status valmod_run_status(valmod_plan_t P, void* stream_) {
+  if (!P) return VALMOD_E_ARG;
+  if (!P->run_pending) return P->last_status;
+  int prev_dev = -1;
+  if (hipGetDevice(&prev_dev) != hipSuccess) return VALMOD_E_HIP;
+  if (hipSetDevice(P->cfg.device) != hipSuccess) return VALMOD_E_HIP;
+  hipError_t e = stream_ ? hipStreamSynchronize((hipStream_t)stream_) : hipSuccess;
+  if (e == hipSuccess) e = hipEventSynchronize(P->finished);
+  P->pass_ms = 0.0;
+  if (e == hipSuccess && P->cfg.graph) {
     // graph mode reports the whole replay as one launch
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, P->g0, P->g1);
     P->pass_ms = ms;
     P->pass_launches = 1;
     P->pass_cells = P->graph_cells;
   } else if (e == hipSuccess) {
-    e = enqueue_run(P, ws, o, (const char*)d_series, st, false);
-  }
-  // device error flags of every lane
-  for (Lane& ln : P->lanes)
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(&ln.hcnt[4], ws + ln.base + ln.ws.counters + CNT_ERR * 8, 8, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e == hipSuccess && !P->cfg.graph) {
     for (Lane& ln : P->lanes)
       for (int64_t i = 0; e == hipSuccess && i + 1 < ln.nev; i += 2) {
         float ms = 0.f;
@@ -1045,12 +1158,15 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
         P->pass_ms += ms;
       }
   }
+  valmod_status status = VALMOD_OK;
   if (e != hipSuccess) {
     status = VALMOD_E_HIP;
   } else {
     for (Lane& ln : P->lanes)
-      if (ln.hcnt[4]) status = VALMOD_E_DEVICE;
+      if (ln.hcnt[kErrSlot]) status = VALMOD_E_DEVICE;
   }
+  P->run_pending = false;
+  P->last_status = status;
   (void)hipSetDevice(prev_dev);
   return status;
 }
@@ -1062,7 +1178,8 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
 // are overwritten (the real run writes them again).
 extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, void* d_ws, const valmod_outputs* o,
                                          void* stream, int32_t* chosen) {
-  if (!P || !d_series || !d_ws || !o) return VALMOD_E_ARG;
+  (void)o;  // the tuning runs skip every output
+  if (!P || !d_series || !d_ws) return VALMOD_E_ARG;
   const bool fp32 = P->cfg.precision == VALMOD_PREC_FP32_REFRESH;
   int sbest = 0;
   double cbest = -1.0;
@@ -1088,33 +1205,9 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
   const valmod_layout& Ls = P->lay[sbest];
   const int esz = P->cfg.dtype == VALMOD_F32 ? 4 : 8;
   const int32_t T = (int32_t)std::min<int64_t>(3, Ls.nlen);
-  valmod_outputs so = *o;  // the first T lengths of series sbest
-  so.prof_dist += Ls.prof;
-  so.prof_idx += Ls.prof;
-  so.valmp_norm += Ls.valmp;
-  so.valmp_dist += Ls.valmp;
-  so.valmp_len += Ls.valmp;
-  so.valmp_idx += Ls.valmp;
-  so.motif_ab += 2 * Ls.motif;
-  so.motif_d += Ls.motif;
-  so.discord_on += 2 * Ls.discord;
-  so.discord_d += Ls.discord;
-  so.g_motif_abl += 3 * Ls.g_motif;
-  so.g_motif_d += 2 * Ls.g_motif;
-  so.g_discord_onl += 3 * Ls.g_discord;
-  so.g_discord_d += 2 * Ls.g_discord;
-  if (so.stats) so.stats += Ls.stats;
-  if (P->cfg.m_discords > 1) {
-    so.mdiscord_on += 2 * Ls.mdiscord;
-    so.mdiscord_d += Ls.mdiscord;
-    so.g_mdiscord_onl += 3 * Ls.g_mdiscord;
-    so.g_mdiscord_d += 2 * Ls.g_mdiscord;
-  }
-  if (P->cfg.mset_radius > 0.0) {
-    so.mset_count += Ls.g_motif;
-    so.mset_off += Ls.mset;
-    so.mset_dist += Ls.mset;
-  }
+  // the tuning runs write no output (every output skipped)
+  valmod_outputs so;
+  memset(&so, 0, sizeof(so));
   const void* sub_series = (const char*)d_series + (size_t)Ls.series * esz;
   double best_ms = -1.0;
   std::pair<int, int32_t> best = {P->tune_hmul, P->tune_R};
@@ -1130,6 +1223,8 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
     sc.lanes = 1;
     sc.graph = 0;
     sc.refresh_R = c.second;
+    sc.m_discords = 1;  // the pass geometry alone is timed
+    sc.mset_radius = 0.0;
     valmod_plan_t sub = nullptr;
     valmod_status st = valmod_plan(&sc, &sub);
     if (st != VALMOD_OK) return st;
@@ -1140,8 +1235,10 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
       continue;
     }
     st = valmod_run(sub, sub_series, d_ws, &so, stream);
+    if (st == VALMOD_OK) st = valmod_run_status(sub, stream);
     const auto t0 = std::chrono::steady_clock::now();
     if (st == VALMOD_OK) st = valmod_run(sub, sub_series, d_ws, &so, stream);
+    if (st == VALMOD_OK) st = valmod_run_status(sub, stream);
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     valmod_plan_free(sub);
     if (st != VALMOD_OK) return st;
@@ -1174,4 +1271,12 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
     chosen[1] = P->geom[sbest].K;
   }
   return VALMOD_OK;
+}
+
+extern "C" double valmod_rounding_bound(int32_t precision, int64_t H, int32_t L, double phi, double psi, double xi) {
+  if (H < 1 || L < 1 || !(phi >= 0.0) || !(psi >= 0.0) || !(xi >= 0.0)) return NAN;
+  if (precision == VALMOD_PREC_FP32_REFRESH)
+    return recurrence_bound(kEps32, (double)H, phi, psi, xi, L) + kFilter32;
+  if (precision == VALMOD_PREC_FP64) return recurrence_bound(kEps64, (double)H, phi, psi, xi, L);
+  return NAN;
 }

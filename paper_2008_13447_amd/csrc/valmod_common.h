@@ -73,6 +73,42 @@ __device__ __forceinline__ double wave_min_f64(double v) {
 
 __device__ __forceinline__ int64_t iabs64(int64_t v) { return v < 0 ? -v : v; }
 
+// --------------------------------------------------------------------------
+// Rounding bounds, in correlation units (rho = C / (sw_i sw_j), sw = sigma sqrt(L)).
+//
+// Direct anchored sums S = sum_{k<L} a_k b_k with a_k = x_{o+k} - x_o: an FMA
+// chain (or one FMA per length when grown) errs by at most L u sum |a_k b_k|
+// <= L u |a| |b| (u = 2^-53), and |a|^2 = L sigma^2 + L (mu - x_o)^2 <=
+// L (L + 1) sigma^2, so |a| |b| <= (L + 1) sw_o sw_c. The conversion to the
+// co-moment (S - A_o A_c / L, |A_o A_c| / L <= L sw_o sw_c) and the
+// normalisation add a few units more: (L + 1)(L + 2) 2^-52 covers all of it.
+__host__ __device__ __forceinline__ double direct_bound(int L) {
+  return (double)(L + 1) * (double)(L + 2) * 2.220446049250313e-16;
+}
+
+// The diagonal recurrence over a work item of H rows, in a precision with unit
+// roundoff eps: each step adds two rounded FMAs on |C| <= sw_i sw_j, the inputs
+// df, dg carry one rounding each, and the start and the normalisation a few
+// more. The means inside dg = (x_{i+L} - mu_{i+1}) + (x_i - mu_i) are FP64 values
+// near the series level, so dg also carries their absolute rounding, up to
+// 2 u max|mu| (u = 2^-53), which each step multiplies by |df|. With
+// Phi = (max sw / min sw)_rows (max sw / min sw)_cols,
+// Psi = (max|df|_rows max|dg|_cols + max|dg|_rows max|df|_cols) / (min sw_rows min sw_cols) and
+// Xi = (max|df|_rows + max|df|_cols) max|mu| / (min sw_rows min sw_cols)
+// over the item's windows, the first-order error of rho after r <= H steps is
+// at most eps [(2H + 1) Phi + 4 H Psi + 4] + 2 u H Xi; the bound doubles it for
+// the higher-order terms and adds the error of the FP64 anchor it starts from.
+__host__ __device__ __forceinline__ double recurrence_bound(double eps, double H, double phi, double psi, double xi,
+                                                           int L) {
+  return 2.0 * (eps * ((2.0 * H + 1.0) * phi + 4.0 * H * psi + 4.0) + 2.0 * 1.1102230246251565e-16 * H * xi) +
+         direct_bound(L);
+}
+constexpr double kEps32 = 5.9604644775390625e-08;   // 2^-24
+constexpr double kEps64 = 1.1102230246251565e-16;   // 2^-53
+// the FP32 filter compares the rounded difference rho - threshold (|.| < 4)
+// with -delta: one more FP32 ulp at magnitude 2..4
+constexpr double kFilter32 = 2.384185791015625e-07;  // 2^-22
+
 __host__ __device__ __forceinline__ int64_t excl_zone(int64_t L, int64_t den) {
   return (L + den - 1) / den;
 }

@@ -11,7 +11,10 @@
 // costs O(1): rho_L = (S_L - A_o A_c / L) / (L sigma_o sigma_c), with A the
 // anchored window sums of the statistics kernel. Every candidate not stored has
 // a base correlation <= bound_rho (stored per owner), hence a distance at L of
-// at least sqrt(b (1 - max(bound_rho, 0)^2)) sigma_{o,b} / sigma_{o,L}.
+// at least sqrt(b (1 - max(bound_rho, 0)^2)) sigma_{o,b} / sigma_{o,L}
+// (Eq. lowerBoundFinalFormula), except the windows that were flat at b (never
+// collected): each of them, c, is at least sqrt(b) (sigma_{o,b} / sigma_{o,L} -
+// sigma_{c,b} / sigma_{c,L}) away, and the sweep takes the smaller bound.
 #include "valmod_common.h"
 #include "valmod_kernels.h"
 
@@ -197,7 +200,8 @@ __global__ __launch_bounds__(kWave) void k_seed_append(const double* __restrict_
 constexpr int kMergeCap = 512;
 constexpr int kSmallG = 8;
 
-// every candidate not collected is below the threshold (up to the pass rounding);
+// every candidate not collected has an exact correlation below the threshold
+// (the pass compares with the threshold lowered by its item's rounding bound);
 // below -1 every candidate was collected, and -3 marks a complete profile
 __device__ __forceinline__ double collect_bound(double thr, double margin) {
   return thr < -1.5 ? -3.0 : thr + 2.0 * margin;
@@ -208,8 +212,9 @@ __global__ __launch_bounds__(kWave) void k_merge_small(
     const double* __restrict__ sig, const uint8_t* __restrict__ flat, const double* __restrict__ thr,
     const uint32_t* __restrict__ cnt, const int32_t* __restrict__ buf, int64_t cap, int64_t N, int L, int p,
     int keep, double margin, int best_exact, int32_t* __restrict__ hc, double* __restrict__ hS, int32_t* __restrict__ hn,
-    double* __restrict__ hbound, double* __restrict__ hsig, uint64_t* __restrict__ best, int32_t* __restrict__ fail,
-    unsigned long long* __restrict__ nfail, int32_t* __restrict__ big, unsigned long long* __restrict__ nbig) {
+    double* __restrict__ hbound, double* __restrict__ hsig, uint8_t* __restrict__ hflat, uint64_t* __restrict__ best,
+    int32_t* __restrict__ fail, unsigned long long* __restrict__ nfail, int32_t* __restrict__ big,
+    unsigned long long* __restrict__ nbig) {
   const int t = threadIdx.x, l = t % kSmallG, gb = t - l;
   const int64_t o = (int64_t)blockIdx.x * (kWave / kSmallG) + t / kSmallG;
   const bool live = o < N;
@@ -260,6 +265,7 @@ __global__ __launch_bounds__(kWave) void k_merge_small(
       hn[o] = 0;
       hbound[o] = 2.0;
       hsig[o] = sig[o];
+      hflat[o] = flat[o];
       if (skip) {
         if (!best_exact || flat[o]) best[o] = kEmptyKey;
       } else if (!best_exact) {
@@ -270,7 +276,13 @@ __global__ __launch_bounds__(kWave) void k_merge_small(
     return;
   }
   if (m > kSmallG) {
-    if (l == 0) push_fail(big, nbig, o);
+    if (l == 0) {
+      hflat[o] = 0;  // a non-flat owner (k_merge_big writes the rest)
+      // the list holds each owner at most once per merge (its counter is cleared
+      // before every collecting pass); never write past its N entries
+      const unsigned long long pos = atomicAdd(nbig, 1ull);
+      if ((int64_t)pos < N) big[pos] = (int32_t)o;
+    }
     return;
   }
   if (ok && rank < keep) {
@@ -279,17 +291,19 @@ __global__ __launch_bounds__(kWave) void k_merge_small(
   }
   if (ok && rank == 0) best[o] = key;
   if (l == 0) {
-    const double sb = collect_bound(thr[o], margin);
+    // the best candidate not kept was evaluated directly (error <= margin)
+    const double sb = collect_bound(thr[o], margin), nbu = nb + margin;
     hn[o] = (int32_t)(m < keep ? m : keep);
-    hbound[o] = nb > sb ? nb : sb;
+    hbound[o] = nbu > sb ? nbu : sb;
     hsig[o] = sig[o];
+    hflat[o] = 0;
   }
 }
 
 __global__ __launch_bounds__(kWave) void k_merge_big(
     const double* __restrict__ xs, const double* __restrict__ A, const double* __restrict__ invn,
     const double* __restrict__ sig, const double* __restrict__ thr, const uint32_t* __restrict__ cnt,
-    const int32_t* __restrict__ buf, int64_t cap, int L, int p, int keep, double margin,
+    const int32_t* __restrict__ buf, int64_t cap, int64_t N, int L, int p, int keep, double margin,
     int32_t* __restrict__ hc, double* __restrict__ hS, int32_t* __restrict__ hn, double* __restrict__ hbound,
     double* __restrict__ hsig, uint64_t* __restrict__ best, const int32_t* __restrict__ big,
     const unsigned long long* __restrict__ nbig) {
@@ -299,7 +313,8 @@ __global__ __launch_bounds__(kWave) void k_merge_big(
   double* ssum = merge_lds + 2 * cap;
   __shared__ double sbound;
   const int t = threadIdx.x;
-  const int64_t count = (int64_t)*nbig;
+  const int64_t listed = (int64_t)*nbig;
+  const int64_t count = listed < N ? listed : N;  // the list has N entries
   for (int64_t w = blockIdx.x; w < count; w += gridDim.x) {
     const int64_t o = big[w];
     const int64_t m = cnt[o];  // kSmallG < m <= cap
@@ -324,7 +339,7 @@ __global__ __launch_bounds__(kWave) void k_merge_big(
         hS[o * p + rank] = ssum[r];
       }
       if (rank == 0) best[o] = k;
-      if (rank == keep && srho[r] > sbound) sbound = srho[r];  // a single lane has this rank
+      if (rank == keep && srho[r] + margin > sbound) sbound = srho[r] + margin;  // a single lane has this rank
     }
     __syncthreads();
     if (t == 0) {
@@ -347,7 +362,8 @@ __global__ void k_sweep(const double* __restrict__ xs, const double* __restrict_
                         const double* __restrict__ sig, const uint8_t* __restrict__ flat, int64_t N, int L, int64_t e,
                         int p, int base, const int32_t* __restrict__ hc, double* __restrict__ hS,
                         const int32_t* __restrict__ hn, const double* __restrict__ hbound,
-                        const double* __restrict__ hsig, uint64_t* __restrict__ best, int32_t* __restrict__ fail,
+                        const double* __restrict__ hsig, const unsigned long long* __restrict__ rflat, double margin,
+                        uint64_t* __restrict__ best, int32_t* __restrict__ fail,
                         unsigned long long* __restrict__ nfail, unsigned long long* __restrict__ nvalid,
                         double* __restrict__ lbm, unsigned long long* __restrict__ min_dist,
                         unsigned long long* __restrict__ min_lb) {
@@ -381,17 +397,28 @@ __global__ void k_sweep(const double* __restrict__ xs, const double* __restrict_
       }
     }
     if (hsig[o] > 0.0) {
+      const double ro = hsig[o] / sig[o];  // sigma_{o,b} / sigma_{o,L}
       if (hbound[o] < -2.5) {
         max_lb = INFINITY;  // complete profile: no candidate was left out
       } else {
         const double q = hbound[o] > 0.0 ? (hbound[o] < 1.0 ? hbound[o] : 1.0) : 0.0;
-        max_lb = sqrt((double)base * (1.0 - q * q)) * hsig[o] / sig[o];
+        max_lb = sqrt((double)base * (1.0 - q * q)) * ro;
+      }
+      // windows flat at b (never stored) that are candidates at L
+      const double rf = __longlong_as_double((long long)*rflat);
+      if (rf > 0.0) {
+        const double lbf = sqrt((double)base) * (ro > rf ? ro - rf : 0.0);
+        max_lb = lbf < max_lb ? lbf : max_lb;
       }
     }
     if (kb != kEmptyKey) {
+      // the stored minimum from a correlation evaluated directly (error <= margin):
+      // certified when even its largest possible exact distance is below the bound
       const double u = 1.0 - rb;
       min_d = sqrt(2.0 * (double)L * (u > 0.0 ? u : 0.0));
-      valid = hsig[o] > 0.0 && (max_lb == INFINITY || min_d < max_lb * (1.0 - 1.0e-9));
+      const double uh = u + margin;
+      const double d_hi = sqrt(2.0 * (double)L * (uh > 0.0 ? uh : 0.0));
+      valid = hsig[o] > 0.0 && (max_lb == INFINITY || d_hi < max_lb * (1.0 - 1.0e-12));
     }
     best[o] = valid ? kb : kEmptyKey;
     if (!valid && lbm) lbm[o] = max_lb < INFINITY ? max_lb : 0.0;
@@ -636,29 +663,31 @@ hipError_t launch_seed_append(const double* xs, const double* A, const double* i
 hipError_t launch_merge(const double* xs, const double* A, const double* invn, const double* sig, const uint8_t* flat,
                         const double* thr, const uint32_t* cnt, const int32_t* buf, int64_t cap, int64_t N, int L,
                         int p, int keep, double margin, int best_exact, int32_t* hc, double* hS, int32_t* hn,
-                        double* hbound, double* hsig, uint64_t* best, int32_t* fail, unsigned long long* nfail,
-                        int32_t* big, unsigned long long* nbig, unsigned long long* nappend, hipStream_t st) {
+                        double* hbound, double* hsig, uint8_t* hflat, uint64_t* best, int32_t* fail,
+                        unsigned long long* nfail, int32_t* big, unsigned long long* nbig, unsigned long long* nappend,
+                        hipStream_t st) {
   if (N <= 0) return hipSuccess;
   if (cap <= 0 || cap > kMergeCap || keep < 0 || keep > p) return hipErrorInvalidValue;
   k_merge_small<<<blocks_for(N, kWave / kSmallG), kWave, 0, st>>>(xs, A, invn, sig, flat, thr, cnt, buf, cap, N, L, p,
                                                                    keep, margin, best_exact, hc, hS, hn, hbound, hsig,
-                                                                   best, fail, nfail, big, nbig);
+                                                                   hflat, best, fail, nfail, big, nbig);
   // a wavefront per listed owner; 4,096 workgroups fill the chip (the list is
   // walked in a grid-stride loop, so a short list costs little to dispatch)
   k_merge_big<<<(unsigned)(N < 4096 ? N : 4096), kWave, (size_t)cap * 3 * sizeof(double), st>>>(
-      xs, A, invn, sig, thr, cnt, buf, cap, L, p, keep, margin, hc, hS, hn, hbound, hsig, best, big, nbig);
+      xs, A, invn, sig, thr, cnt, buf, cap, N, L, p, keep, margin, hc, hS, hn, hbound, hsig, best, big, nbig);
   k_sum_counts<<<64, 1024, 0, st>>>(cnt, N, nappend);
   return hipGetLastError();
 }
 
 hipError_t launch_sweep(const double* xs, const double* A, const double* invn, const double* sig, const uint8_t* flat,
                         int64_t N, int L, int64_t e, int p, int base, const int32_t* hc, double* hS, const int32_t* hn,
-                        const double* hbound, const double* hsig, uint64_t* best, int32_t* fail,
-                        unsigned long long* nfail, unsigned long long* nvalid, double* lbm,
-                        unsigned long long* min_dist, unsigned long long* min_lb, hipStream_t st) {
+                        const double* hbound, const double* hsig, const unsigned long long* rflat, double margin,
+                        uint64_t* best, int32_t* fail, unsigned long long* nfail, unsigned long long* nvalid,
+                        double* lbm, unsigned long long* min_dist, unsigned long long* min_lb, hipStream_t st) {
   if (N <= 0) return hipSuccess;
+  if (!rflat) return hipErrorInvalidValue;
   k_sweep<<<blocks_for(N, 128), 128, 0, st>>>(xs, A, invn, sig, flat, N, L, e, p, base, hc, hS, hn, hbound, hsig,
-                                               best, fail, nfail, nvalid, lbm, min_dist, min_lb);
+                                               rflat, margin, best, fail, nfail, nvalid, lbm, min_dist, min_lb);
   return hipGetLastError();
 }
 

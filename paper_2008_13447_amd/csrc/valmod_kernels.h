@@ -24,6 +24,7 @@ enum CounterSlot {
   CNT_MINLB = 10,    // paper mode: minimum bound of the failing owners (bits of a double)
   CNT_NREC = 11,     // paper mode: owners listed for the row recompute
   CNT_NPART = 12,    // paper mode: owners left partial
+  CNT_RFLAT = 13,    // largest sigma_b / sigma_L of the windows flat at the base length but not at L (bits of a double)
   CNT_WORDS = 32
 };
 
@@ -36,8 +37,8 @@ struct PassLaunch {
   const int32_t* items;  // optional work-item list (FP64 re-run of items the FP32 bound rejects)
   int64_t nitems;        // grid size for the list (upper bound of the count)
   const unsigned long long* nitems_dev;  // device count of listed items
-  const float* delta;    // FP32: rounding bound per work item
-  float delta_max;
+  const float* delta;    // rounding bound per work item of the pass's precision (null: none)
+  float delta_max;       // items with a larger bound are skipped (left to the FP64 kernel)
   bool fp32;
   uint64_t* best;
   uint32_t* cnt;
@@ -83,20 +84,34 @@ struct WindowPrep {
   unsigned long long* nflat;
   double *df, *dg;
   float* sw32;
-  float *df32, *dg32, *inv32, *bsw_max, *bsw_min, *bdf_max, *bdg_max;  // FP32 path (null: none)
+  float *df32, *dg32, *inv32;                    // FP32 path (null: none)
+  float *bsw_max, *bsw_min, *bdf_max, *bdg_max, *bmu_max;  // per-64-window extrema of the rounding bounds
+  // partial profiles at base b (null: none): windows flat at b (hflat) but not at L
+  // raise *rflat to their sigma_b / sigma_L (hsig: sigma at b)
+  const uint8_t* hflat;
+  const double* hsig;
+  unsigned long long* rflat;
 };
 hipError_t launch_window_prep(const WindowPrep& w, hipStream_t st);
 hipError_t launch_seed_mp(const double* xs, const double* mu, const double* invn, const uint8_t* flat,
                           const int32_t* prev_idx, int64_t N, int L, int64_t e, uint64_t* best,
                           double* thr, float* thr32, hipStream_t st);
 hipError_t launch_pass(const PassLaunch& p, hipStream_t st);
-hipError_t launch_fp32_items(const float* bsw_max, const float* bsw_min, const float* bdf_max, const float* bdg_max,
-                             int64_t N, int64_t e, int64_t dstart, int K, int64_t H, float delta_max, float* delta,
-                             int32_t* hard, unsigned long long* nhard, hipStream_t st);
-// (also writes +inf / -1 to the profile row's entries N .. N0 - 1)
+// Rounding bounds of the diagonal pass per work item: delta64 (FP64 recurrence)
+// always; with delta32 non-null also the FP32 bound, and the items whose FP32
+// bound exceeds delta_max are listed in `hard` for the FP64 kernel.
+hipError_t launch_item_bounds(const float* bsw_max, const float* bsw_min, const float* bdf_max, const float* bdg_max,
+                              const float* bmu_max, int64_t N, int64_t e, int64_t dstart, int K, int64_t H, int L,
+                              float delta_max,
+                              float* delta64, float* delta32, int32_t* hard, unsigned long long* nhard,
+                              hipStream_t st);
+// Profile row of one length from the best keys into ring_dist / ring_idx and,
+// when non-null, prof_dist / prof_idx (also +inf / -1 for the entries
+// N .. N0 - 1); the VALMP update.
 hipError_t launch_finalize(const double* xs, const double* mu, const double* sig, const uint64_t* best,
-                           int64_t N, int64_t N0, int L, double* prof_dist, int32_t* prof_idx, double* valmp_norm,
-                           double* valmp_dist, int32_t* valmp_len, int32_t* valmp_idx, hipStream_t st);
+                           int64_t N, int64_t N0, int L, double* ring_dist, int32_t* ring_idx, double* prof_dist,
+                           int32_t* prof_idx, double* valmp_norm, double* valmp_dist, int32_t* valmp_len,
+                           int32_t* valmp_idx, hipStream_t st);
 // Writes one stats row (host-known values and the per-length device counters;
 // `recomputed`: 0 none, 1 the recompute list (CNT_NFAIL), 2 the paper-mode list
 // (CNT_NREC)) and clears the per-length counters.
@@ -127,14 +142,15 @@ hipError_t launch_seed_append(const double* xs, const double* A, const double* i
 hipError_t launch_merge(const double* xs, const double* A, const double* invn, const double* sig, const uint8_t* flat,
                         const double* thr, const uint32_t* cnt, const int32_t* buf, int64_t cap, int64_t N, int L,
                         int p, int keep, double margin, int best_exact, int32_t* hc, double* hS, int32_t* hn,
-                        double* hbound, double* hsig, uint64_t* best, int32_t* fail, unsigned long long* nfail,
-                        int32_t* big, unsigned long long* nbig, unsigned long long* nappend, hipStream_t st);
+                        double* hbound, double* hsig, uint8_t* hflat, uint64_t* best, int32_t* fail,
+                        unsigned long long* nfail, int32_t* big, unsigned long long* nbig, unsigned long long* nappend,
+                        hipStream_t st);
 // lbm, min_dist, min_lb: optional (paper mode)
 hipError_t launch_sweep(const double* xs, const double* A, const double* invn, const double* sig, const uint8_t* flat,
                         int64_t N, int L, int64_t e, int p, int base, const int32_t* hc, double* hS, const int32_t* hn,
-                        const double* hbound, const double* hsig, uint64_t* best, int32_t* fail,
-                        unsigned long long* nfail, unsigned long long* nvalid, double* lbm,
-                        unsigned long long* min_dist, unsigned long long* min_lb, hipStream_t st);
+                        const double* hbound, const double* hsig, const unsigned long long* rflat, double margin,
+                        uint64_t* best, int32_t* fail, unsigned long long* nfail, unsigned long long* nvalid,
+                        double* lbm, unsigned long long* min_dist, unsigned long long* min_lb, hipStream_t st);
 hipError_t launch_split_fail(const int32_t* fail, const unsigned long long* nfail, int64_t max_listed,
                              const double* lbm, const unsigned long long* limit, int all_partial, int32_t* rec,
                              unsigned long long* nrec, int32_t* part, unsigned long long* npart, hipStream_t st);

@@ -47,8 +47,17 @@ __global__ void k_convert(const TIn* __restrict__ in, int64_t n, int64_t npad, d
 // F32: also the FP32 copies of df, dg and the inverse norms for the FP32 pass
 // (nearest rounding: their error is part of the item bound; a flat or padded
 // window, whose inverse norm is zero, gets NaN so that every correlation it
-// enters fails every threshold test), and per block of 64 windows the extrema
-// of sigma sqrt(L), |df| and |dg| that bound the FP32 rounding, rounded outward.
+// enters fails every threshold test). Per block of 64 windows, the extrema of
+// sigma sqrt(L), |df| and |dg| that bound the rounding of the recurrence in
+// either precision, rounded outward.
+//
+// With partial profiles at base b (hflat non-null): the largest ratio
+// sigma_b / sigma_L over the windows that were flat at b (never stored in a
+// partial profile) but are candidates at L goes to *rflat (bits of a
+// non-negative double): such a window c is at distance at least
+// sqrt(b) (sigma_{o,b} / sigma_{o,L} - sigma_{c,b} / sigma_{c,L}) from any owner o
+// (the base-length part of the distance, minimised over the offset, with the
+// correlation at b at most 1), which the sweep folds into its bound.
 template <bool F32>
 __global__ __launch_bounds__(256) void k_window_prep(
     const double* __restrict__ xs, int64_t N, int L, int first, double flat_eps, const double* __restrict__ A_in,
@@ -57,7 +66,8 @@ __global__ __launch_bounds__(256) void k_window_prep(
     unsigned long long* __restrict__ nflat, double* __restrict__ df, double* __restrict__ dg,
     float* __restrict__ sw32, float* __restrict__ df32, float* __restrict__ dg32, float* __restrict__ inv32,
     float* __restrict__ bsw_max, float* __restrict__ bsw_min, float* __restrict__ bdf_max,
-    float* __restrict__ bdg_max) {
+    float* __restrict__ bdg_max, float* __restrict__ bmu_max, const uint8_t* __restrict__ hflat,
+    const double* __restrict__ hsig, unsigned long long* __restrict__ rflat) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   // anchored sums of window w at this length
@@ -104,6 +114,12 @@ __global__ __launch_bounds__(256) void k_window_prep(
   }
   const unsigned long long fm = __ballot(fl);
   if (lane == 0 && fm) atomicAdd(nflat, (unsigned long long)__popcll(fm));
+  if (hflat) {
+    double r = 0.0;  // non-negative: its bit pattern orders like its value
+    if (live && !fl && hflat[i]) r = hsig[i] / s;
+    r = wave_max_f64(r);
+    if (lane == 0 && r > 0.0) atomicMax(rflat, (unsigned long long)__double_as_longlong(r));
+  }
   if (i >= N + kPad) return;
   mu[i] = live ? mval : 0.0;
   sig[i] = live ? s : 0.0;
@@ -122,10 +138,12 @@ __global__ __launch_bounds__(256) void k_window_prep(
     df32[i] = (float)f;
     dg32[i] = (float)g;
     inv32[i] = inv > 0.0 ? (float)inv : __int_as_float(0x7fc00000);
+  }
+  if (bsw_max) {
     // blocks of 64 windows are whole wavefronts (blockDim is a multiple of 64)
     const int64_t blk = i / kWave;
     if (blk * kWave < N) {
-      double smax = 0.0, smin = INFINITY, fmx = 0.0, gmx = 0.0;
+      double smax = 0.0, smin = INFINITY, fmx = 0.0, gmx = 0.0, mmx = 0.0;
       if (live) {
         if (inv > 0.0) {
           const double w = s * sqrt((double)L);
@@ -134,16 +152,20 @@ __global__ __launch_bounds__(256) void k_window_prep(
         }
         fmx = fabs(f);
         gmx = fabs(g);
+        mmx = fabs(mval);
+        if (lane == kWave - 1 && i + 1 < N) mmx = fmax(mmx, fabs(mnext));  // dg reads the next mean too
       }
       smax = wave_max_f64(smax);
       smin = wave_min_f64(smin);
       fmx = wave_max_f64(fmx);
       gmx = wave_max_f64(gmx);
+      mmx = wave_max_f64(mmx);
       if (lane == 0) {
         bsw_max[blk] = smax > 0.0 ? __double2float_ru(smax) : 0.0f;
         bsw_min[blk] = smin < INFINITY ? __double2float_rd(smin) : INFINITY;
         bdf_max[blk] = __double2float_ru(fmx);
         bdg_max[blk] = __double2float_ru(gmx);
+        bmu_max[blk] = __double2float_ru(mmx);
       }
     }
   }
@@ -210,7 +232,8 @@ constexpr int kFinG = 8;  // lanes per owner in k_finalize, each summing every k
 
 __global__ __launch_bounds__(128) void k_finalize(const double* __restrict__ xs, const double* __restrict__ mu,
                                                   const double* __restrict__ sig, const uint64_t* __restrict__ best,
-                                                  int64_t N, int64_t N0, int L, double* __restrict__ prof_dist,
+                                                  int64_t N, int64_t N0, int L, double* __restrict__ ring_dist,
+                                                  int32_t* __restrict__ ring_idx, double* __restrict__ prof_dist,
                                                   int32_t* __restrict__ prof_idx, double* __restrict__ valmp_norm,
                                                   double* __restrict__ valmp_dist, int32_t* __restrict__ valmp_len,
                                                   int32_t* __restrict__ valmp_idx) {
@@ -236,6 +259,8 @@ __global__ __launch_bounds__(128) void k_finalize(const double* __restrict__ xs,
   if (r != 0) return;
   if (o >= N) {
     if (o < N0) {  // the row's entries past N_L (no window of this length)
+      ring_dist[o] = INFINITY;
+      ring_idx[o] = -1;
       if (prof_dist) prof_dist[o] = INFINITY;
       if (prof_idx) prof_idx[o] = -1;
     }
@@ -243,6 +268,8 @@ __global__ __launch_bounds__(128) void k_finalize(const double* __restrict__ xs,
   }
   const double d = key != kEmptyKey ? sqrt(acc) : INFINITY;
   const int32_t c32 = (int32_t)c;
+  ring_dist[o] = d;
+  ring_idx[o] = c32;
   if (prof_dist) prof_dist[o] = d;
   if (prof_idx) prof_idx[o] = c32;
   if (valmp_norm) {
@@ -276,7 +303,7 @@ __global__ void k_record_stats(unsigned long long* __restrict__ cnt, int64_t* __
   }
   cnt[CNT_NFLAT] = cnt[CNT_EV_STEPS] = cnt[CNT_EV_HITS] = cnt[CNT_APPENDS] = 0;
   cnt[CNT_NFAIL] = cnt[CNT_VALID] = cnt[CNT_HARD] = cnt[CNT_BIG] = 0;
-  cnt[CNT_NREC] = cnt[CNT_NPART] = 0;
+  cnt[CNT_NREC] = cnt[CNT_NPART] = cnt[CNT_RFLAT] = 0;
 }
 
 __global__ void k_fill_counters(unsigned long long* __restrict__ p, int n, unsigned long long v) {
@@ -579,14 +606,18 @@ hipError_t launch_convert(const void* in, int dtype, int64_t n, int64_t npad, do
 
 hipError_t launch_window_prep(const WindowPrep& w, hipStream_t st) {
   const unsigned blocks = blocks_for(w.N + kPad, 256);
+  if (w.hflat && (!w.hsig || !w.rflat)) return hipErrorInvalidValue;
+  if (w.bsw_max && (!w.bsw_min || !w.bdf_max || !w.bdg_max || !w.bmu_max)) return hipErrorInvalidValue;
   if (w.df32)
     k_window_prep<true><<<blocks, 256, 0, st>>>(w.xs, w.N, w.L, w.first, w.flat_eps, w.A_in, w.B_in, w.A_out, w.B_out,
                                                 w.mu, w.sig, w.invn, w.flat, w.nflat, w.df, w.dg, w.sw32, w.df32,
-                                                w.dg32, w.inv32, w.bsw_max, w.bsw_min, w.bdf_max, w.bdg_max);
+                                                w.dg32, w.inv32, w.bsw_max, w.bsw_min, w.bdf_max, w.bdg_max,
+                                                w.bmu_max, w.hflat, w.hsig, w.rflat);
   else
     k_window_prep<false><<<blocks, 256, 0, st>>>(w.xs, w.N, w.L, w.first, w.flat_eps, w.A_in, w.B_in, w.A_out,
                                                  w.B_out, w.mu, w.sig, w.invn, w.flat, w.nflat, w.df, w.dg, w.sw32,
-                                                 nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+                                                 nullptr, nullptr, nullptr, w.bsw_max, w.bsw_min, w.bdf_max,
+                                                 w.bdg_max, w.bmu_max, w.hflat, w.hsig, w.rflat);
   return hipGetLastError();
 }
 
@@ -598,11 +629,13 @@ hipError_t launch_seed_mp(const double* xs, const double* mu, const double* invn
 }
 
 hipError_t launch_finalize(const double* xs, const double* mu, const double* sig, const uint64_t* best,
-                           int64_t N, int64_t N0, int L, double* prof_dist, int32_t* prof_idx, double* valmp_norm,
-                           double* valmp_dist, int32_t* valmp_len, int32_t* valmp_idx, hipStream_t st) {
+                           int64_t N, int64_t N0, int L, double* ring_dist, int32_t* ring_idx, double* prof_dist,
+                           int32_t* prof_idx, double* valmp_norm, double* valmp_dist, int32_t* valmp_len,
+                           int32_t* valmp_idx, hipStream_t st) {
+  if (!ring_dist || !ring_idx) return hipErrorInvalidValue;
   const int64_t n = N0 > N ? N0 : N;
-  k_finalize<<<blocks_for(n * kFinG, 128), 128, 0, st>>>(xs, mu, sig, best, N, N0, L, prof_dist, prof_idx,
-                                                         valmp_norm, valmp_dist, valmp_len, valmp_idx);
+  k_finalize<<<blocks_for(n * kFinG, 128), 128, 0, st>>>(xs, mu, sig, best, N, N0, L, ring_dist, ring_idx, prof_dist,
+                                                         prof_idx, valmp_norm, valmp_dist, valmp_len, valmp_idx);
   return hipGetLastError();
 }
 

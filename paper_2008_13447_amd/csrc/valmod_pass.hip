@@ -85,8 +85,8 @@ struct PassArgs {
   unsigned long long* events;  // [0] wave-steps that took the slow path, [1] queue entries
   const int32_t* items;        // optional list of work items (seg * bands + band); null: the whole grid
   const unsigned long long* nitems;  // number of listed items (device count; the grid may be larger)
-  const float* delta;          // FP32 recurrence: bound of |rho32 - rho| per work item (null: none)
-  float delta_max;             // FP32 recurrence: items with a larger bound are left to the FP64 kernel
+  const float* delta;          // bound of |rho computed - rho| per work item (null: none)
+  float delta_max;             // items with a larger bound are skipped (left to the FP64 kernel)
   int64_t anc_stride;  // anchor-table row length (diagonals per segment row)
   double* anc_next;    // optional: the item's anchors are moved on to length L + 1 in place
   int64_t bands;       // bands of the grid (decodes item ids)
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
   const int64_t i0 = seg * a.H;
   const int64_t rowEnd = N - d0;
   if (i0 >= rowEnd) goto next;
-  // FP32 recurrence: rigorous bound of the rounding of rho over this item
+  // rigorous bound of the rounding of rho over this item (collecting passes)
   T delta = (T)0;
   if (a.delta) {
     const float dl_ = a.delta[seg * a.bands + band];
@@ -358,14 +358,16 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
         any_pass = __builtin_expect(__any(dq[0] >= -delta), 0);
       } else {
         // FP64: per-cell comparisons (this form allocates registers better
-        // there); the FP64 recurrence carries no rounding bound (delta = 0)
+        // there) of rho + delta, the correlation raised by the item's rounding
+        // bound with one rounding (fma), so a cell whose exact correlation
+        // reaches a threshold always passes (delta = 0 in matrix-profile mode)
         bool pass = false;
 #pragma unroll
         for (int q = 0; q < K; ++q) {
           const int s = (q + u) % K;
           const T inv = s < u ? Qinv[s] : Pinv[s];
           const T th = s < u ? Qthr[s] : Pthr[s];
-          pass |= (C[q] * inv) * rinv[u] >= vmin(th, rthr[u]);
+          pass |= fma(C[q] * inv, rinv[u], delta) >= vmin(th, rthr[u]);
         }
         any_pass = __any(pass);
       }
@@ -407,13 +409,24 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
           const int s = (q + u) % K;
           const int64_t j = i + dl + q;
           const T inv = s < u ? Qinv[s] : Pinv[s];
-          const T th = (s < u ? Qthr[s] : Pthr[s]) - delta;  // lowered by the rounding bound
-          const T rho = (C[q] * inv) * rinv[u];
+          const T thc = s < u ? Qthr[s] : Pthr[s];
           // FP32: flat and padded windows have a NaN inverse norm, so rho is NaN
           // and fails both tests; FP64: zero inverse norms are tested
           const bool ok = sizeof(T) == 4 || (j < N && rinv[u] > (T)0 && inv > (T)0);
-          mask |= (ok && rho >= th) ? (1u << q) : 0u;
-          mask |= (ok && rho >= rthr[u] - delta) ? (1u << (K + q)) : 0u;
+          bool colp, rowp;
+          if constexpr (sizeof(T) == 4) {
+            // thresholds lowered by the rounding bound (the bound includes the
+            // rounding of these differences)
+            const T rho = (C[q] * inv) * rinv[u];
+            colp = rho >= thc - delta;
+            rowp = rho >= rthr[u] - delta;
+          } else {
+            const T rp = fma(C[q] * inv, rinv[u], delta);  // as in the filter
+            colp = rp >= thc;
+            rowp = rp >= rthr[u];
+          }
+          mask |= (ok && colp) ? (1u << q) : 0u;
+          mask |= (ok && rowp) ? (1u << (K + q)) : 0u;
         }
         if (qn + kWave > kQueue) flush();
         push(mask != 0, (int32_t)i, (uint64_t)((uint32_t)t | (mask << 6)));
@@ -459,59 +472,66 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
 }
 
 // --------------------------------------------------------------------------
-// Rounding bound of the FP32 recurrence per work item. With eps = 2^-24, a
-// segment of R rows, Phi = (max sw / min sw)_rows (max sw / min sw)_cols and
-// Psi = (max|df|_rows max|dg|_cols + max|dg|_rows max|df|_cols) / (min sw_rows min sw_cols)
-// over the item's windows (sw = sigma sqrt L, flat windows excluded), the
-// first-order error of rho = C / (sw_i sw_j) after r <= R steps is at most
-//   eps [(2R + 1) Phi + 4R Psi + 4]
-// (two rounded FMAs per step on |C| <= sw_i sw_j, rounded FP32 inputs, the
-// anchor conversion and the normalisation). The bound is doubled for the
-// second-order terms, and one FP32 ulp at magnitude 2..4 is added for the
-// rounding of the test's own threshold difference.
-__global__ void k_delta(const float* __restrict__ bsw_max, const float* __restrict__ bsw_min,
-                        const float* __restrict__ bdf_max, const float* __restrict__ bdg_max, int64_t nblk,
-                        int64_t segs, int64_t bands, int64_t H, int64_t dstart, int64_t BW, int64_t N,
-                        float delta_max, float* __restrict__ delta, int32_t* __restrict__ hard,
-                        unsigned long long* __restrict__ nhard) {
+// Rounding bounds of the recurrence per work item (recurrence_bound: H = the
+// segment height, Phi and Psi from the per-64-window extrema of sigma sqrt(L),
+// |df| and |dg| of the item's rows and columns, flat windows excluded). The
+// FP64 bound is always written; it widens the thresholds of the FP64 collecting
+// passes, so every candidate whose exact correlation reaches its owner's
+// threshold is collected. With delta32, also the FP32 bound (plus one ulp for
+// the filter's own difference), and the items whose FP32 bound exceeds the limit
+// are listed for the FP64 kernel.
+__global__ void k_item_bounds(const float* __restrict__ bsw_max, const float* __restrict__ bsw_min,
+                              const float* __restrict__ bdf_max, const float* __restrict__ bdg_max,
+                              const float* __restrict__ bmu_max, int64_t nblk,
+                              int64_t segs, int64_t bands, int64_t H, int64_t dstart, int64_t BW, int64_t N, int L,
+                              float delta_max, float* __restrict__ delta64, float* __restrict__ delta32,
+                              int32_t* __restrict__ hard, unsigned long long* __restrict__ nhard) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= segs * bands) return;
   const int64_t seg = id / bands, band = id % bands;
   const int64_t i0 = seg * H, d0 = dstart + band * BW;
+  auto none = [&]() {
+    delta64[id] = 0.0f;
+    if (delta32) delta32[id] = 0.0f;
+  };
   if (d0 > N - 1 || i0 >= N - d0) {
-    delta[id] = 0.0f;
+    none();
     return;
   }
-  auto range = [&](int64_t lo, int64_t hi, float& smax, float& smin, float& fmax_, float& gmax) {
+  auto range = [&](int64_t lo, int64_t hi, float& smax, float& smin, float& fmax_, float& gmax, float& mmax) {
     smax = 0.0f;
     smin = INFINITY;
     fmax_ = 0.0f;
     gmax = 0.0f;
+    mmax = 0.0f;
     const int64_t b0 = lo / 64, b1 = (hi - 1) / 64 < nblk - 1 ? (hi - 1) / 64 : nblk - 1;
     for (int64_t b = b0; b <= b1; ++b) {
       smax = fmaxf(smax, bsw_max[b]);
       smin = fminf(smin, bsw_min[b]);
       fmax_ = fmaxf(fmax_, bdf_max[b]);
       gmax = fmaxf(gmax, bdg_max[b]);
+      mmax = fmaxf(mmax, bmu_max[b]);
     }
   };
-  float rsx, rsn, rfx, rgx, csx, csn, cfx, cgx;
-  range(i0, i0 + H + 1, rsx, rsn, rfx, rgx);
-  range(i0 + d0, i0 + d0 + H + BW + 1, csx, csn, cfx, cgx);
+  float rsx, rsn, rfx, rgx, rmx, csx, csn, cfx, cgx, cmx;
+  range(i0, i0 + H + 1, rsx, rsn, rfx, rgx, rmx);
+  range(i0 + d0, i0 + d0 + H + BW + 1, csx, csn, cfx, cgx, cmx);
   if (!(rsn < INFINITY) || !(csn < INFINITY)) {
-    delta[id] = 0.0f;  // no non-flat window on one side: nothing can pass
+    none();  // no non-flat window on one side: nothing can pass
     return;
   }
   const double R = (double)H;
   const double phi = ((double)rsx / rsn) * ((double)csx / csn);
   const double psi = ((double)rfx * cgx + (double)rgx * cfx) / ((double)rsn * csn);
-  const double eps = 5.9604644775390625e-08;  // 2^-24
-  // + 2^-22: the rounding of the FP32 difference threshold - delta (|.| < 4)
-  const double d = 2.0 * eps * ((2.0 * R + 1.0) * phi + 4.0 * R * psi + 4.0) + 2.384185791015625e-07;
-  const float df_ = d < 1.0 ? (float)d * 1.0000002f : 1.0f;
-  delta[id] = df_;
-  // items whose bound exceeds the limit are listed for the FP64 kernel
-  if (df_ > delta_max) hard[atomicAdd(nhard, 1ull)] = (int32_t)id;
+  const double xi = ((double)rfx + cfx) * (double)fmaxf(rmx, cmx) / ((double)rsn * csn);
+  const double d64 = recurrence_bound(kEps64, R, phi, psi, xi, L);
+  delta64[id] = d64 < 4.0 ? __double2float_ru(d64) : 4.0f;
+  if (delta32) {
+    const double d = recurrence_bound(kEps32, R, phi, psi, xi, L) + kFilter32;
+    const float df_ = d < 1.0 ? __double2float_ru(d) : 1.0f;
+    delta32[id] = df_;
+    if (df_ > delta_max) hard[atomicAdd(nhard, 1ull)] = (int32_t)id;
+  }
 }
 
 PassGrid pass_grid(int64_t N, int64_t e, int64_t dstart, int K, int64_t H) {
@@ -611,15 +631,20 @@ hipError_t launch_pass(const PassLaunch& p, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_fp32_items(const float* bsw_max, const float* bsw_min, const float* bdf_max, const float* bdg_max,
-                             int64_t N, int64_t e, int64_t dstart, int K, int64_t H, float delta_max, float* delta,
-                             int32_t* hard, unsigned long long* nhard, hipStream_t st) {
+hipError_t launch_item_bounds(const float* bsw_max, const float* bsw_min, const float* bdf_max, const float* bdg_max,
+                              const float* bmu_max, int64_t N, int64_t e, int64_t dstart, int K, int64_t H, int L,
+                              float delta_max,
+                              float* delta64, float* delta32, int32_t* hard, unsigned long long* nhard,
+                              hipStream_t st) {
   const PassGrid g = pass_grid(N, e, dstart, K, H);
   const int64_t nitems = g.segs * g.bands;
   if (nitems == 0) return hipSuccess;
+  if (!delta64 || (delta32 && (!hard || !nhard))) return hipErrorInvalidValue;
   const int64_t nblk = (N + 63) / 64;
-  k_delta<<<blocks_for(nitems, 256), 256, 0, st>>>(bsw_max, bsw_min, bdf_max, bdg_max, nblk, g.segs, g.bands, H,
-                                                   dstart, (int64_t)kWave * K, N, delta_max, delta, hard, nhard);
+  k_item_bounds<<<blocks_for(nitems, 256), 256, 0, st>>>(bsw_max, bsw_min, bdf_max, bdg_max, bmu_max, nblk, g.segs,
+                                                         g.bands, H,
+                                                         dstart, (int64_t)kWave * K, N, L, delta_max, delta64, delta32,
+                                                         hard, nhard);
   return hipGetLastError();
 }
 

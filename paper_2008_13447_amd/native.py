@@ -32,7 +32,8 @@ STAT_NAMES = ["valid", "failed", "recomputed", "full_pass", "flat", "appends", "
 
 # (name, C type) of every function declared in include/valmod.h
 EXPORTS = ["valmod_plan", "valmod_workspace_bytes", "valmod_output_sizes", "valmod_series_layout",
-           "valmod_run", "valmod_autotune", "valmod_plan_free", "valmod_status_str", "valmod_last_pass_timing"]
+           "valmod_run", "valmod_run_status", "valmod_autotune", "valmod_plan_free", "valmod_status_str",
+           "valmod_last_pass_timing", "valmod_rounding_bound"]
 
 
 class ValmodConfig(ctypes.Structure):
@@ -111,6 +112,11 @@ def lib() -> ctypes.CDLL:
     L.valmod_series_layout.restype = ctypes.c_int
     L.valmod_run.argtypes = [P, P, P, ctypes.POINTER(ValmodOutputs), P]
     L.valmod_run.restype = ctypes.c_int
+    L.valmod_run_status.argtypes = [P, P]
+    L.valmod_run_status.restype = ctypes.c_int
+    L.valmod_rounding_bound.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double]
+    L.valmod_rounding_bound.restype = ctypes.c_double
     L.valmod_autotune.argtypes = [P, P, P, ctypes.POINTER(ValmodOutputs), P, ctypes.POINTER(ctypes.c_int32)]
     L.valmod_autotune.restype = ctypes.c_int
     L.valmod_plan_free.argtypes = [P]
@@ -186,8 +192,20 @@ def valmod_series_layout(plan: int, s: int) -> Dict[str, int]:
 
 def valmod_run(plan: int, series_ptr: int, workspace_ptr: int, outputs: ValmodOutputs,
                stream: Optional[int] = None) -> None:
+    """Enqueue a run (returns before it completes; see valmod_run_status)."""
     _check(lib().valmod_run(plan, series_ptr, workspace_ptr, ctypes.byref(outputs), stream),
            "valmod_run")
+
+
+def valmod_run_status(plan: int, stream: Optional[int] = None) -> None:
+    """Wait for the plan's last run and raise if it reported an error."""
+    _check(lib().valmod_run_status(plan, stream), "valmod_run_status")
+
+
+def valmod_rounding_bound(precision: str, H: int, L: int, phi: float, psi: float, xi: float) -> float:
+    """Rounding bound of the diagonal pass for one work item (host function)."""
+    return float(lib().valmod_rounding_bound(PRECISION[precision], int(H), int(L), float(phi), float(psi),
+                                             float(xi)))
 
 
 def valmod_autotune(plan: int, series_ptr: int, workspace_ptr: int, outputs: ValmodOutputs,
@@ -219,7 +237,8 @@ class Valmod:
                  k_motifs: int = 1, k_discords: int = 1, excl_den: int = 4, flat_eps: float = 0.0,
                  precision: str = "fp64", refresh_R: int = 0, path: str = "auto", lanes: int = 0,
                  graph: bool = False, mode: str = "exact", m_discords: int = 1, mset_radius: float = 0.0,
-                 mset_cap: int = 0):
+                 mset_cap: int = 0, skip: Sequence[str] = ()):
+        """skip: names of outputs passed as NULL (not written by the run)."""
         import torch
 
         if isinstance(series, torch.Tensor):
@@ -276,27 +295,39 @@ class Valmod:
             "mset_off": torch.empty(max(1, z["mset"]), dtype=i32, device=dev),
             "mset_dist": torch.empty(max(1, z["mset"]), dtype=f64, device=dev),
         }
-        self._outs = ValmodOutputs(*[self.out[f].data_ptr() for f in OUTPUT_FIELDS])
+        bad = set(skip) - set(OUTPUT_FIELDS)
+        if bad:
+            raise ValueError(f"unknown outputs {sorted(bad)}")
+        self.skip = set(skip)
+        for f in self.skip:
+            self.out[f] = None
+        self._outs = ValmodOutputs(*[None if self.out[f] is None else self.out[f].data_ptr()
+                                     for f in OUTPUT_FIELDS])
 
-    def run(self, stream=None) -> None:
+    def _stream_for(self, stream):
         torch = self.torch
         if stream is None and self.graph:
             # graph capture needs a stream other than the legacy default one
             if self._stream is None:
                 self._stream = torch.cuda.Stream(self.device)
             stream = self._stream
-        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return stream if stream is not None else torch.cuda.current_stream(self.device)
+
+    def run(self, stream=None, sync: bool = True) -> None:
+        """Enqueue one run; with sync (default) also wait for it and check its status."""
+        st = self._stream_for(stream)
         valmod_run(self.plan, self.series.data_ptr(), self.workspace.data_ptr(), self._outs,
                    st.cuda_stream)
+        if sync:
+            valmod_run_status(self.plan, st.cuda_stream)
+
+    def status(self, stream=None) -> None:
+        """Wait for the last enqueued run and raise if it reported an error."""
+        valmod_run_status(self.plan, self._stream_for(stream).cuda_stream)
 
     def autotune(self, stream=None):
         """Empirical pass geometry (see valmod_autotune); returns (H, K) of the tuned series."""
-        torch = self.torch
-        if stream is None and self.graph:
-            if self._stream is None:
-                self._stream = torch.cuda.Stream(self.device)
-            stream = self._stream
-        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = self._stream_for(stream)
         return valmod_autotune(self.plan, self.series.data_ptr(), self.workspace.data_ptr(), self._outs,
                                st.cuda_stream)
 
@@ -309,23 +340,27 @@ class Valmod:
         L = self.layouts[s]
         n0, nl = L["n0"], L["nlen"]
         km, kd = self.k_motifs, self.k_discords
-        o = {k: v.cpu().numpy() for k, v in self.out.items()}
+        o = {k: (v.cpu().numpy() if v is not None else None) for k, v in self.out.items()}
+
+        def sl(key, a, b, shape):  # a skipped output reads back as None
+            return None if o[key] is None else o[key][a:b].reshape(shape)
+
         out = dict(
-            prof_dist=o["prof_dist"][L["prof"]:L["prof"] + nl * n0].reshape(nl, n0),
-            prof_idx=o["prof_idx"][L["prof"]:L["prof"] + nl * n0].reshape(nl, n0),
-            valmp_norm=o["valmp_norm"][L["valmp"]:L["valmp"] + n0],
-            valmp_dist=o["valmp_dist"][L["valmp"]:L["valmp"] + n0],
-            valmp_len=o["valmp_len"][L["valmp"]:L["valmp"] + n0],
-            valmp_idx=o["valmp_idx"][L["valmp"]:L["valmp"] + n0],
-            motif_ab=o["motif_ab"][2 * L["motif"]:2 * (L["motif"] + nl * km)].reshape(nl, km, 2),
-            motif_d=o["motif_d"][L["motif"]:L["motif"] + nl * km].reshape(nl, km),
-            discord_on=o["discord_on"][2 * L["discord"]:2 * (L["discord"] + nl * kd)].reshape(nl, kd, 2),
-            discord_d=o["discord_d"][L["discord"]:L["discord"] + nl * kd].reshape(nl, kd),
-            g_motif_abl=o["g_motif_abl"][3 * L["g_motif"]:3 * (L["g_motif"] + km)].reshape(km, 3),
-            g_motif_d=o["g_motif_d"][2 * L["g_motif"]:2 * (L["g_motif"] + km)].reshape(km, 2),
-            g_discord_onl=o["g_discord_onl"][3 * L["g_discord"]:3 * (L["g_discord"] + kd)].reshape(kd, 3),
-            g_discord_d=o["g_discord_d"][2 * L["g_discord"]:2 * (L["g_discord"] + kd)].reshape(kd, 2),
-            stats=o["stats"][L["stats"]:L["stats"] + nl * NSTATS].reshape(nl, NSTATS),
+            prof_dist=sl("prof_dist", L["prof"], L["prof"] + nl * n0, (nl, n0)),
+            prof_idx=sl("prof_idx", L["prof"], L["prof"] + nl * n0, (nl, n0)),
+            valmp_norm=sl("valmp_norm", L["valmp"], L["valmp"] + n0, (n0,)),
+            valmp_dist=sl("valmp_dist", L["valmp"], L["valmp"] + n0, (n0,)),
+            valmp_len=sl("valmp_len", L["valmp"], L["valmp"] + n0, (n0,)),
+            valmp_idx=sl("valmp_idx", L["valmp"], L["valmp"] + n0, (n0,)),
+            motif_ab=sl("motif_ab", 2 * L["motif"], 2 * (L["motif"] + nl * km), (nl, km, 2)),
+            motif_d=sl("motif_d", L["motif"], L["motif"] + nl * km, (nl, km)),
+            discord_on=sl("discord_on", 2 * L["discord"], 2 * (L["discord"] + nl * kd), (nl, kd, 2)),
+            discord_d=sl("discord_d", L["discord"], L["discord"] + nl * kd, (nl, kd)),
+            g_motif_abl=sl("g_motif_abl", 3 * L["g_motif"], 3 * (L["g_motif"] + km), (km, 3)),
+            g_motif_d=sl("g_motif_d", 2 * L["g_motif"], 2 * (L["g_motif"] + km), (km, 2)),
+            g_discord_onl=sl("g_discord_onl", 3 * L["g_discord"], 3 * (L["g_discord"] + kd), (kd, 3)),
+            g_discord_d=sl("g_discord_d", 2 * L["g_discord"], 2 * (L["g_discord"] + kd), (kd, 2)),
+            stats=sl("stats", L["stats"], L["stats"] + nl * NSTATS, (nl, NSTATS)),
         )
         m = self.m_discords
         if m > 1:

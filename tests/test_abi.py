@@ -189,3 +189,38 @@ def test_pass_tiling_covers_upper_triangle_once():
         ii, jj = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
         want = (jj - ii > e).astype(np.int32)
         assert np.array_equal(cover, want)
+
+
+def test_run_and_status_argument_errors(lib):
+    """Argument errors come back synchronously, before any device work."""
+    import ctypes
+
+    assert lib.valmod_run_status(None, None) == -1
+    assert lib.valmod_run(None, None, None, None, None) == -1
+    cfg, keep = native.make_config([1000], [20], [30], p=5)
+    h = native.valmod_plan(cfg)
+    try:
+        outs = native.ValmodOutputs()
+        # null series or workspace, and an unaligned workspace
+        assert lib.valmod_run(h, None, ctypes.c_void_p(256), ctypes.byref(outs), None) == -1
+        assert lib.valmod_run(h, ctypes.c_void_p(256), None, ctypes.byref(outs), None) == -1
+        assert lib.valmod_run(h, ctypes.c_void_p(256), ctypes.c_void_p(257), ctypes.byref(outs), None) == -1
+        # no run enqueued yet: the status is OK
+        assert lib.valmod_run_status(h, None) == 0
+    finally:
+        native.valmod_plan_free(h)
+
+
+def test_workspace_holds_the_profile_ring(lib):
+    """The workspace keeps the last profile rows (at most 32 lengths) so the
+    per-length outputs can be skipped: it grows with min(nlen, 32) rows."""
+    def ws(hi):
+        cfg, keep = native.make_config([20000], [20], [hi], p=5)
+        h = native.valmod_plan(cfg)
+        b = native.valmod_workspace_bytes(h)
+        native.valmod_plan_free(h)
+        return b
+    w1, w8, w32, w64 = ws(20), ws(27), ws(51), ws(83)
+    assert w1 < w8 < w32
+    # beyond 32 lengths only the (small) per-length ranking stand-ins grow
+    assert w64 - w32 < 20000
