@@ -61,10 +61,14 @@ __global__ void k_anchor_grow(const double* __restrict__ xs, int64_t n, int L, i
 // The per-cell work is the two-FMA update and a test against both owners'
 // thresholds (correlation units): the cell can matter only if
 // rho = C invn_i invn_j >= min(thr_i, thr_j), with invn = 1 / (sigma sqrt L).
-// The FP32 pass reduces fma(C invn_j, invn_i, -min(thr_j, thr_i)) over the
-// lane's K cells with a max and compares it with minus the rounding bound of
-// the work item; the FP64 pass compares per cell. A step whose wavefront has a passing cell goes to a slow path that
-// evaluates rho and applies the mode's action:
+// The FP32 pass takes the largest C invn_j over the lane's K cells, scales it by
+// the row's inverse norm and raises it by the item's rounding bound (one fma),
+// and compares it with the lane's threshold: the minimum of the row's threshold
+// and those of the column slots the block has used (a superset of the cells that
+// pass per cell, at K multiplies and a max tree per step instead of K
+// multiplies, K minimums, K fmas and the max tree). The FP64 pass compares per
+// cell. A step whose wavefront has a passing cell goes to a slow path that
+// evaluates rho per cell and applies the mode's action:
 //   MODE_MP     : running best of each owner as a packed (distance, index) key
 //                 updated by 64-bit atomic min; thr = the running best's bound.
 //   MODE_APPEND : thr is a fixed per-owner threshold; every candidate with
@@ -328,6 +332,20 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
       rthr[u] = g_thr[ib + u];
     }
     const int64_t cn = ib + dl + 2 * K;  // first column entering during the next block
+    // FP32 filter threshold of the lane: the running minimum of the thresholds of
+    // the column slots the block has used so far (the current set at its start,
+    // then each column as it enters), taken with the step's row threshold
+    T tcol = (T)0;
+    if constexpr (sizeof(T) == 4) {
+      T m[K];
+#pragma unroll
+      for (int q = 0; q < K; ++q) m[q] = Pthr[q];
+#pragma unroll
+      for (int w = 1; w < K; w *= 2)
+#pragma unroll
+        for (int q = 0; q + w < K; q += 2 * w) m[q] = __builtin_elementwise_minimum(m[q], m[q + w]);
+      tcol = m[0];
+    }
     // Every block runs all K steps: rows past the segment or the series only meet
     // columns past the end (zero inverse norm, padded thresholds), so they never
     // produce a queue entry, and all their reads stay inside the zero padding.
@@ -343,19 +361,23 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
       // the max ignores the NaN of flat and padded windows.
       bool any_pass;
       if constexpr (sizeof(T) == 4) {
+        // the largest C invn_j over the lane's cells, scaled by the row's inverse
+        // norm and raised by the rounding bound with one rounding (fma), against
+        // the lane's threshold: a superset of the cells whose correlation reaches
+        // min(thr_i, thr_j) lowered by the bound; the slow path tests each cell
+        if (u > 0) tcol = __builtin_elementwise_minimum(tcol, Qthr[u - 1]);  // the column that entered
         T dq[K];
 #pragma unroll
         for (int q = 0; q < K; ++q) {
           const int s = (q + u) % K;
-          const T inv = s < u ? Qinv[s] : Pinv[s];
-          const T th = s < u ? Qthr[s] : Pthr[s];
-          dq[q] = fma(C[q] * inv, rinv[u], -__builtin_elementwise_minimum(th, rthr[u]));
+          dq[q] = C[q] * (s < u ? Qinv[s] : Pinv[s]);
         }
 #pragma unroll
         for (int w = 1; w < K; w *= 2)  // pairwise, to keep the dependency chain short
 #pragma unroll
           for (int q = 0; q + w < K; q += 2 * w) dq[q] = __builtin_fmaxf(dq[q], dq[q + w]);
-        any_pass = __builtin_expect(__any(dq[0] >= -delta), 0);
+        any_pass = __builtin_expect(
+            __any(fma(dq[0], rinv[u], delta) >= __builtin_elementwise_minimum(tcol, rthr[u])), 0);
       } else {
         // FP64: per-cell comparisons (this form allocates registers better
         // there) of rho + delta, the correlation raised by the item's rounding
