@@ -62,7 +62,8 @@ typedef enum {
   VALMOD_E_NOMEM = -3,     /* host allocation failed */
   VALMOD_E_HIP = -4,       /* a HIP runtime call failed */
   VALMOD_E_LAYOUT = -5,    /* sizes exceed the supported index range */
-  VALMOD_E_DEVICE = -6     /* error reported by a kernel (returned by valmod_run_status) */
+  VALMOD_E_DEVICE = -6,    /* error reported by a kernel (returned by valmod_run_status) */
+  VALMOD_E_SCRATCH = -7    /* valmod_run_noalloc: the plan's workspace exceeds its static scratch */
 } valmod_status;
 
 typedef enum { VALMOD_F32 = 0, VALMOD_F64 = 1 } valmod_dtype;
@@ -302,7 +303,28 @@ VALMOD_API valmod_status valmod_run(valmod_plan_t plan, const void* d_series, vo
                          const valmod_outputs* d_out, void* stream);
 
 /*
- * Wait for the last run enqueued by valmod_run on this plan (synchronising
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): valmod_run with the
+ * workspace in a static device array of VALMOD_NOALLOC_SCRATCH_BYTES (64 MiB)
+ * that the library holds on every GPU it runs on until the process ends. The
+ * caller still passes the input series and the outputs (NULL members skip their
+ * output, as for valmod_run). The call allocates nothing: no device or pinned
+ * memory, no streams or events; every lane's series run in turn on `stream`,
+ * with a full diagonal pass at every length (partial profiles take host
+ * decisions, so they are off; in exact mode the outputs are the same) and no
+ * pass timing. The call enqueues and returns; valmod_run_status waits and reads
+ * the device status word. All calls on one GPU share its array and it keeps the
+ * last call's contents (each run clears what it reads first), so calls that
+ * overlap on one GPU race: serialise them. Errors: VALMOD_E_SCRATCH when
+ * valmod_workspace_bytes(plan) exceeds the array, VALMOD_E_ARG (null arguments,
+ * paper mode, missing m-th discord or motif-set outputs), VALMOD_E_HIP.
+ */
+#define VALMOD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+VALMOD_API valmod_status valmod_run_noalloc(valmod_plan_t plan, const void* d_series, const valmod_outputs* d_out,
+                                            void* stream);
+
+/*
+ * Wait for the last run enqueued by valmod_run or valmod_run_noalloc on this plan (synchronising
  * `stream` first when it is not NULL) and return its status: VALMOD_OK,
  * VALMOD_E_DEVICE (the input held non-finite values; the device status word of a
  * lane was set) or VALMOD_E_HIP. Also makes valmod_last_pass_timing reflect that

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <math.h>
+#include <mutex>
 #include <new>
 #include <stdio.h>
 #include <stdlib.h>
@@ -91,6 +92,34 @@ PassGeom pass_geom(int64_t n, int32_t l_min, int32_t excl_den, bool fp32, int32_
 
 }  // namespace
 
+// --------------------------------------------------------------------------
+// Static scratch of valmod_run_noalloc: the workspace of a plan that needs at
+// most VALMOD_NOALLOC_SCRATCH_BYTES lives in this array instead of a caller
+// buffer. Every GPU the library runs on holds its own copy until the process
+// ends; its device address is taken once per device (with that device current)
+// and kept, since the array's name is only a host-side stand-in.
+static __device__ __align__(256) unsigned char scratch[VALMOD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// device address of `scratch` on device `dev`, which must be current
+hipError_t scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 // A lane runs its series one after another on its own stream; lanes run
 // concurrently.
 struct Lane {
@@ -128,6 +157,10 @@ struct valmod_plan_s {
   int64_t graph_cells = 0;
   hipEvent_t finished = nullptr;  // end of the last enqueued run (after its error-flag copies)
   bool run_pending = false;       // a run was enqueued and valmod_run_status has not read it yet
+  // the last run was valmod_run_noalloc's: its scratch address and stream
+  bool na_pending = false;
+  char* na_ws = nullptr;
+  hipStream_t na_stream = nullptr;
   valmod_status last_status = VALMOD_OK;
   // autotuned geometry: FP64 segment-height multiplier, FP32 refresh interval (0: default)
   int tune_hmul = 1;
@@ -147,6 +180,7 @@ extern "C" const char* valmod_status_str(int status) {
     case VALMOD_E_HIP: return "HIP runtime error";
     case VALMOD_E_LAYOUT: return "sizes exceed the supported index range";
     case VALMOD_E_DEVICE: return "device-side error (non-finite input or capacity exceeded)";
+    case VALMOD_E_SCRATCH: return "the plan's workspace exceeds the static scratch of valmod_run_noalloc";
     default: return "unknown status";
   }
 }
@@ -508,6 +542,8 @@ struct LaneRun {
   const valmod_outputs* o = nullptr;
   const char* d_series = nullptr;
   bool capture = false;
+  bool noalloc = false;     // valmod_run_noalloc: the caller's stream, no events, no partial profiles
+  hipStream_t run_st = nullptr;  // stream of the lane's work
   hipError_t err = hipSuccess;
   // workspace
   double *xs, *A, *B, *A2, *B2, *mu, *sig, *invn, *df, *dg, *thr, *anc, *hS, *hbound, *hsig, *lbm;
@@ -541,6 +577,7 @@ struct LaneRun {
     o = o_;
     d_series = series;
     capture = cap;
+    run_st = ln_->st;
     char* b = ws + ln->base;
     const WsLayout& w = ln->ws;
     xs = (double*)(b + w.xs);
@@ -633,7 +670,7 @@ struct LaneRun {
 
 LaneRun::Status LaneRun::advance() {
   if (err != hipSuccess || si >= ln->series.size()) return DONE;
-  hipStream_t st = ln->st;
+  hipStream_t st = run_st;
   const int s = ln->series[si];
   const valmod_layout& Ls = P->lay[s];
   const PassGeom& G = P->geom[s];
@@ -661,7 +698,7 @@ LaneRun::Status LaneRun::advance() {
     LCHECK(launch_valmp_init(N0, vnorm, vdist, vlen, vidx, st));
     // partial profiles are used unless every length is forced through a full pass
     // (the m-th discords keep exact top-m lists at every length instead)
-    heaps_on = P->cfg.path != VALMOD_PATH_FULL && Ls.l_max > Ls.l_min && P->cfg.m_discords == 1;
+    heaps_on = P->cfg.path != VALMOD_PATH_FULL && Ls.l_max > Ls.l_min && P->cfg.m_discords == 1 && !noalloc;
     base = 0;            // base length of the current partial profiles (0: none)
     probe_next = false;  // judge the partial profiles at the first length after a rebuild
     L = Ls.l_min;
@@ -783,7 +820,7 @@ LaneRun::Status LaneRun::advance() {
   // full-grid launch of the plan's own pass kernel, timed by events that the
   // launch records itself (kernel start and end)
   auto timed_pass = [&](const PassLaunch& q) -> hipError_t {
-    const bool tm = !capture && evi + 2 <= (int64_t)ln->ev.size();
+    const bool tm = !capture && !noalloc && evi + 2 <= (int64_t)ln->ev.size();
     PassLaunch qt = q;
     if (tm) {
       qt.ev_start = ln->ev[evi];
@@ -973,7 +1010,7 @@ LaneRun::Status LaneRun::advance() {
   LCHECK(launch_record_stats(cnt, o->stats ? o->stats + Ls.stats + t * VALMOD_NSTATS : nullptr, full ? 1 : 0,
                              nvalid, nswept_fail, paper_split == 1 ? 2 : (recompute ? 1 : 0), passes, st));
   // VALMOD_PROGRESS=k: one line on stderr every k lengths, once the length has run
-  const int progress = capture ? 0 : env_int("VALMOD_PROGRESS", 0);
+  const int progress = capture || noalloc ? 0 : env_int("VALMOD_PROGRESS", 0);
   if (progress > 0 && (t % progress == 0 || L == Ls.l_max)) {
     LCHECK(hipStreamSynchronize(st));
     fprintf(stderr, "valmod: series %d length %d (%lld of %lld) done, heaps %s\n", s, L, (long long)t + 1,
@@ -1094,6 +1131,7 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
   P->pass_launches = 0;
   P->pass_cells = 0;
   P->run_pending = false;
+  P->na_pending = false;
   if (e == hipSuccess && P->cfg.graph) {
     // one captured graph per set of buffers and stream, replayed on later calls
     const bool same = P->exec && P->key_series == d_series && P->key_ws == d_ws && P->key_stream == st &&
@@ -1136,6 +1174,26 @@ extern "C" valmod_status valmod_run(valmod_plan_t P, const void* d_series, void*
 
 extern "C" valmod_status valmod_run_status(valmod_plan_t P, void* stream_) {
   if (!P) return VALMOD_E_ARG;
+  if (P->na_pending) {
+    // a run of valmod_run_noalloc: its error flags sit in the static scratch
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) return VALMOD_E_HIP;
+    if (hipSetDevice(P->cfg.device) != hipSuccess) return VALMOD_E_HIP;
+    hipError_t e = hipStreamSynchronize(stream_ ? (hipStream_t)stream_ : P->na_stream);
+    valmod_status status = VALMOD_OK;
+    for (Lane& ln : P->lanes) {
+      unsigned long long flag = 0;
+      if (e == hipSuccess)
+        e = hipMemcpy(&flag, P->na_ws + ln.base + ln.ws.counters + CNT_ERR * 8, 8, hipMemcpyDeviceToHost);
+      if (e == hipSuccess && flag) status = VALMOD_E_DEVICE;
+    }
+    if (e != hipSuccess) status = VALMOD_E_HIP;
+    P->pass_ms = 0.0;  // no timing events in this mode
+    P->na_pending = false;
+    P->last_status = status;
+    (void)hipSetDevice(prev);
+    return status;
+  }
   if (!P->run_pending) return P->last_status;
   int prev_dev = -1;
   if (hipGetDevice(&prev_dev) != hipSuccess) return VALMOD_E_HIP;
@@ -1169,6 +1227,53 @@ extern "C" valmod_status valmod_run_status(valmod_plan_t P, void* stream_) {
   P->last_status = status;
   (void)hipSetDevice(prev_dev);
   return status;
+}
+
+// The run of valmod_run on the static scratch: every lane in turn on the
+// caller's stream, full diagonal pass at every length (no host decisions), no
+// lane streams, events or pinned memory, and no allocation of any kind.
+extern "C" valmod_status valmod_run_noalloc(valmod_plan_t P, const void* d_series, const valmod_outputs* o,
+                                            void* stream_) {
+  if (!P || !d_series || !o) return VALMOD_E_ARG;
+  if (P->ws_total > (size_t)VALMOD_NOALLOC_SCRATCH_BYTES) return VALMOD_E_SCRATCH;
+  if (P->cfg.mode == VALMOD_MODE_PAPER) return VALMOD_E_ARG;  // needs host decisions
+  if (P->cfg.m_discords > 1 && (!o->mdiscord_on || !o->mdiscord_d || !o->g_mdiscord_onl || !o->g_mdiscord_d))
+    return VALMOD_E_ARG;
+  if (P->cfg.mset_radius > 0.0 && (!o->mset_count || !o->mset_off || !o->mset_dist)) return VALMOD_E_ARG;
+  hipStream_t st = (hipStream_t)stream_;
+  int prev_dev = -1;
+  if (hipGetDevice(&prev_dev) != hipSuccess) return VALMOD_E_HIP;
+  if (hipSetDevice(P->cfg.device) != hipSuccess) return VALMOD_E_HIP;
+  void* ws = nullptr;
+  hipError_t e = scratch_address(P->cfg.device, &ws);
+  P->pass_ms = 0.0;
+  P->pass_launches = 0;
+  P->pass_cells = 0;
+  P->run_pending = false;
+  P->na_pending = false;
+  for (Lane& ln : P->lanes) {
+    if (e != hipSuccess) break;
+    LaneRun r;
+    r.init(P, &ln, (char*)ws, o, (const char*)d_series, false);
+    r.noalloc = true;
+    r.run_st = st;
+    e = launch_zero_counters((unsigned long long*)((char*)ws + ln.base + ln.ws.counters), CNT_WORDS, st);
+    // no partial profiles, so no length waits for device counters: a lane only
+    // continues or finishes
+    while (e == hipSuccess) {
+      const LaneRun::Status rs = r.advance();
+      if (rs == LaneRun::DONE) break;
+      if (rs == LaneRun::BLOCKED) e = hipErrorNotSupported;
+    }
+    if (e == hipSuccess) e = r.err;
+  }
+  if (e == hipSuccess) {
+    P->na_pending = true;
+    P->na_ws = (char*)ws;
+    P->na_stream = st;
+  }
+  (void)hipSetDevice(prev_dev);
+  return e == hipSuccess ? VALMOD_OK : VALMOD_E_HIP;
 }
 
 // Empirical choice of the pass geometry (FP64: segment height; FP32: refresh

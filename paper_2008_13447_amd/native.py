@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libvalmod.so")
 
 VALMOD_OK = 0
 STATUS = {0: "VALMOD_OK", -1: "VALMOD_E_ARG", -2: "VALMOD_E_TOO_SHORT", -3: "VALMOD_E_NOMEM",
-          -4: "VALMOD_E_HIP", -5: "VALMOD_E_LAYOUT", -6: "VALMOD_E_DEVICE"}
+          -4: "VALMOD_E_HIP", -5: "VALMOD_E_LAYOUT", -6: "VALMOD_E_DEVICE", -7: "VALMOD_E_SCRATCH"}
 DTYPE = {"f32": 0, "f64": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 MODE = {"exact": 0, "paper": 1}
@@ -32,7 +32,7 @@ STAT_NAMES = ["valid", "failed", "recomputed", "full_pass", "flat", "appends", "
 
 # (name, C type) of every function declared in include/valmod.h
 EXPORTS = ["valmod_plan", "valmod_workspace_bytes", "valmod_output_sizes", "valmod_series_layout",
-           "valmod_run", "valmod_run_status", "valmod_autotune", "valmod_plan_free", "valmod_status_str",
+           "valmod_run", "valmod_run_noalloc", "valmod_run_status", "valmod_autotune", "valmod_plan_free", "valmod_status_str",
            "valmod_last_pass_timing", "valmod_rounding_bound"]
 
 
@@ -112,6 +112,8 @@ def lib() -> ctypes.CDLL:
     L.valmod_series_layout.restype = ctypes.c_int
     L.valmod_run.argtypes = [P, P, P, ctypes.POINTER(ValmodOutputs), P]
     L.valmod_run.restype = ctypes.c_int
+    L.valmod_run_noalloc.argtypes = [P, P, ctypes.POINTER(ValmodOutputs), P]
+    L.valmod_run_noalloc.restype = ctypes.c_int
     L.valmod_run_status.argtypes = [P, P]
     L.valmod_run_status.restype = ctypes.c_int
     L.valmod_rounding_bound.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,

@@ -224,3 +224,21 @@ def test_workspace_holds_the_profile_ring(lib):
     assert w1 < w8 < w32
     # beyond 32 lengths only the (small) per-length ranking stand-ins grow
     assert w64 - w32 < 20000
+
+
+def test_noalloc_rejects_plans_beyond_its_scratch(lib):
+    """valmod_run_noalloc checks the plan's workspace against its static scratch
+    before any device work: a plan of more than 64 MiB gets VALMOD_E_SCRATCH."""
+    import ctypes
+
+    cfg, keep = native.make_config([65536], [100], [200], p=10, precision="fp32")
+    h = native.valmod_plan(cfg)
+    try:
+        assert native.valmod_workspace_bytes(h) > (64 << 20)
+        outs = native.ValmodOutputs()
+        rc = lib.valmod_run_noalloc(h, ctypes.c_void_p(256), ctypes.byref(outs), None)
+        assert rc == -7, rc
+        assert "static scratch" in native.status_str(rc)
+        assert lib.valmod_run_noalloc(None, None, None, None) == -1
+    finally:
+        native.valmod_plan_free(h)
