@@ -125,7 +125,7 @@ def main():
                     help="also grow the motif sets of the global top-k pairs with radius factor D")
     ap.add_argument("--mset-cap", type=int, default=1024, help="members stored per motif set")
     ap.add_argument("--path", default="auto", choices=["auto", "full", "recompute"])
-    ap.add_argument("--cpu-rows", type=int, default=512,
+    ap.add_argument("--cpu-rows", type=int, default=256,
                     help="oracle owners per length (at l_min, the middle length and l_max)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
