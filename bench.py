@@ -178,17 +178,17 @@ def main():
         tune = None
         if not args.no_autotune:
             t0 = time.perf_counter()
-            H, K = v.autotune()
-            tune = {"segment_rows": H, "diagonals_per_lane": K, "ms": (time.perf_counter() - t0) * 1e3}
+            H, K, p_used = v.autotune()
+            tune = {"segment_rows": H, "diagonals_per_lane": K, "p": p_used, "ms": (time.perf_counter() - t0) * 1e3}
             print(f"bench: {precision} autotune {tune}", file=sys.stderr, flush=True)
         for _ in range(warmup):
             v.run()
             print(f"bench: {precision} warm-up step done", file=sys.stderr, flush=True)
         torch.cuda.synchronize(dev)
         t0 = time.perf_counter()
-        for _ in range(steps):
-            v.run(sync=False)  # enqueued back to back; the status read below waits for the last one
-        v.status()
+        for k in range(steps):
+            v.run()  # waits for the step (a line per step; the wait costs microseconds against seconds)
+            print(f"bench: {precision} step {k + 1} of {steps} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize(dev)
         ms = (time.perf_counter() - t0) * 1e3 / steps
         print(f"bench: {precision} {ms:.1f} ms per step", file=sys.stderr, flush=True)

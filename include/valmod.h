@@ -334,18 +334,22 @@ VALMOD_API valmod_status valmod_run_noalloc(valmod_plan_t plan, const void* d_se
 VALMOD_API valmod_status valmod_run_status(valmod_plan_t plan, void* stream);
 
 /*
- * Autotuner: choose the diagonal-pass geometry empirically, on the series with
- * the most work. FP64 plans try segment heights of 1x, 2x and 4x the default;
- * FP32 plans without a fixed refresh_R try R = 256, 512 and 1024. Each candidate
- * runs the first three lengths of that series on the full path twice; the
- * second run is timed and the fastest candidate whose workspace fits in
- * valmod_workspace_bytes (as it was before the call) is kept. The plan's
- * workspace requirement can only shrink. Results do not depend on the choice
- * (exact mode). Arguments are those of valmod_run (same buffers; d_out may be
- * NULL: the tuning runs write no output). The call waits for its runs.
- * chosen (optional, host int32[2]): segment height and diagonals per lane of the
- * tuned series; zeros when there was nothing to tune (fixed refresh_R or
- * VALMOD_PASS_H set). Errors: those of valmod_run.
+ * Autotuner: choose the diagonal-pass geometry and the partial-profile size p
+ * empirically, on the series with the most work (the pass geometry of Alg.
+ * ComputeMatrixProfile's recurrence; p of Alg. ComputeMatrixProfile and Alg.
+ * ComputeSubMP). Stage 1: FP64 plans try segment heights of 1x, 2x and 4x the
+ * default; FP32 plans without a fixed refresh_R try R = 256, 512 and 1024 with 8
+ * and 4 diagonals per lane (4 only unless VALMOD_PASS_K32 fixes it); each
+ * candidate is timed on three lengths at the start and three at the end of the
+ * range on the full path. Stage 2 (exact mode with partial profiles): p, p/2 and
+ * p/4 are timed on the first four lengths with the plan's own path (the outputs
+ * do not depend on p in exact mode). Every measurement is the second of two runs,
+ * and the fastest candidate whose workspace fits in valmod_workspace_bytes (as it
+ * was before the call) is kept: the plan's workspace requirement can only shrink.
+ * Arguments are those of valmod_run (same buffers; d_out may be NULL: the tuning
+ * runs write no output). The call waits for its runs. chosen (optional, host
+ * int32[3]): segment height, diagonals per lane and p of the tuned series (the
+ * current ones when nothing was tuned). Errors: those of valmod_run.
  */
 VALMOD_API valmod_status valmod_autotune(valmod_plan_t plan, const void* d_series, void* d_workspace,
                                          const valmod_outputs* d_out, void* stream, int32_t* chosen);

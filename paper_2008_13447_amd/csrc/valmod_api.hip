@@ -50,11 +50,11 @@ int env_int(const char* name, int dflt) {
   return v && *v ? atoi(v) : dflt;
 }
 
-PassGeom pass_geom(int64_t n, int32_t l_min, int32_t excl_den, bool fp32, int32_t refresh_R, int hmul) {
+PassGeom pass_geom(int64_t n, int32_t l_min, int32_t excl_den, bool fp32, int32_t refresh_R, int hmul, int kdiag) {
   PassGeom g;
   const int64_t N0 = n - l_min + 1;
   const int64_t e0 = excl_zone(l_min, excl_den);
-  g.K = env_int(fp32 ? "VALMOD_PASS_K32" : "VALMOD_PASS_K", 8) == 4 ? 4 : 8;
+  g.K = kdiag == 4 || kdiag == 8 ? kdiag : (env_int(fp32 ? "VALMOD_PASS_K32" : "VALMOD_PASS_K", 8) == 4 ? 4 : 8);
   const int64_t bw = 64 * g.K;
   g.dstart = (e0 + 1) / 8 * 8;  // bands start on a multiple of 8 (aligned wide loads)
   g.bands = (N0 - g.dstart + bw - 1) / bw;
@@ -165,6 +165,7 @@ struct valmod_plan_s {
   // autotuned geometry: FP64 segment-height multiplier, FP32 refresh interval (0: default)
   int tune_hmul = 1;
   int32_t tune_R = 0;
+  int tune_K = 0;  // diagonals per lane (0: default)
   double pass_ms = 0.0;
   int64_t pass_launches = 0, pass_cells = 0;
 };
@@ -289,7 +290,7 @@ static void build_layout(valmod_plan_s* P) {
   const int32_t R = P->cfg.refresh_R > 0 ? P->cfg.refresh_R : P->tune_R;
   P->geom.clear();
   for (int s = 0; s < P->cfg.num_series; ++s)
-    P->geom.push_back(pass_geom(P->n[s], P->lmin[s], P->cfg.excl_den, fp32, R, P->tune_hmul));
+    P->geom.push_back(pass_geom(P->n[s], P->lmin[s], P->cfg.excl_den, fp32, R, P->tune_hmul, P->tune_K));
   size_t off = 0;
   for (Lane& ln : P->lanes) {
     ln.nmax = ln.n0max = ln.ancmax = ln.itemmax = ln.total_lengths = 0;
@@ -417,6 +418,9 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
   }
   const size_t pp = (size_t)P->cfg.p;
   P->cap = 8 * (int64_t)pp < 64 ? 64 : (8 * (int64_t)pp > 512 ? 512 : 8 * (int64_t)pp);
+  // test hook: a smaller list capacity makes owners overflow into the row recompute
+  const int cap_env = env_int("VALMOD_COLLECT_CAP", 0);
+  if (cap_env > 0) P->cap = cap_env < 512 ? cap_env : 512;
 
   // lanes: longest-processing-time assignment of the series by sum over lengths of N_L^2
   const int nl = std::min(S, P->cfg.lanes > 0 ? (int)P->cfg.lanes : 4);
@@ -717,6 +721,14 @@ LaneRun::Status LaneRun::advance() {
   const int64_t N = n - L + 1;
   const int64_t e = excl_zone(L, excl_den);
   const PassGrid grid = pass_grid(N, e, G.dstart, G.K, G.H);
+  // dense dot-product blocks (anchor table, row recompute) on FP64 matrix cores;
+  // VALMOD_MFMA=0 selects the VALU kernels
+  const bool use_mfma = env_int("VALMOD_MFMA", 1) != 0;
+  // exact rows of the listed owners (every eligible candidate), reduced into `best`
+  auto recompute_rows = [&](const int32_t* list, const unsigned long long* nlist) -> hipError_t {
+    return use_mfma ? launch_recompute_mfma(xs, A, invn, flat, list, nlist, N, N, L, e, best, st)
+                    : launch_recompute(xs, A, invn, flat, list, nlist, N, N, L, e, best, st);
+  };
   // this length's profile row in the ring (and in the outputs unless skipped)
   double* rd = ring_d + (t % ring_rows) * N0;
   int32_t* ri = ring_i + (t % ring_rows) * N0;
@@ -767,7 +779,12 @@ LaneRun::Status LaneRun::advance() {
     // the anchor table at L: formed at the first length, else moved on by one
     // term unless the last pass of the previous length did so
     if (G.table && anc_len != L) {
-      LCHECK(launch_anchor(xs, n, L, L == Ls.l_min, G.H, G.dstart, G.segs, G.stride, G.stride, anc, st));
+      // first length: the Hankel-block contraction on FP64 matrix cores; later
+      // lengths add one term per anchor
+      if (L == Ls.l_min && use_mfma)
+        LCHECK(launch_anchor_mfma(xs, n, L, G.H, G.dstart, G.segs, G.stride, G.stride, anc, st));
+      else
+        LCHECK(launch_anchor(xs, n, L, L == Ls.l_min, G.H, G.dstart, G.segs, G.stride, G.stride, anc, st));
       anc_len = L;
     }
     if (sweep) {
@@ -848,12 +865,14 @@ LaneRun::Status LaneRun::advance() {
   bool grow_collect = false;  // the collecting pass is the length's last and moves the anchor table on
   // collecting pass above per-owner thresholds from the candidates of `src`,
   // then the exact merge (top-`keep` partial profiles and best keys)
+  bool fail_reset = sweep;  // the sweep's recompute list, replaced by the first collecting pass
   auto collect = [&](const int32_t* src, int p_eff, int keep, int best_exact) -> hipError_t {
     // the wavefront-per-owner merge list is rebuilt by every collecting pass (a
     // length may run two); the recompute list keeps the owners listed so far at
-    // this length, except after a sweep, whose list the collecting pass replaces
+    // this length, except the sweep's, which the first collecting pass replaces
     hipError_t e1 = launch_zero_counters(&cnt[CNT_BIG], 1, st);
-    if (e1 == hipSuccess && sweep) e1 = launch_zero_counters(&cnt[CNT_NFAIL], 1, st);
+    if (e1 == hipSuccess && fail_reset) e1 = launch_zero_counters(&cnt[CNT_NFAIL], 1, st);
+    fail_reset = false;
     if (e1 == hipSuccess)
       e1 = launch_seed_append(xs, A, invn, flat, src, N, L, e, p_eff, p_eff == 1 ? 0 : D, margin, best_exact, thr,
                               fp32 ? thr32 : nullptr, acnt, fail, &cnt[CNT_NFAIL], st);
@@ -909,10 +928,15 @@ LaneRun::Status LaneRun::advance() {
     memcpy(&min_dist_abs, &bd, 8);
     memcpy(&min_lb_abs, &bl, 8);
     const double limit = (double)N * log((double)(p > 1 ? p : 2)) / log((double)(N > 2 ? N : 3));
+    // the published limit weighs an O(n log n) profile against the matrix profile;
+    // here a recomputed row costs N L multiply-adds against N^2 / 2 cells of a
+    // full pass, so a full pass is also taken when the rows would cost more
+    const double cells = 0.5 * (double)N * (double)N;
+    const bool rows_cheap = (double)nswept_fail * (double)N * (double)L <= rec_factor * cells;
     if (min_dist_abs < min_lb_abs) {
       full = false;
       paper_split = 2;
-    } else if ((double)nswept_fail < limit) {
+    } else if ((double)nswept_fail < limit && rows_cheap) {
       full = false;
       paper_split = 1;
     } else {
@@ -953,19 +977,20 @@ LaneRun::Status LaneRun::advance() {
       ++passes;
       LCHECK(launch_keys_to_idx(best, N, ri, st));
       src = ri;
-      if (rebuild) {
-        // exact neighbours first (a list of one threshold rarely overflows), so
-        // that the owners whose partial-profile list overflows keep them
-        grow_collect = false;
-        LCHECK(collect(src, 1, 0, 0));
-        LCHECK(launch_keys_to_idx(best, N, ri, st));
-        grow_collect = grow;
-      }
     }
     if (rebuild) {
-      // new partial profiles at base L (Alg. ComputeMatrixProfile); at the first
-      // length `best` already holds the exact neighbours
-      LCHECK(collect(src, p, p, L == Ls.l_min ? 1 : 0));
+      // exact neighbours first (a list of one threshold rarely overflows), so that
+      // the owners whose partial-profile list overflows keep them: on periodic
+      // series the p-th best seed is far below the p-th best candidate, and the
+      // lists of nearly all owners overflow
+      grow_collect = false;
+      LCHECK(collect(src, 1, 0, 0));
+      LCHECK(launch_keys_to_idx(best, N, ri, st));
+      src = ri;
+      grow_collect = grow;
+      // new partial profiles at base L (Alg. ComputeMatrixProfile); `best` already
+      // holds the exact neighbours
+      LCHECK(collect(src, p, p, 1));
       base = L;
       probe_next = true;
     } else if (md > 1) {
@@ -980,13 +1005,13 @@ LaneRun::Status LaneRun::advance() {
   if (paper_split) {
     LCHECK(launch_split_fail(fail, &cnt[CNT_NFAIL], N, lbm, &cnt[CNT_MINDIST], paper_split == 2 ? 1 : 0, rec,
                              &cnt[CNT_NREC], part, &cnt[CNT_NPART], st));
-    if (paper_split == 1) LCHECK(launch_recompute(xs, A, invn, flat, rec, &cnt[CNT_NREC], N, N, L, e, best, st));
+    if (paper_split == 1) LCHECK(recompute_rows(rec, &cnt[CNT_NREC]));
   }
   if (recompute && md > 1)
     LCHECK(launch_recompute_topm(xs, A, invn, flat, fail, &cnt[CNT_NFAIL], N, N, L, e, md, p, mkeys, hc, hS, hn, best,
                                  st));
   else if (recompute)
-    LCHECK(launch_recompute(xs, A, invn, flat, fail, &cnt[CNT_NFAIL], N, N, L, e, best, st));
+    LCHECK(recompute_rows(fail, &cnt[CNT_NFAIL]));
   LCHECK(launch_finalize(xs, mu, sig, best, N, N0, L, rd, ri, pd, pi, vnorm, vdist, vlen, vidx, st));
   if (md > 1) {
     const int kd = P->cfg.k_discords;
@@ -1276,11 +1301,15 @@ extern "C" valmod_status valmod_run_noalloc(valmod_plan_t P, const void* d_serie
   return e == hipSuccess ? VALMOD_OK : VALMOD_E_HIP;
 }
 
-// Empirical choice of the pass geometry (FP64: segment height; FP32: refresh
-// interval R) on the series with the most work: each candidate runs the first
-// lengths of that series through the full path twice, the second run is timed,
-// and the fastest candidate whose workspace fits is kept. Outputs of that series
-// are overwritten (the real run writes them again).
+// Empirical choice of the pass geometry and of p on the series with the most
+// work. Stage 1 (geometry: FP64 segment height, FP32 refresh interval, and
+// diagonals per lane) times each candidate on two slices of three lengths, at
+// the start and at the end of the length range, on the full path. Stage 2
+// (exact mode with partial profiles only) times p, p/2 and p/4 on the first four
+// lengths with the plan's own path: the outputs do not depend on p there, but the
+// cost of building the partial profiles and what they save do. Each measurement
+// is the second of two runs; the fastest candidate whose workspace fits is kept.
+// The tuning runs write no output.
 extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, void* d_ws, const valmod_outputs* o,
                                          void* stream, int32_t* chosen) {
   (void)o;  // the tuning runs skip every output
@@ -1296,71 +1325,120 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
       sbest = s;
     }
   }
-  std::vector<std::pair<int, int32_t>> cand;  // (hmul, R)
-  if (fp32) {
-    if (P->cfg.refresh_R <= 0)
-      for (int32_t R : {256, 512, 1024}) cand.push_back({1, R});
-  } else if (env_int("VALMOD_PASS_H", 0) == 0) {
-    for (int h : {1, 2, 4}) cand.push_back({h, 0});
-  }
-  if (cand.size() < 2) {
-    if (chosen) chosen[0] = chosen[1] = 0;
-    return VALMOD_OK;
-  }
   const valmod_layout& Ls = P->lay[sbest];
   const int esz = P->cfg.dtype == VALMOD_F32 ? 4 : 8;
-  const int32_t T = (int32_t)std::min<int64_t>(3, Ls.nlen);
-  // the tuning runs write no output (every output skipped)
+  const void* sub_series = (const char*)d_series + (size_t)Ls.series * esz;
   valmod_outputs so;
   memset(&so, 0, sizeof(so));
-  const void* sub_series = (const char*)d_series + (size_t)Ls.series * esz;
-  double best_ms = -1.0;
-  std::pair<int, int32_t> best = {P->tune_hmul, P->tune_R};
-  for (const auto& c : cand) {
+  struct Cand {
+    int hmul;
+    int32_t R;
+    int K;
+    int32_t p;
+  };
+  // time one candidate on lengths [lo, hi] of the tuned series (ms, -1 if it does not fit)
+  auto time_run = [&](const Cand& c, int32_t lo, int32_t hi, int32_t path, double* ms) -> valmod_status {
     valmod_config sc = P->cfg;
     const int64_t n1 = Ls.n;
-    const int32_t lo1 = Ls.l_min, hi1 = Ls.l_min + T - 1;
     sc.num_series = 1;
     sc.n = &n1;
-    sc.l_min = &lo1;
-    sc.l_max = &hi1;
-    sc.path = VALMOD_PATH_FULL;
+    sc.l_min = &lo;
+    sc.l_max = &hi;
+    sc.path = path;
     sc.lanes = 1;
     sc.graph = 0;
-    sc.refresh_R = c.second;
-    sc.m_discords = 1;  // the pass geometry alone is timed
+    sc.refresh_R = c.R;
+    sc.p = c.p;
+    sc.m_discords = 1;  // what is timed is the pass geometry and the partial profiles
     sc.mset_radius = 0.0;
+    sc.mode = VALMOD_MODE_EXACT;
     valmod_plan_t sub = nullptr;
     valmod_status st = valmod_plan(&sc, &sub);
     if (st != VALMOD_OK) return st;
-    sub->tune_hmul = c.first;
+    sub->tune_hmul = c.hmul;
+    sub->tune_K = c.K;
     build_layout(sub);
-    if (sub->ws_total > P->ws_total) {
-      valmod_plan_free(sub);
-      continue;
+    *ms = -1.0;
+    if (sub->ws_total <= P->ws_total) {
+      st = valmod_run(sub, sub_series, d_ws, &so, stream);
+      if (st == VALMOD_OK) st = valmod_run_status(sub, stream);
+      const auto t0 = std::chrono::steady_clock::now();
+      if (st == VALMOD_OK) st = valmod_run(sub, sub_series, d_ws, &so, stream);
+      if (st == VALMOD_OK) st = valmod_run_status(sub, stream);
+      *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
-    st = valmod_run(sub, sub_series, d_ws, &so, stream);
-    if (st == VALMOD_OK) st = valmod_run_status(sub, stream);
-    const auto t0 = std::chrono::steady_clock::now();
-    if (st == VALMOD_OK) st = valmod_run(sub, sub_series, d_ws, &so, stream);
-    if (st == VALMOD_OK) st = valmod_run_status(sub, stream);
-    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     valmod_plan_free(sub);
-    if (st != VALMOD_OK) return st;
-    if (best_ms < 0.0 || ms < best_ms) {
-      best_ms = ms;
-      best = c;
+    return st;
+  };
+  Cand best{P->tune_hmul, P->tune_R, P->tune_K, P->cfg.p};
+  // stage 1: pass geometry
+  std::vector<Cand> cand;
+  const bool k_fixed = env_int(fp32 ? "VALMOD_PASS_K32" : "VALMOD_PASS_K", 0) != 0;
+  if (fp32) {
+    if (P->cfg.refresh_R <= 0)
+      for (int32_t R : {256, 512, 1024})
+        for (int K : {8, 4})
+          if (K == 8 || !k_fixed) cand.push_back({1, R, k_fixed ? 0 : K, P->cfg.p});
+  } else if (env_int("VALMOD_PASS_H", 0) == 0) {
+    for (int h : {1, 2, 4}) cand.push_back({h, 0, 0, P->cfg.p});
+  }
+  const int32_t T = (int32_t)std::min<int64_t>(3, Ls.nlen);
+  const int32_t lo_a = Ls.l_min, lo_b = std::max<int32_t>(Ls.l_min, Ls.l_max - T + 1);
+  if (cand.size() >= 2) {
+    double best_ms = -1.0;
+    for (const Cand& c : cand) {
+      double ms_a = 0.0, ms_b = 0.0;
+      valmod_status st = time_run(c, lo_a, lo_a + T - 1, VALMOD_PATH_FULL, &ms_a);
+      if (st == VALMOD_OK && ms_a >= 0.0 && lo_b > lo_a) st = time_run(c, lo_b, lo_b + T - 1, VALMOD_PATH_FULL, &ms_b);
+      if (st != VALMOD_OK) return st;
+      if (ms_a < 0.0 || ms_b < 0.0) continue;  // does not fit the workspace
+      const double ms = ms_a + ms_b;
+      if (best_ms < 0.0 || ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
     }
   }
-  const int old_hmul = P->tune_hmul;
-  const int32_t old_R = P->tune_R;
+  // stage 2: p (exact mode with partial profiles)
+  const bool heaps = P->cfg.mode == VALMOD_MODE_EXACT && P->cfg.path != VALMOD_PATH_FULL && P->cfg.m_discords <= 1 &&
+                     !P->cfg.graph && Ls.nlen >= 2;
+  if (heaps) {
+    const int32_t T2 = (int32_t)std::min<int64_t>(4, Ls.nlen);
+    double best_ms = -1.0;
+    Cand keep = best;
+    std::vector<int32_t> pcs;
+    for (int32_t pc : {P->cfg.p, P->cfg.p / 2, P->cfg.p / 4})
+      if (pc >= 1 && std::find(pcs.begin(), pcs.end(), pc) == pcs.end()) pcs.push_back(pc);
+    for (int32_t pc : pcs) {
+      Cand c = keep;
+      c.p = pc;
+      double ms = 0.0;
+      const valmod_status st = time_run(c, Ls.l_min, Ls.l_min + T2 - 1, P->cfg.path, &ms);
+      if (st != VALMOD_OK) return st;
+      if (ms < 0.0) continue;
+      if (best_ms < 0.0 || ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+  }
+  const Cand old{P->tune_hmul, P->tune_R, P->tune_K, P->cfg.p};
+  const int64_t old_cap = P->cap;
   const size_t old_total = P->ws_total;
-  P->tune_hmul = best.first;
-  P->tune_R = best.second;
-  build_layout(P);
+  auto apply = [&](const Cand& c) {
+    P->tune_hmul = c.hmul;
+    P->tune_R = c.R;
+    P->tune_K = c.K;
+    P->cfg.p = c.p;
+    P->cap = 8 * (int64_t)c.p < 64 ? 64 : (8 * (int64_t)c.p > 512 ? 512 : 8 * (int64_t)c.p);
+    const int cap_env = env_int("VALMOD_COLLECT_CAP", 0);
+    if (cap_env > 0) P->cap = cap_env < 512 ? cap_env : 512;
+    build_layout(P);
+  };
+  apply(best);
   if (P->ws_total > old_total) {  // never needs more workspace than the caller holds
-    P->tune_hmul = old_hmul;
-    P->tune_R = old_R;
+    apply(old);
+    P->cap = old_cap;
     build_layout(P);
   }
   if (P->exec) {  // a captured run used the old geometry
@@ -1374,6 +1452,7 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
   if (chosen) {
     chosen[0] = (int32_t)P->geom[sbest].H;
     chosen[1] = P->geom[sbest].K;
+    chosen[2] = P->cfg.p;
   }
   return VALMOD_OK;
 }

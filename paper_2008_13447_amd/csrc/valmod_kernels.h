@@ -199,6 +199,13 @@ struct MotifSetLaunch {
 };
 size_t motif_sets_hist_words(int64_t cand_cap);
 hipError_t launch_motif_sets(const MotifSetLaunch& m, hipStream_t st);
+// Hankel-block contractions on FP64 MFMA (valmod_mfma.hip): the anchor table of
+// the first length, and the exact row recompute of the listed owners
+hipError_t launch_anchor_mfma(const double* xs, int64_t n, int L, int64_t H, int64_t dstart, int64_t segs,
+                              int64_t stride, int64_t ncols, double* anc, hipStream_t st);
+hipError_t launch_recompute_mfma(const double* xs, const double* A, const double* invn, const uint8_t* flat,
+                                 const int32_t* list, const unsigned long long* nlist, int64_t max_listed, int64_t N,
+                                 int L, int64_t e, uint64_t* best, hipStream_t st);
 // copies best keys into an int32 index array (-1 for empty keys)
 hipError_t launch_keys_to_idx(const uint64_t* best, int64_t N, int32_t* idx, hipStream_t st);
 

@@ -212,11 +212,11 @@ def valmod_rounding_bound(precision: str, H: int, L: int, phi: float, psi: float
 
 def valmod_autotune(plan: int, series_ptr: int, workspace_ptr: int, outputs: ValmodOutputs,
                     stream: Optional[int] = None):
-    """Returns (segment height, diagonals per lane) of the tuned series, or (0, 0)."""
-    chosen = (ctypes.c_int32 * 2)()
+    """Returns (segment height, diagonals per lane, p) of the tuned series."""
+    chosen = (ctypes.c_int32 * 3)()
     _check(lib().valmod_autotune(plan, series_ptr, workspace_ptr, ctypes.byref(outputs), stream, chosen),
            "valmod_autotune")
-    return int(chosen[0]), int(chosen[1])
+    return int(chosen[0]), int(chosen[1]), int(chosen[2])
 
 
 def valmod_plan_free(plan: int) -> None:
@@ -328,7 +328,7 @@ class Valmod:
         valmod_run_status(self.plan, self._stream_for(stream).cuda_stream)
 
     def autotune(self, stream=None):
-        """Empirical pass geometry (see valmod_autotune); returns (H, K) of the tuned series."""
+        """Empirical pass geometry and p (see valmod_autotune); returns (H, K, p) of the tuned series."""
         st = self._stream_for(stream)
         return valmod_autotune(self.plan, self.series.data_ptr(), self.workspace.data_ptr(), self._outs,
                                st.cuda_stream)
@@ -342,10 +342,9 @@ class Valmod:
         L = self.layouts[s]
         n0, nl = L["n0"], L["nlen"]
         km, kd = self.k_motifs, self.k_discords
-        o = {k: (v.cpu().numpy() if v is not None else None) for k, v in self.out.items()}
-
-        def sl(key, a, b, shape):  # a skipped output reads back as None
-            return None if o[key] is None else o[key][a:b].reshape(shape)
+        def sl(key, a, b, shape):  # only the series' slice is copied; a skipped output reads back as None
+            t = self.out[key]
+            return None if t is None else t[a:b].cpu().numpy().reshape(shape)
 
         out = dict(
             prof_dist=sl("prof_dist", L["prof"], L["prof"] + nl * n0, (nl, n0)),
@@ -367,16 +366,16 @@ class Valmod:
         m = self.m_discords
         if m > 1:
             a, g = L["mdiscord"], L["g_mdiscord"]
-            out["mdiscord_on"] = o["mdiscord_on"][2 * a:2 * (a + nl * m * kd)].reshape(nl, m, kd, 2)
-            out["mdiscord_d"] = o["mdiscord_d"][a:a + nl * m * kd].reshape(nl, m, kd)
-            out["g_mdiscord_onl"] = o["g_mdiscord_onl"][3 * g:3 * (g + m * kd)].reshape(m, kd, 3)
-            out["g_mdiscord_d"] = o["g_mdiscord_d"][2 * g:2 * (g + m * kd)].reshape(m, kd, 2)
+            out["mdiscord_on"] = sl("mdiscord_on", 2 * a, 2 * (a + nl * m * kd), (nl, m, kd, 2))
+            out["mdiscord_d"] = sl("mdiscord_d", a, a + nl * m * kd, (nl, m, kd))
+            out["g_mdiscord_onl"] = sl("g_mdiscord_onl", 3 * g, 3 * (g + m * kd), (m, kd, 3))
+            out["g_mdiscord_d"] = sl("g_mdiscord_d", 2 * g, 2 * (g + m * kd), (m, kd, 2))
         cap = self.mset_cap
         if cap:
             g, a = L["g_motif"], L["mset"]
-            out["mset_count"] = o["mset_count"][g:g + km]
-            out["mset_off"] = o["mset_off"][a:a + km * cap].reshape(km, cap)
-            out["mset_dist"] = o["mset_dist"][a:a + km * cap].reshape(km, cap)
+            out["mset_count"] = sl("mset_count", g, g + km, (km,))
+            out["mset_off"] = sl("mset_off", a, a + km * cap, (km, cap))
+            out["mset_dist"] = sl("mset_dist", a, a + km * cap, (km, cap))
         return out
 
     def close(self):

@@ -347,8 +347,8 @@ def _check_reported_pairs(x, g, l_min, tol, lengths):
 
 def test_config3_sensor_fp32_sampled_parity(oracle_mod):
     """n = 2^20 sensor-like series, lengths 256..384, p = 20, top-10, FP32 path:
-    sampled owners at three lengths (plus every reported motif and discord
-    endpoint) against the oracle, reported pairs re-evaluated."""
+    512 sampled owners at each of three lengths (plus every reported motif and
+    discord endpoint) against the oracle, reported pairs re-evaluated."""
     from oracle import compare
 
     w = gen.config3()
@@ -357,7 +357,7 @@ def test_config3_sensor_fp32_sampled_parity(oracle_mod):
     _say(f"config3 GPU done, stats sums {g['stats'].sum(axis=0).tolist()}")
     t = 320 - w.l_min
     extra = [int(v) for v in np.concatenate([g["motif_ab"][t].ravel(), g["discord_on"][t][:, 0]]) if v >= 0]
-    rep = compare.check_sampled(w.x, w.l_min, g, [256, 320, 384], 48, TOL64, extra=extra)
+    rep = compare.check_sampled(w.x, w.l_min, g, [256, 320, 384], 512, TOL64, extra=extra)
     _say(f"config3 sampled report {dict(rep)}")
     _check_reported_pairs(w.x, g, w.l_min, TOL64, [256, 320, 384])
 
@@ -483,9 +483,10 @@ def test_autotune_keeps_results_exact(oracle_mod, precision):
     lo, hi = 40, 48
     v = native.Valmod(torch.from_numpy(x).cuda(), lo, hi, p=5, k_motifs=3, k_discords=3, precision=precision)
     before = native.valmod_workspace_bytes(v.plan)
-    H, K = v.autotune()
+    H, K, p_used = v.autotune()
     assert native.valmod_workspace_bytes(v.plan) <= before
-    _say(f"autotune {precision}: H={H} K={K}")
+    _say(f"autotune {precision}: H={H} K={K} p={p_used}")
+    assert 1 <= p_used <= 5
     v.run()
     g = v.result(0)
     v.close()
