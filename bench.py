@@ -125,6 +125,8 @@ def main():
                     help="also grow the motif sets of the global top-k pairs with radius factor D")
     ap.add_argument("--mset-cap", type=int, default=1024, help="members stored per motif set")
     ap.add_argument("--path", default="auto", choices=["auto", "full", "recompute"])
+    ap.add_argument("--m-discords", type=int, default=1, metavar="M",
+                    help="also rank the Top-k M-th discords (M > 1; exact mode)")
     ap.add_argument("--cpu-rows", type=int, default=256,
                     help="oracle owners per length (at l_min, the middle length and l_max)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -174,7 +176,7 @@ def main():
         v = native.Valmod(x, lo, hi, p=w.p, k_motifs=km, k_discords=w.k_discords,
                           excl_den=w.excl_den, precision=precision, path="full" if graph else args.path,
                           lanes=args.lanes, graph=graph, mode=args.mode, mset_radius=args.mset,
-                          mset_cap=args.mset_cap)
+                          mset_cap=args.mset_cap, m_discords=args.m_discords)
         tune = None
         if not args.no_autotune:
             t0 = time.perf_counter()
@@ -210,7 +212,7 @@ def main():
                    "l_min": lo if batch is None else min(lo), "l_max": hi if batch is None else max(hi),
                    "p": w.p, "k": km, "precision": args.precision, "path": args.path,
                    "lanes": args.lanes, "graph": bool(args.graph and args.precision == "fp64"),
-                   "mode": args.mode, "mset_radius": args.mset},
+                   "mode": args.mode, "mset_radius": args.mset, "m_discords": args.m_discords},
         "roofline": {"bound": "alu", "kernel": f"k_pass<{'double' if args.precision == 'fp64' else 'float'}> "
                      "(diagonal pass)", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": profiled_traffic(args.precision, name),

@@ -125,7 +125,9 @@ typedef struct {
                                (VALMOD_PATH_RECOMPUTE is rejected); FP64 precision only */
   int32_t mode;             /* valmod_mode; VALMOD_MODE_PAPER needs VALMOD_PATH_AUTO and no graph */
   int32_t m_discords;       /* m of the Top-k m-th discords (0 or 1: only the 1st discords); m > 1 needs
-                               m <= 16, m <= p, exact mode and no graph, and the mdiscord outputs */
+                               m <= 16, m <= p, exact mode and no graph, and the mdiscord outputs.
+                               With partial profiles the m-lists follow Alg. Topkm_nextLength: certified
+                               from the profiles, pruned by the top-k cutoff, or recomputed */
   double mset_radius;       /* radius factor D of the motif sets (Sec. "Finding Motif Sets"): 0 = no
                                motif sets; else in (0, 1e6], and the mset outputs are required */
   int32_t mset_cap;         /* members stored per motif set, in [1, 2^20] when mset_radius > 0 (the
@@ -147,7 +149,13 @@ enum {
   VALMOD_STAT_FP64_ITEMS = 8, /* FP32 path: work items whose rounding bound sent them to the FP64 kernel */
   VALMOD_STAT_PASSES = 9,     /* diagonal-pass launches at this length */
   VALMOD_STAT_PARTIAL = 10,   /* paper mode: profile entries left uncomputed (index -2) */
-  VALMOD_NSTATS = 11
+  /* m-th discords with partial profiles (Alg. Topkm_nextLength), 0 at lengths that build
+     the m-lists with a full pass: */
+  VALMOD_STAT_MTH_CERTIFIED = 11,  /* windows whose m best matches the partial profile certifies */
+  VALMOD_STAT_MTH_RECOMPUTED = 12, /* windows whose m best matches a top-m row scan recomputes */
+  VALMOD_STAT_MTH_PRUNED = 13,     /* uncertified windows the top-k cutoff leaves out of the
+                                      m-th discord rankings (their best match stays exact) */
+  VALMOD_NSTATS = 14
 };
 
 /*

@@ -27,6 +27,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct WsLayout {
   size_t xs, A, B, A2, B2, mu, sig, invn, flat, df, dg, sw32, thr, thr32, best, counters, anc;
   size_t hc, hS, hn, hbound, hsig, hflat, acnt, abuf, fail, big, lbm, rec, part, mvals, mnn, mkeys;
+  size_t mstate, mub, mlist, tau_on, tau_d;
   size_t df32, dg32, inv32, bsw_max, bsw_min, bdf_max, bdg_max, bmu_max, delta64, delta, hard, fext, fthr;
   size_t ms_keys0, ms_keys1, ms_vals0, ms_vals1, ms_hist, ms_meta, ms_count, ms_taken, ms_bucket;
   // the last ring_rows profile rows (distance, index; stride N0 of the series):
@@ -230,6 +231,12 @@ static size_t layout_lane(const valmod_plan_s* P, Lane& ln) {
     w.mvals = take(md * wp * 8);
     w.mnn = take(md * wp * 4);
     w.mkeys = take(md * wp * 8);
+    const size_t kdd = (size_t)P->cfg.k_discords;
+    w.mstate = take(wp);
+    w.mub = take(md * wp * 8);
+    w.mlist = take(wp * 4);
+    w.tau_on = take(md * kdd * 2 * 4);
+    w.tau_d = take(md * kdd * 8);
   }
   if (P->cfg.mset_radius > 0.0) {
     const size_t cc = (size_t)P->cfg.k_motifs * (size_t)ln.n0max;
@@ -563,6 +570,9 @@ struct LaneRun {
   int32_t *hc, *hn, *abuf, *fail, *big, *hard, *rec, *part, *mnn;
   double* mvals;
   uint64_t* mkeys;
+  uint8_t* mstate;
+  double *mub, *tau_d;
+  int32_t *mlist, *tau_on;
   uint32_t* acnt;
   double* ring_d;
   int32_t* ring_i;
@@ -618,6 +628,11 @@ struct LaneRun {
     mvals = mth ? (double*)(b + w.mvals) : nullptr;
     mnn = mth ? (int32_t*)(b + w.mnn) : nullptr;
     mkeys = mth ? (uint64_t*)(b + w.mkeys) : nullptr;
+    mstate = mth ? (uint8_t*)(b + w.mstate) : nullptr;
+    mub = mth ? (double*)(b + w.mub) : nullptr;
+    mlist = mth ? (int32_t*)(b + w.mlist) : nullptr;
+    tau_on = mth ? (int32_t*)(b + w.tau_on) : nullptr;
+    tau_d = mth ? (double*)(b + w.tau_d) : nullptr;
     const bool paper = P->cfg.mode == VALMOD_MODE_PAPER;
     lbm = paper ? (double*)(b + w.lbm) : nullptr;
     rec = paper ? (int32_t*)(b + w.rec) : nullptr;
@@ -707,8 +722,7 @@ LaneRun::Status LaneRun::advance() {
     LCHECK(launch_convert(series, P->cfg.dtype, n, n + kPad, xs, (int*)&cnt[CNT_ERR], st));
     LCHECK(launch_valmp_init(N0, vnorm, vdist, vlen, vidx, st));
     // partial profiles are used unless every length is forced through a full pass
-    // (the m-th discords keep exact top-m lists at every length instead)
-    heaps_on = P->cfg.path != VALMOD_PATH_FULL && Ls.l_max > Ls.l_min && P->cfg.m_discords == 1 && !noalloc;
+    heaps_on = P->cfg.path != VALMOD_PATH_FULL && Ls.l_max > Ls.l_min && !noalloc;
     base = 0;            // base length of the current partial profiles (0: none)
     probe_next = false;  // judge the partial profiles at the first length after a rebuild
     L = Ls.l_min;
@@ -736,6 +750,41 @@ LaneRun::Status LaneRun::advance() {
   auto recompute_rows = [&](const int32_t* list, const unsigned long long* nlist) -> hipError_t {
     return use_mfma ? launch_recompute_mfma(xs, A, invn, flat, list, nlist, N, N, L, e, best, st)
                     : launch_recompute(xs, A, invn, flat, list, nlist, N, N, L, e, best, st);
+  };
+  // m-th discords from the partial profiles: each owner's m best stored
+  // candidates and whether the bound of the unstored ones certifies them
+  const int md = P->cfg.m_discords;
+  auto mth_select = [&](bool fresh) -> hipError_t {
+    MthSelect ms_{};
+    ms_.A = A;
+    ms_.invn = invn;
+    ms_.sig = sig;
+    ms_.flat = flat;
+    ms_.hc = hc;
+    ms_.hn = hn;
+    ms_.hS = hS;
+    ms_.hbound = hbound;
+    ms_.hsig = hsig;
+    ms_.rflat = &cnt[CNT_RFLAT];
+    ms_.thr = thr;
+    ms_.acnt = acnt;
+    ms_.cap = P->cap;
+    ms_.dmax = &cnt[CNT_DMAX];
+    ms_.fresh = fresh ? 1 : 0;
+    ms_.p = p;
+    ms_.m = md;
+    ms_.N = N;
+    ms_.N0 = N0;
+    ms_.L = L;
+    ms_.e = e;
+    ms_.base = base;
+    ms_.margin = margin;
+    ms_.vals = mvals;
+    ms_.nn = mnn;
+    ms_.ub = mub;
+    ms_.mstate = mstate;
+    ms_.n_open = &cnt[CNT_MOPEN];
+    return launch_mth_select(ms_, st);
   };
   // this length's profile row in the ring (and in the outputs unless skipped)
   double* rd = ring_d + (t % ring_rows) * N0;
@@ -807,8 +856,13 @@ LaneRun::Status LaneRun::advance() {
         err = hipErrorNotSupported;  // unreachable: a captured plan has no partial profiles
         return DONE;
       }
-      // NFAIL, VALID, HARD, BIG, MINDIST, MINLB
+      if (md > 1) {
+        LCHECK(launch_zero_counters(&cnt[CNT_MOPEN], 1, st));
+        LCHECK(mth_select(false));
+      }
+      // NFAIL, VALID, HARD, BIG, MINDIST, MINLB (and MOPEN)
       LCHECK(hipMemcpyAsync(ln->hcnt, &cnt[CNT_NFAIL], 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+      if (md > 1) LCHECK(hipMemcpyAsync(ln->hcnt + 6, &cnt[CNT_MOPEN], sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
       LCHECK(hipEventRecord(ln->ready, st));
       phase = 1;
       return BLOCKED;
@@ -926,6 +980,7 @@ LaneRun::Status LaneRun::advance() {
 
   int64_t nvalid = 0, nswept_fail = 0;
   bool full = true, rebuild = false;
+  int mth = 0;  // m-th discords from the partial profiles: 1 after a sweep, 2 after a rebuild
   int paper_split = 0;  // paper mode: 1 recompute the failing owners below minDistAbs, 2 leave all partial
   if (L == Ls.l_min) {
     rebuild = heaps_on;
@@ -958,12 +1013,16 @@ LaneRun::Status LaneRun::advance() {
   } else if (sweep) {
     nswept_fail = (int64_t)ln->hcnt[0];
     nvalid = (int64_t)ln->hcnt[1];
-    // row recompute of the failing windows vs one full pass (cost model in FMA-equivalents)
+    // row recompute of the failing windows vs one full pass (cost model in
+    // FMA-equivalents); with m-th discords at most m rows for every owner whose
+    // m-list is not certified
     const double cells = 0.5 * (double)N * (double)N;
-    const bool cheap = (double)nswept_fail * (double)N * (double)L <= rec_factor * cells;
+    const double rows = md > 1 ? (double)md * (double)ln->hcnt[6] : (double)nswept_fail;
+    const bool cheap = rows * (double)N * (double)L <= rec_factor * cells;
     if (P->cfg.path == VALMOD_PATH_RECOMPUTE || cheap) {
       full = false;
       recompute = nswept_fail > 0;
+      if (md > 1) mth = 1;
     } else if (probe_next && (double)nswept_fail > 0.25 * (double)N) {
       heaps_on = false;  // the bound fails right after a rebuild: partial profiles do not pay here
     } else {
@@ -971,7 +1030,6 @@ LaneRun::Status LaneRun::advance() {
     }
     probe_next = false;
   }
-  const int md = P->cfg.m_discords;
   if (full) {
     const int32_t* src = prev;
     // Every length's neighbours come from a collecting pass: the recurrence (in
@@ -1006,6 +1064,7 @@ LaneRun::Status LaneRun::advance() {
       LCHECK(collect(src, p, p, 1));
       base = L;
       probe_next = true;
+      if (md > 1) mth = 2;
     } else if (md > 1) {
       // exact top-m lists of every owner (Def. m-th best match)
       LCHECK(collect(src, md, md, 0));
@@ -1020,16 +1079,40 @@ LaneRun::Status LaneRun::advance() {
                              &cnt[CNT_NREC], part, &cnt[CNT_NPART], st));
     if (paper_split == 1) LCHECK(recompute_rows(rec, &cnt[CNT_NREC]));
   }
-  if (recompute && md > 1)
+  if (mth) {
+    // Alg. Topkm_nextLength: owners whose m-list the partial profiles certify
+    // enter the rankings as they are; the cutoff from their rankings (twice the
+    // exclusion zone) leaves out the uncertified owners that cannot reach the
+    // top k of any column, and the rest get a top-m row recompute. After a
+    // sweep, the best-match recompute list becomes the pruned owners whose best
+    // match the sweep did not certify.
+    const int kd = P->cfg.k_discords;
+    const bool fresh = mth == 2;
+    if (fresh) {
+      LCHECK(bounds_setup());
+      LCHECK(launch_max_delta(delta64, fp32 ? delta : nullptr, N, e, G.dstart, G.K, G.H, delta_max, &cnt[CNT_DMAX],
+                              st));
+      LCHECK(mth_select(true));
+    }
+    LCHECK(launch_mth_rankings(mvals, mnn, N0, n, L, md, excl_den, kd, tau_on, tau_d, st, 2));
+    if (!fresh) LCHECK(launch_zero_counters(&cnt[CNT_NFAIL], 1, st));
+    LCHECK(launch_mth_prune(mstate, mub, tau_d, N, N0, md, kd, fresh ? 1 : 0, mlist, &cnt[CNT_MREC], fail,
+                            &cnt[CNT_NFAIL], &cnt[CNT_MCERT], &cnt[CNT_MPRUNED], st));
+    LCHECK(launch_recompute_topm_keys(xs, A, invn, flat, mlist, &cnt[CNT_MREC], N, N, N0, L, e, md, mkeys, best,
+                                      mvals, mnn, st));
+    if (!fresh) recompute = true;
+    if (recompute) LCHECK(recompute_rows(fail, &cnt[CNT_NFAIL]));
+  } else if (recompute && md > 1) {
     LCHECK(launch_recompute_topm(xs, A, invn, flat, fail, &cnt[CNT_NFAIL], N, N, L, e, md, p, mkeys, hc, hS, hn, best,
                                  st));
-  else if (recompute)
+  } else if (recompute) {
     LCHECK(recompute_rows(fail, &cnt[CNT_NFAIL]));
+  }
   LCHECK(launch_finalize(xs, mu, sig, best, N, N0, L, rd, ri, pd, pi, vnorm, vdist, vlen, vidx, st));
   if (md > 1) {
     const int kd = P->cfg.k_discords;
     const int64_t at = Ls.mdiscord + t * md * kd;
-    LCHECK(launch_mth_values(A, invn, flat, hc, hS, hn, p, md, N, N0, L, mvals, mnn, st));
+    if (!mth) LCHECK(launch_mth_values(A, invn, flat, hc, hS, hn, p, md, N, N0, L, mvals, mnn, st));
     LCHECK(launch_mth_rankings(mvals, mnn, N0, n, L, md, excl_den, kd, o->mdiscord_on + 2 * at, o->mdiscord_d + at,
                                st));
   }

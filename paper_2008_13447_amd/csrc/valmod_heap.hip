@@ -224,13 +224,16 @@ __global__ __launch_bounds__(kWave) void k_merge_small(
     m = cnt[o];
     skip = flat[o] || thr[o] >= 2.0;  // not an owner, or already queued for recompute by the seeding
   }
-  const bool ok = live && !skip && m <= kSmallG && l < m;
+  // the list holds min(m, cap) entries: an owner with more (overflow) is not
+  // merged, and its entries past cap are not read (they are another owner's)
+  const bool merged = live && !skip && m >= 1 && m <= kSmallG && m <= cap;
+  const bool ok = merged && l < m;
   // the group's lanes share the candidates' sums: R = 8 / P lanes per candidate
   // (P = m rounded up to a power of two), each summing a chunk of the terms
   const int P = m <= 1 ? 1 : (m <= 2 ? 2 : (m <= 4 ? 4 : 8));
   const int R = kSmallG / P;
   double part = 0.0;
-  if (live && !skip && m >= 1 && m <= kSmallG) {
+  if (merged) {
     const int ci = l / R, r = l % R;
     if (ci < m) {
       const int kb = 1 + (int)((int64_t)(L - 1) * r / R), ke = 1 + (int)((int64_t)(L - 1) * (r + 1) / R);
@@ -351,6 +354,31 @@ __global__ __launch_bounds__(kWave) void k_merge_big(
   }
 }
 
+// Lower bound at L of the distance from owner o to every candidate its partial
+// profile (built at the base length b) does not hold (Eq. lowerBoundFinalFormula,
+// rescaled by sigma_{o,b} / sigma_{o,L} as in Alg. ComputeSubMP): +inf for a
+// complete profile, 0 for an owner without a profile. rf > 0: the largest
+// sigma_b / sigma_L of the windows flat at b (never stored) that are candidates
+// at L, which bounds those from below as well.
+__device__ __forceinline__ double unstored_bound(int64_t o, int base, const double* __restrict__ sig,
+                                                 const double* __restrict__ hbound, const double* __restrict__ hsig,
+                                                 double rf) {
+  if (!(hsig[o] > 0.0)) return 0.0;
+  const double ro = hsig[o] / sig[o];  // sigma_{o,b} / sigma_{o,L}
+  double lb;
+  if (hbound[o] < -2.5) {
+    lb = INFINITY;  // complete profile: no candidate was left out
+  } else {
+    const double q = hbound[o] > 0.0 ? (hbound[o] < 1.0 ? hbound[o] : 1.0) : 0.0;
+    lb = sqrt((double)base * (1.0 - q * q)) * ro;
+  }
+  if (rf > 0.0) {
+    const double lbf = sqrt((double)base) * (ro > rf ? ro - rf : 0.0);
+    lb = lbf < lb ? lbf : lb;
+  }
+  return lb;
+}
+
 // --------------------------------------------------------------------------
 // Per-length sweep (Alg. ComputeSubMP): grow every stored cross sum by one
 // term, take the exact minimum over the stored candidates still eligible at L,
@@ -396,21 +424,7 @@ __global__ void k_sweep(const double* __restrict__ xs, const double* __restrict_
         rb = rho;
       }
     }
-    if (hsig[o] > 0.0) {
-      const double ro = hsig[o] / sig[o];  // sigma_{o,b} / sigma_{o,L}
-      if (hbound[o] < -2.5) {
-        max_lb = INFINITY;  // complete profile: no candidate was left out
-      } else {
-        const double q = hbound[o] > 0.0 ? (hbound[o] < 1.0 ? hbound[o] : 1.0) : 0.0;
-        max_lb = sqrt((double)base * (1.0 - q * q)) * ro;
-      }
-      // windows flat at b (never stored) that are candidates at L
-      const double rf = __longlong_as_double((long long)*rflat);
-      if (rf > 0.0) {
-        const double lbf = sqrt((double)base) * (ro > rf ? ro - rf : 0.0);
-        max_lb = lbf < max_lb ? lbf : max_lb;
-      }
-    }
+    max_lb = unstored_bound(o, base, sig, hbound, hsig, __longlong_as_double((long long)*rflat));
     if (kb != kEmptyKey) {
       // the stored minimum from a correlation evaluated directly (error <= margin):
       // certified when even its largest possible exact distance is below the bound
@@ -612,6 +626,194 @@ __global__ void k_mth_values(const double* __restrict__ A, const double* __restr
     vals[(int64_t)j * N0 + o] = d;
     nn[(int64_t)j * N0 + o] = c;
   }
+}
+
+// --------------------------------------------------------------------------
+// Top-k m-th discords from the partial profiles (Alg. Topkm_nextLength).
+//
+// k_mth_select, one thread per owner at length L: the m best stored candidates in
+// key order (m rounds over the stored list) and whether they are the owner's
+// exact m best matches, i.e. the m-th one's largest possible distance lies below
+// the bound of the unstored candidates (a complete profile also certifies fewer
+// than m). Certified owners get their j-th best-match distances in vals / nn
+// (column j, stride N0). The others get no entry (nn = -1) and, in ub, upper
+// bounds of those distances: the j-th stored candidate's distance widened by two
+// correlation error margins (its stored sum, and a later direct evaluation), or
+// +inf. With `fresh` (the profiles were rebuilt at this length), an owner whose
+// collecting list overflowed has more than cap >= m candidates whose exact
+// correlation is at least its threshold lowered by twice the largest rounding
+// bound of the pass's work items (dmax) and one FP32 ulp, which bounds all its m
+// best-match distances. mstate: bit 0 the m-list is certified, bit 1 the best
+// match is (the rule of k_sweep), bit 2 an owner (a non-flat window).
+__global__ void k_mth_select(const double* __restrict__ A, const double* __restrict__ invn,
+                             const double* __restrict__ sig, const uint8_t* __restrict__ flat,
+                             const int32_t* __restrict__ hc, const double* __restrict__ hS,
+                             const int32_t* __restrict__ hn, const double* __restrict__ hbound,
+                             const double* __restrict__ hsig, const unsigned long long* __restrict__ rflat,
+                             const double* __restrict__ thr, const uint32_t* __restrict__ acnt, int64_t cap,
+                             const unsigned long long* __restrict__ dmax, int fresh, int p, int m, int64_t N,
+                             int64_t N0, int L, int64_t e, int base, double margin, double* __restrict__ vals,
+                             int32_t* __restrict__ nn, double* __restrict__ ub, uint8_t* __restrict__ mstate,
+                             unsigned long long* __restrict__ n_open) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = o < N;
+  const bool owner = live && !flat[o];
+  bool cert_m = false;
+  if (owner) {
+    const int nh = hn[o];
+    const double Ao = A[o], io = invn[o];
+    const double lb = unstored_bound(o, base, sig, hbound, hsig, fresh ? 0.0 : __longlong_as_double((long long)*rflat));
+    const double twoL = 2.0 * (double)L;
+    auto dist = [&](double u) { return sqrt(twoL * (u > 0.0 ? u : 0.0)); };
+    auto below = [&](double d) { return lb == INFINITY || d < lb * (1.0 - 1.0e-12); };
+    uint64_t prev = 0;
+    int cnt = 0;
+    bool cert_1 = false;
+    for (int j = 0; j < m; ++j) {
+      uint64_t kb = kEmptyKey;
+      double rb = -2.0;
+      for (int r = 0; r < nh; ++r) {
+        const int64_t c = hc[o * p + r];
+        if (c >= N || iabs64(c - o) <= e || flat[c]) continue;
+        const double rho = rho_from_sum(hS[o * p + r], Ao, A[c], L, io, invn[c]);
+        const uint64_t k = make_key(rho, c);
+        if (j > 0 && k <= prev) continue;
+        if (k < kb) {
+          kb = k;
+          rb = rho;
+        }
+      }
+      if (kb == kEmptyKey) break;
+      prev = kb;
+      cnt = j + 1;
+      vals[(int64_t)j * N0 + o] = dist(1.0 - rb);
+      nn[(int64_t)j * N0 + o] = (int32_t)key_cand(kb);
+      ub[(int64_t)j * N0 + o] = dist(1.0 - rb + 2.0 * margin);
+      const bool ok = below(dist(1.0 - rb + margin));
+      if (j == 0) cert_1 = ok;
+      if (j == m - 1) cert_m = ok;
+    }
+    if (cnt < m) cert_m = lb == INFINITY;  // a complete profile: the owner has no more candidates
+    double uo = INFINITY;                    // bound of the missing entries
+    if (fresh && nh == 0 && cap >= m && (int64_t)acnt[o] > cap && thr[o] >= -1.0) {
+      const double dm = (double)__uint_as_float((uint32_t)*dmax);
+      uo = dist(1.0 - thr[o] + 2.0 * dm + 0x1p-21 + margin);
+    }
+    for (int j = cnt; j < m; ++j) {
+      vals[(int64_t)j * N0 + o] = INFINITY;
+      nn[(int64_t)j * N0 + o] = -1;
+      ub[(int64_t)j * N0 + o] = uo;
+    }
+    if (!cert_m)
+      for (int j = 0; j < cnt; ++j) {  // no entry until the owner is resolved
+        vals[(int64_t)j * N0 + o] = INFINITY;
+        nn[(int64_t)j * N0 + o] = -1;
+      }
+    mstate[o] = (uint8_t)(4 | (cert_m ? 1 : 0) | (cert_1 ? 2 : 0));
+  } else if (live) {
+    for (int j = 0; j < m; ++j) {
+      vals[(int64_t)j * N0 + o] = INFINITY;
+      nn[(int64_t)j * N0 + o] = -1;
+    }
+    mstate[o] = 0;
+  }
+  count_wave(owner && !cert_m, n_open);
+}
+
+// After the certified owners' rankings with twice the exclusion zone: tau_j is
+// the distance of the k-th owner taken for column j. Those k owners are pairwise
+// more than 2e apart, so any window excludes at most one of them, and the
+// greedy ranking of all owners (exclusion e) takes k owners at distance >= tau_j
+// whatever the unresolved owners turn out to be. An unresolved owner whose upper
+// bounds lie below tau_j in every column is never examined before the k-th pick
+// of any column: its m-list is left out (pruned). The others are listed for the
+// top-m row recompute; with !best_exact, a pruned owner whose best match is not
+// certified goes to the best-match recompute list.
+__global__ void k_mth_prune(const uint8_t* __restrict__ mstate, const double* __restrict__ ub,
+                            const double* __restrict__ tau_d, int64_t N, int64_t N0, int m, int kd, int best_exact,
+                            int32_t* __restrict__ mlist, unsigned long long* __restrict__ nmlist,
+                            int32_t* __restrict__ fail, unsigned long long* __restrict__ nfail,
+                            unsigned long long* __restrict__ ncert, unsigned long long* __restrict__ npruned) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint8_t st = o < N ? mstate[o] : 0;
+  const bool open = (st & 4) && !(st & 1);
+  bool need = false;
+  if (open) {
+    for (int j = 0; j < m && !need; ++j) {
+      const double t = tau_d[(int64_t)j * kd + kd - 1];
+      need = !(t == t) || !(ub[(int64_t)j * N0 + o] * (1.0 + 1.0e-12) < t);
+    }
+  }
+  count_wave((st & 4) && (st & 1), ncert);
+  count_wave(open && !need, npruned);
+  push_fail_wave(open && need, mlist, nmlist, o);
+  push_fail_wave(open && !need && !best_exact && !(st & 2), fail, nfail, o);
+}
+
+// exact j-th best-match distances of the recomputed owners (direct FP64 sums)
+__global__ void k_mth_fill(const double* __restrict__ xs, const double* __restrict__ A,
+                           const double* __restrict__ invn, const int32_t* __restrict__ list,
+                           const unsigned long long* __restrict__ nlist, const uint64_t* __restrict__ keys, int m,
+                           int64_t N0, int L, double* __restrict__ vals, int32_t* __restrict__ nn) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= (int64_t)*nlist) return;
+  const int64_t o = list[w];
+  for (int j = 0; j < m; ++j) {
+    const uint64_t k = keys[o * m + j];
+    double d = INFINITY;
+    int32_t c = -1;
+    if (k != kEmptyKey) {
+      c = (int32_t)key_cand(k);
+      const double rho = rho_from_sum(cross_sum(xs, L, o, c), A[o], A[c], L, invn[o], invn[c]);
+      const double u = 1.0 - rho;
+      d = sqrt(2.0 * (double)L * (u > 0.0 ? u : 0.0));
+    }
+    vals[(int64_t)j * N0 + o] = d;
+    nn[(int64_t)j * N0 + o] = c;
+  }
+}
+
+// the best key of every recomputed owner (its first of m)
+__global__ void k_topm_best(const int32_t* __restrict__ list, const unsigned long long* __restrict__ nlist, int m,
+                            const uint64_t* __restrict__ keys, uint64_t* __restrict__ best) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= (int64_t)*nlist) return;
+  const int64_t o = list[w];
+  best[o] = keys[o * m];
+}
+
+hipError_t launch_mth_select(const MthSelect& a, hipStream_t st) {
+  if (a.N <= 0) return hipSuccess;
+  if (a.m < 1 || a.m > a.p) return hipErrorInvalidValue;
+  k_mth_select<<<blocks_for(a.N, 128), 128, 0, st>>>(a.A, a.invn, a.sig, a.flat, a.hc, a.hS, a.hn, a.hbound, a.hsig,
+                                                     a.rflat, a.thr, a.acnt, a.cap, a.dmax, a.fresh, a.p, a.m, a.N,
+                                                     a.N0, a.L, a.e, a.base, a.margin, a.vals, a.nn, a.ub, a.mstate,
+                                                     a.n_open);
+  return hipGetLastError();
+}
+
+hipError_t launch_mth_prune(const uint8_t* mstate, const double* ub, const double* tau_d, int64_t N, int64_t N0,
+                            int m, int kd, int best_exact, int32_t* mlist, unsigned long long* nmlist, int32_t* fail,
+                            unsigned long long* nfail, unsigned long long* ncert, unsigned long long* npruned,
+                            hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  k_mth_prune<<<blocks_for(N, 256), 256, 0, st>>>(mstate, ub, tau_d, N, N0, m, kd, best_exact, mlist, nmlist, fail,
+                                                  nfail, ncert, npruned);
+  return hipGetLastError();
+}
+
+hipError_t launch_recompute_topm_keys(const double* xs, const double* A, const double* invn, const uint8_t* flat,
+                                      const int32_t* list, const unsigned long long* nlist, int64_t max_listed,
+                                      int64_t N, int64_t N0, int L, int64_t e, int m, uint64_t* keys, uint64_t* best,
+                                      double* vals, int32_t* nn, hipStream_t st) {
+  if (max_listed <= 0 || N <= 0) return hipSuccess;
+  k_clear_keys<<<blocks_for(max_listed, 256), 256, 0, st>>>(list, nlist, m, keys);
+  const dim3 grid(blocks_for(N, kWave * kRecK), (unsigned)(max_listed < 32 ? max_listed : 32));
+  for (int j = 0; j < m; ++j)
+    k_recompute_round<<<grid, kWave, 0, st>>>(xs, A, invn, flat, list, nlist, N, L, e, m, j, keys);
+  k_topm_best<<<blocks_for(max_listed, 256), 256, 0, st>>>(list, nlist, m, keys, best);
+  k_mth_fill<<<blocks_for(max_listed, 128), 128, 0, st>>>(xs, A, invn, list, nlist, keys, m, N0, L, vals, nn);
+  return hipGetLastError();
 }
 
 hipError_t launch_recompute_topm(const double* xs, const double* A, const double* invn, const uint8_t* flat,

@@ -25,6 +25,11 @@ enum CounterSlot {
   CNT_NREC = 11,     // paper mode: owners listed for the row recompute
   CNT_NPART = 12,    // paper mode: owners left partial
   CNT_RFLAT = 13,    // largest sigma_b / sigma_L of the windows flat at the base length but not at L (bits of a double)
+  CNT_MOPEN = 14,    // m-th discords: owners whose m-list the partial profiles do not certify
+  CNT_DMAX = 15,     // largest rounding bound of the work items of the length's collecting passes (float bits)
+  CNT_MREC = 16,     // m-th discords: owners listed for the top-m row recompute
+  CNT_MCERT = 17,    // m-th discords: owners whose m-list the partial profiles certify
+  CNT_MPRUNED = 18,  // m-th discords: uncertified owners left out by the top-k cutoff
   CNT_WORDS = 32
 };
 
@@ -180,8 +185,49 @@ hipError_t launch_recompute_topm(const double* xs, const double* A, const double
 hipError_t launch_mth_values(const double* A, const double* invn, const uint8_t* flat, const int32_t* hc,
                              const double* hS, const int32_t* hn, int p, int m, int64_t N, int64_t N0, int L,
                              double* vals, int32_t* nn, hipStream_t st);
+// emul: the exclusion zone is emul times the zone of length L (2 gives the
+// pruning cutoff of the m-th discords)
 hipError_t launch_mth_rankings(const double* vals, const int32_t* nn, int64_t N0, int64_t n, int L, int m,
-                               int excl_den, int kd, int32_t* on, double* d, hipStream_t st);
+                               int excl_den, int kd, int32_t* on, double* d, hipStream_t st, int emul = 1);
+// m-th discords from the partial profiles (Alg. Topkm_nextLength): selection and
+// certification of every owner's m best stored candidates, the pruning cutoff,
+// and the top-m row recompute of the owners it cannot exclude
+struct MthSelect {
+  const double *A, *invn, *sig;
+  const uint8_t* flat;
+  const int32_t *hc, *hn;
+  const double *hS, *hbound, *hsig;
+  const unsigned long long* rflat;  // CNT_RFLAT (read unless fresh)
+  const double* thr;                // collecting thresholds (read when fresh)
+  const uint32_t* acnt;             // collected candidates per owner (read when fresh)
+  int64_t cap;
+  const unsigned long long* dmax;   // CNT_DMAX (read when fresh)
+  int fresh;                        // the partial profiles were rebuilt at this length
+  int p, m;
+  int64_t N, N0;
+  int L;
+  int64_t e;
+  int base;
+  double margin;
+  double* vals;  // j-th best-match distances, column j at j * N0
+  int32_t* nn;
+  double* ub;    // upper bounds of the uncertified owners' distances (same layout)
+  uint8_t* mstate;
+  unsigned long long* n_open;
+};
+hipError_t launch_mth_select(const MthSelect& a, hipStream_t st);
+// largest rounding bound of the work items of the length's collecting passes
+// (after launch_item_bounds), atomically maxed into `out` (float bits)
+hipError_t launch_max_delta(const float* delta64, const float* delta32, int64_t N, int64_t e, int64_t dstart, int K,
+                            int64_t H, float dlim, unsigned long long* out, hipStream_t st);
+hipError_t launch_mth_prune(const uint8_t* mstate, const double* ub, const double* tau_d, int64_t N, int64_t N0,
+                            int m, int kd, int best_exact, int32_t* mlist, unsigned long long* nmlist, int32_t* fail,
+                            unsigned long long* nfail, unsigned long long* ncert, unsigned long long* npruned,
+                            hipStream_t st);
+hipError_t launch_recompute_topm_keys(const double* xs, const double* A, const double* invn, const uint8_t* flat,
+                                      const int32_t* list, const unsigned long long* nlist, int64_t max_listed,
+                                      int64_t N, int64_t N0, int L, int64_t e, int m, uint64_t* keys, uint64_t* best,
+                                      double* vals, int32_t* nn, hipStream_t st);
 hipError_t launch_mth_global(const int32_t* on, const double* d, int nlen, int l_min, int m, int kd,
                              int32_t* g_onl, double* g_d, hipStream_t st);
 // motif sets grown from the global top-k motif pairs of one series (valmod_sets.hip)

@@ -300,10 +300,14 @@ __global__ void k_record_stats(unsigned long long* __restrict__ cnt, int64_t* __
     row[8] = (int64_t)cnt[CNT_HARD];
     row[9] = passes;
     row[10] = (int64_t)cnt[CNT_NPART];
+    row[11] = (int64_t)cnt[CNT_MCERT];
+    row[12] = (int64_t)cnt[CNT_MREC];
+    row[13] = (int64_t)cnt[CNT_MPRUNED];
   }
   cnt[CNT_NFLAT] = cnt[CNT_EV_STEPS] = cnt[CNT_EV_HITS] = cnt[CNT_APPENDS] = 0;
   cnt[CNT_NFAIL] = cnt[CNT_VALID] = cnt[CNT_HARD] = cnt[CNT_BIG] = 0;
   cnt[CNT_NREC] = cnt[CNT_NPART] = cnt[CNT_RFLAT] = 0;
+  cnt[CNT_MOPEN] = cnt[CNT_DMAX] = cnt[CNT_MREC] = cnt[CNT_MCERT] = cnt[CNT_MPRUNED] = 0;
 }
 
 __global__ void k_fill_counters(unsigned long long* __restrict__ p, int n, unsigned long long v) {
@@ -458,13 +462,13 @@ __device__ __forceinline__ bool discord_less(const DiscordKey& u, const DiscordK
 __global__ __launch_bounds__(kRankThreads) void k_topk_discords(
     const double* __restrict__ prof_dist, const int32_t* __restrict__ prof_idx, int64_t N0,
     int64_t n, int l_min, int lstep, int excl_den, int k, int32_t* __restrict__ discord_on,
-    double* __restrict__ discord_d) {
+    double* __restrict__ discord_d, int emul = 1) {
   __shared__ DiscordKey sh[kRankThreads];
   __shared__ int32_t acc_i[kMaxK];
   const int tl = blockIdx.x;
   const int L = l_min + tl * lstep;
   const int64_t N = n - L + 1;
-  const int64_t e = excl_zone(L, excl_den);
+  const int64_t e = emul * excl_zone(L, excl_den);
   const double* dist = prof_dist + (int64_t)tl * N0;
   const int32_t* idx = prof_idx + (int64_t)tl * N0;
   int got = 0;
@@ -685,9 +689,9 @@ hipError_t launch_rankings(const double* prof_dist, const int32_t* prof_idx, int
 
 // m-th discords of one length: columns j = 0..m-1 of vals / nn (stride N0)
 hipError_t launch_mth_rankings(const double* vals, const int32_t* nn, int64_t N0, int64_t n, int L, int m,
-                               int excl_den, int kd, int32_t* on, double* d, hipStream_t st) {
-  if (m <= 0 || kd <= 0 || kd > kMaxK) return hipErrorInvalidValue;
-  k_topk_discords<<<m, kRankThreads, 0, st>>>(vals, nn, N0, n, L, 0, excl_den, kd, on, d);
+                               int excl_den, int kd, int32_t* on, double* d, hipStream_t st, int emul) {
+  if (m <= 0 || kd <= 0 || kd > kMaxK || emul < 1) return hipErrorInvalidValue;
+  k_topk_discords<<<m, kRankThreads, 0, st>>>(vals, nn, N0, n, L, 0, excl_den, kd, on, d, emul);
   return hipGetLastError();
 }
 

@@ -558,14 +558,10 @@ def test_paper_mode_motif_per_length_exact(oracle_mod, precision, p):
     assert rep["partial_entries"] == int(st[:, 10].sum())
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_mth_discords_parity(oracle_mod, precision):
-    """Top-k m-th discords (m = 3) per length and across lengths against the
-    oracle: offsets equal except between ties, distances to the FP64 tolerance;
-    the 1st-discord column equals the plain discords."""
-    x = gen.small_random_walk(1600, 97, np.float32)
-    lo, hi, k, m = 24, 30, 3, 3
-    g = run_gpu(x, lo, hi, p=5, k_motifs=2, k_discords=k, m_discords=m, precision=precision)
+def _check_mth(oracle_mod, x, lo, hi, g, k, m):
+    """Top-k m-th discords per length and across lengths against the oracle:
+    offsets equal except between ties, distances to the FP64 tolerance; the
+    1st-discord column equals the plain discords."""
     r = oracle_mod.mth_discords(x, lo, hi, k, m)
     for t in range(hi - lo + 1):
         L = lo + t
@@ -574,6 +570,9 @@ def test_mth_discords_parity(oracle_mod, precision):
                 go, gn = (int(v) for v in g["mdiscord_on"][t, j, q])
                 ro = int(r["on"][t, j, q, 0])
                 gd, rd = g["mdiscord_d"][t, j, q], r["d"][t, j, q]
+                if np.isnan(rd):
+                    assert np.isnan(gd) and go == -1, (L, j, q, gd, go)
+                    continue
                 assert abs(gd - rd) <= TOL64 * np.sqrt(L), (L, j, q, gd, rd)
                 if go != ro:  # a tie: the reported owner's (j+1)-th distance equals the oracle's
                     d_own, _ = oracle_mod.mth_rows(x, L, m, rows=[go])
@@ -582,7 +581,60 @@ def test_mth_discords_parity(oracle_mod, precision):
                 assert abs(oracle_mod.pair_dist(x, L, go, gn) - dd[0, j]) <= TOL64 * np.sqrt(L)
         np.testing.assert_allclose(g["mdiscord_d"][t, 0], g["discord_d"][t], rtol=0, atol=TOL64 * np.sqrt(L))
     np.testing.assert_allclose(g["g_mdiscord_d"], r["g_d"], rtol=0, atol=TOL64)
-    _say(f"m-th discords {precision}: ok, stats recomputed {g['stats'][:, 2].tolist()}")
+
+
+def _mth_stats(g):
+    st = g["stats"]
+    return {"recomputed": st[:, 2].tolist(), "full": st[:, 3].tolist(), "certified": int(st[:, 11].sum()),
+            "m_recomputed": int(st[:, 12].sum()), "pruned": int(st[:, 13].sum())}
+
+
+@pytest.mark.parametrize("path", ["auto", "recompute", "full"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mth_discords_parity(oracle_mod, precision, path):
+    """Top-k m-th discords (m = 3) on a random walk; with partial profiles the
+    m-lists are certified, pruned or recomputed (Alg. Topkm_nextLength), with a
+    full pass at every length they are collected exactly."""
+    x = gen.small_random_walk(1600, 97, np.float32)
+    lo, hi, k, m = 24, 30, 3, 3
+    g = run_gpu(x, lo, hi, p=5, k_motifs=2, k_discords=k, m_discords=m, precision=precision, path=path)
+    _check_mth(oracle_mod, x, lo, hi, g, k, m)
+    st = _mth_stats(g)
+    _say(f"m-th discords {precision} {path}: ok, {st}")
+    if path == "full":
+        assert st["certified"] == st["m_recomputed"] == st["pruned"] == 0
+    else:
+        assert st["certified"] > 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mth_discords_pruned_on_planted_discord(oracle_mod, precision):
+    """A noisy sine with one planted anomaly: the periodic windows have close
+    m-th best matches, so the top-k cutoff leaves most uncertified m-lists out,
+    and the rankings still equal the oracle's."""
+    x, c = gen.small_sine_with_discord(2400, 5, 60, 40)
+    lo, hi, k, m = 36, 44, 2, 4
+    g = run_gpu(x, lo, hi, p=8, k_motifs=2, k_discords=k, m_discords=m, precision=precision, path="recompute")
+    _check_mth(oracle_mod, x, lo, hi, g, k, m)
+    st = _mth_stats(g)
+    _say(f"planted discord {precision}: {st}")
+    assert st["pruned"] > 0 and st["certified"] > 0
+    top = g["mdiscord_on"][:, 0, 0, 0]
+    assert (np.abs(top - c) <= hi).all(), (top, c)
+
+
+@pytest.mark.parametrize("cap", [3, 2])
+def test_mth_discords_overflowing_lists(oracle_mod, monkeypatch, cap):
+    """Collecting lists of `cap` entries (test hook): at a rebuild most owners
+    overflow; with cap >= m their threshold bounds their m-th best matches and
+    they can be pruned, with cap < m they are recomputed. Rankings equal the
+    oracle's either way."""
+    monkeypatch.setenv("VALMOD_COLLECT_CAP", str(cap))
+    x = gen.small_random_walk(1800, 98, np.float32)
+    lo, hi, k, m = 28, 33, 3, 3
+    g = run_gpu(x, lo, hi, p=5, k_motifs=2, k_discords=k, m_discords=m, precision="fp32")
+    _check_mth(oracle_mod, x, lo, hi, g, k, m)
+    _say(f"overflowing lists cap {cap}: {_mth_stats(g)}")
 
 
 def _check_motif_sets(oracle_mod, x, lo, hi, g, D, cap, k):
