@@ -350,14 +350,16 @@ VALMOD_API valmod_status valmod_run_status(valmod_plan_t plan, void* stream);
  * and 4 diagonals per lane (4 only unless VALMOD_PASS_K32 fixes it); each
  * candidate is timed on three lengths at the start and three at the end of the
  * range on the full path. Stage 2 (exact mode with partial profiles): p, p/2 and
- * p/4 are timed on the first four lengths with the plan's own path (the outputs
- * do not depend on p in exact mode). Every measurement is the second of two runs,
+ * p/4 are timed on the first four lengths with the plan's own path, and against
+ * them a run without partial profiles (a full pass at every length; the outputs
+ * depend on neither choice in exact mode). Every measurement is the second of two runs,
  * and the fastest candidate whose workspace fits in valmod_workspace_bytes (as it
  * was before the call) is kept: the plan's workspace requirement can only shrink.
  * Arguments are those of valmod_run (same buffers; d_out may be NULL: the tuning
  * runs write no output). The call waits for its runs. chosen (optional, host
- * int32[3]): segment height, diagonals per lane and p of the tuned series (the
- * current ones when nothing was tuned). Errors: those of valmod_run.
+ * int32[3]): segment height, diagonals per lane and p of the tuned series (p = 0:
+ * partial profiles off; the current ones when nothing was tuned). Errors: those
+ * of valmod_run.
  */
 VALMOD_API valmod_status valmod_autotune(valmod_plan_t plan, const void* d_series, void* d_workspace,
                                          const valmod_outputs* d_out, void* stream, int32_t* chosen);

@@ -167,6 +167,7 @@ struct valmod_plan_s {
   int tune_hmul = 1;
   int32_t tune_R = 0;
   int tune_K = 0;  // diagonals per lane (0: default)
+  bool tune_no_heaps = false;  // the autotuner found that partial profiles do not pay
   double pass_ms = 0.0;
   int64_t pass_launches = 0, pass_cells = 0;
 };
@@ -722,7 +723,7 @@ LaneRun::Status LaneRun::advance() {
     LCHECK(launch_convert(series, P->cfg.dtype, n, n + kPad, xs, (int*)&cnt[CNT_ERR], st));
     LCHECK(launch_valmp_init(N0, vnorm, vdist, vlen, vidx, st));
     // partial profiles are used unless every length is forced through a full pass
-    heaps_on = P->cfg.path != VALMOD_PATH_FULL && Ls.l_max > Ls.l_min && !noalloc;
+    heaps_on = P->cfg.path != VALMOD_PATH_FULL && Ls.l_max > Ls.l_min && !noalloc && !P->tune_no_heaps;
     base = 0;            // base length of the current partial profiles (0: none)
     probe_next = false;  // judge the partial profiles at the first length after a rebuild
     L = Ls.l_min;
@@ -1431,6 +1432,7 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
     int32_t R;
     int K;
     int32_t p;
+    bool no_heaps;
   };
   // time one candidate on lengths [lo, hi] of the tuned series (ms, -1 if it does not fit)
   auto time_run = [&](const Cand& c, int32_t lo, int32_t hi, int32_t path, double* ms) -> valmod_status {
@@ -1466,7 +1468,7 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
     valmod_plan_free(sub);
     return st;
   };
-  Cand best{P->tune_hmul, P->tune_R, P->tune_K, P->cfg.p};
+  Cand best{P->tune_hmul, P->tune_R, P->tune_K, P->cfg.p, P->tune_no_heaps};
   // stage 1: pass geometry
   std::vector<Cand> cand;
   const bool k_fixed = env_int(fp32 ? "VALMOD_PASS_K32" : "VALMOD_PASS_K", 0) != 0;
@@ -1474,9 +1476,9 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
     if (P->cfg.refresh_R <= 0)
       for (int32_t R : {256, 512, 1024})
         for (int K : {8, 4})
-          if (K == 8 || !k_fixed) cand.push_back({1, R, k_fixed ? 0 : K, P->cfg.p});
+          if (K == 8 || !k_fixed) cand.push_back({1, R, k_fixed ? 0 : K, P->cfg.p, P->tune_no_heaps});
   } else if (env_int("VALMOD_PASS_H", 0) == 0) {
-    for (int h : {1, 2, 4}) cand.push_back({h, 0, 0, P->cfg.p});
+    for (int h : {1, 2, 4}) cand.push_back({h, 0, 0, P->cfg.p, P->tune_no_heaps});
   }
   const int32_t T = (int32_t)std::min<int64_t>(3, Ls.nlen);
   const int32_t lo_a = Ls.l_min, lo_b = std::max<int32_t>(Ls.l_min, Ls.l_max - T + 1);
@@ -1495,7 +1497,9 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
       }
     }
   }
-  // stage 2: p (exact mode with partial profiles)
+  // stage 2: p (exact mode with partial profiles), and no partial profiles at all
+  // (the lower bound may fail right after the first length, as on periodic data;
+  // the outputs are the same)
   const bool heaps = P->cfg.mode == VALMOD_MODE_EXACT && P->cfg.path != VALMOD_PATH_FULL && P->cfg.m_discords <= 1 &&
                      !P->cfg.graph && Ls.nlen >= 2;
   if (heaps) {
@@ -1505,11 +1509,14 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
     std::vector<int32_t> pcs;
     for (int32_t pc : {P->cfg.p, P->cfg.p / 2, P->cfg.p / 4})
       if (pc >= 1 && std::find(pcs.begin(), pcs.end(), pc) == pcs.end()) pcs.push_back(pc);
+    pcs.push_back(0);  // partial profiles off
     for (int32_t pc : pcs) {
       Cand c = keep;
-      c.p = pc;
+      c.p = pc > 0 ? pc : keep.p;
+      c.no_heaps = pc == 0;
       double ms = 0.0;
-      const valmod_status st = time_run(c, Ls.l_min, Ls.l_min + T2 - 1, P->cfg.path, &ms);
+      const valmod_status st =
+          time_run(c, Ls.l_min, Ls.l_min + T2 - 1, c.no_heaps ? (int32_t)VALMOD_PATH_FULL : P->cfg.path, &ms);
       if (st != VALMOD_OK) return st;
       if (ms < 0.0) continue;
       if (best_ms < 0.0 || ms < best_ms) {
@@ -1518,13 +1525,14 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
       }
     }
   }
-  const Cand old{P->tune_hmul, P->tune_R, P->tune_K, P->cfg.p};
+  const Cand old{P->tune_hmul, P->tune_R, P->tune_K, P->cfg.p, P->tune_no_heaps};
   const int64_t old_cap = P->cap;
   const size_t old_total = P->ws_total;
   auto apply = [&](const Cand& c) {
     P->tune_hmul = c.hmul;
     P->tune_R = c.R;
     P->tune_K = c.K;
+    P->tune_no_heaps = c.no_heaps;
     P->cfg.p = c.p;
     P->cap = 8 * (int64_t)c.p < 64 ? 64 : (8 * (int64_t)c.p > 512 ? 512 : 8 * (int64_t)c.p);
     const int cap_env = env_int("VALMOD_COLLECT_CAP", 0);
@@ -1548,7 +1556,7 @@ extern "C" valmod_status valmod_autotune(valmod_plan_t P, const void* d_series, 
   if (chosen) {
     chosen[0] = (int32_t)P->geom[sbest].H;
     chosen[1] = P->geom[sbest].K;
-    chosen[2] = P->cfg.p;
+    chosen[2] = P->tune_no_heaps ? 0 : P->cfg.p;
   }
   return VALMOD_OK;
 }

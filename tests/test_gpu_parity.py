@@ -518,8 +518,8 @@ def test_batched_random_walks_sampled_parity(oracle_mod):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_autotune_keeps_results_exact(oracle_mod, precision):
-    """The autotuner changes only the pass geometry: the run after it still
-    matches the oracle everywhere."""
+    """The autotuner changes only the pass geometry, p and whether partial
+    profiles are used: the run after it still matches the oracle everywhere."""
     torch = _torch()
     from oracle import compare
     from paper_2008_13447_amd import native
@@ -531,7 +531,7 @@ def test_autotune_keeps_results_exact(oracle_mod, precision):
     H, K, p_used = v.autotune()
     assert native.valmod_workspace_bytes(v.plan) <= before
     _say(f"autotune {precision}: H={H} K={K} p={p_used}")
-    assert 1 <= p_used <= 5
+    assert 0 <= p_used <= 5  # 0: partial profiles off
     v.run()
     g = v.result(0)
     v.close()
