@@ -89,9 +89,10 @@ __global__ __launch_bounds__(kWave) void k_anchor_mfma(const double* __restrict_
 }
 
 // Exact row recompute: for the listed owners (16 per wavefront, a grid-stride
-// walk over the device-side list) and a chunk of 64 candidates, the best key
-// (correlation, candidate) over the eligible candidates, merged into the
-// owner's key by a 64-bit atomic min (the listing kernel set it to empty).
+// walk over the device-side list) and chunks of 64 candidates (a grid-stride
+// walk too, so that the grid stays small when the list is short or empty), the
+// best key (correlation, candidate) over the eligible candidates, merged into
+// the owner's key by a 64-bit atomic min (the listing kernel set it to empty).
 __global__ __launch_bounds__(kWave) void k_recompute_mfma(const double* __restrict__ xs, const double* __restrict__ A,
                                                           const double* __restrict__ invn,
                                                           const uint8_t* __restrict__ flat,
@@ -99,9 +100,8 @@ __global__ __launch_bounds__(kWave) void k_recompute_mfma(const double* __restri
                                                           const unsigned long long* __restrict__ nlist, int64_t N,
                                                           int L, int64_t e, uint64_t* __restrict__ best) {
   const int64_t count = (int64_t)*nlist;
-  const int64_t j0 = (int64_t)blockIdx.x * kTileCols;
-  if (j0 >= N) return;
   const int l = threadIdx.x & (kWave - 1);
+  for (int64_t j0 = (int64_t)blockIdx.x * kTileCols; j0 < N; j0 += (int64_t)gridDim.x * kTileCols)
   for (int64_t rb = (int64_t)blockIdx.y * 16; rb < count; rb += (int64_t)gridDim.y * 16) {
     const int64_t ri = rb + (l & 15);
     const int64_t ra = list[ri < count ? ri : count - 1];  // rows past the list repeat its last owner
@@ -154,7 +154,8 @@ hipError_t launch_recompute_mfma(const double* xs, const double* A, const double
                                  int L, int64_t e, uint64_t* best, hipStream_t st) {
   if (max_listed <= 0 || N <= 0) return hipSuccess;
   const int64_t groups = (max_listed + 15) / 16;
-  const dim3 grid(blocks_for(N, kTileCols), (unsigned)(groups < 16 ? groups : 16));
+  const unsigned chunks = blocks_for(N, kTileCols);
+  const dim3 grid(chunks < 2048 ? chunks : 2048, (unsigned)(groups < 16 ? groups : 16));
   k_recompute_mfma<<<grid, kWave, 0, st>>>(xs, A, invn, flat, list, nlist, N, L, e, best);
   return hipGetLastError();
 }
