@@ -34,7 +34,11 @@ constexpr int kNB = kTileCols / 16;
 inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
 // acc[c] += the 16 x 16 block of rows `ra` (this lane's row start, one per
-// l % 16) and columns j0 + 16 c + (l % 16), summed over k < L
+// l % 16) and columns j0 + 16 c + (l % 16), summed over k < L. The operands of
+// a group of four terms are loaded two groups before their products run, and
+// every load is unconditional (a term past L is zeroed after its load), so no
+// load waits inside a branch. Reads reach at most L + 10 past a window's start
+// (the row's and the last column's), inside the series' zero padding.
 __device__ __forceinline__ void hankel_block(const double* __restrict__ xs, int64_t ra, int64_t j0, int L,
                                              f64x4 acc[kNB]) {
   const int l = threadIdx.x & (kWave - 1);
@@ -44,15 +48,30 @@ __device__ __forceinline__ void hankel_block(const double* __restrict__ xs, int6
   double xb0[kNB];
 #pragma unroll
   for (int c = 0; c < kNB; ++c) xb0[c] = xs[jb + 16 * c];
-  for (int k0 = 0; k0 < L; k0 += 4) {
-    const int k = k0 + kk;
-    const bool in = k < L;
-    const double a = in ? xs[ra + k] - xa0 : 0.0;
+  // two groups in flight: terms k0 + kk (set 0) and k0 + 4 + kk (set 1)
+  double a0 = xs[ra + kk], a1 = xs[ra + 4 + kk];
+  double b0[kNB], b1[kNB];
 #pragma unroll
-    for (int c = 0; c < kNB; ++c) {
-      const double b = in ? xs[jb + 16 * c + k] - xb0[c] : 0.0;
-      acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
-    }
+  for (int c = 0; c < kNB; ++c) {
+    b0[c] = xs[jb + 16 * c + kk];
+    b1[c] = xs[jb + 16 * c + 4 + kk];
+  }
+  auto group = [&](int k0, double& an, double* bn) {
+    const bool in = k0 + kk < L;
+    const double a = in ? an - xa0 : 0.0;
+    double b[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) b[c] = in ? bn[c] - xb0[c] : 0.0;
+    const int kn = k0 + 8 + kk;  // this set's next group
+    an = xs[ra + kn];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) bn[c] = xs[jb + 16 * c + kn];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[c], acc[c], 0, 0, 0);
+  };
+  for (int k0 = 0; k0 < L; k0 += 8) {
+    group(k0, a0, b0);
+    if (k0 + 4 < L) group(k0 + 4, a1, b1);
   }
 }
 
