@@ -1100,12 +1100,12 @@ LaneRun::Status LaneRun::advance() {
     LCHECK(launch_mth_prune(mstate, mub, tau_d, N, N0, md, kd, fresh ? 1 : 0, mlist, &cnt[CNT_MREC], fail,
                             &cnt[CNT_NFAIL], &cnt[CNT_MCERT], &cnt[CNT_MPRUNED], st));
     LCHECK(launch_recompute_topm_keys(xs, A, invn, flat, mlist, &cnt[CNT_MREC], N, N, N0, L, e, md, mkeys, best,
-                                      mvals, mnn, st));
+                                      mvals, mnn, use_mfma, st));
     if (!fresh) recompute = true;
     if (recompute) LCHECK(recompute_rows(fail, &cnt[CNT_NFAIL]));
   } else if (recompute && md > 1) {
     LCHECK(launch_recompute_topm(xs, A, invn, flat, fail, &cnt[CNT_NFAIL], N, N, L, e, md, p, mkeys, hc, hS, hn, best,
-                                 st));
+                                 use_mfma, st));
   } else if (recompute) {
     LCHECK(recompute_rows(fail, &cnt[CNT_NFAIL]));
   }

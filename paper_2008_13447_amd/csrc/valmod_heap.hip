@@ -805,12 +805,19 @@ hipError_t launch_mth_prune(const uint8_t* mstate, const double* ub, const doubl
 hipError_t launch_recompute_topm_keys(const double* xs, const double* A, const double* invn, const uint8_t* flat,
                                       const int32_t* list, const unsigned long long* nlist, int64_t max_listed,
                                       int64_t N, int64_t N0, int L, int64_t e, int m, uint64_t* keys, uint64_t* best,
-                                      double* vals, int32_t* nn, hipStream_t st) {
+                                      double* vals, int32_t* nn, bool mfma, hipStream_t st) {
   if (max_listed <= 0 || N <= 0) return hipSuccess;
   k_clear_keys<<<blocks_for(max_listed, 256), 256, 0, st>>>(list, nlist, m, keys);
   const dim3 grid(blocks_for(N, kWave * kRecK), (unsigned)(max_listed < 32 ? max_listed : 32));
-  for (int j = 0; j < m; ++j)
-    k_recompute_round<<<grid, kWave, 0, st>>>(xs, A, invn, flat, list, nlist, N, L, e, m, j, keys);
+  for (int j = 0; j < m; ++j) {
+    if (mfma) {
+      const hipError_t e1 = launch_recompute_round_mfma(xs, A, invn, flat, list, nlist, max_listed, N, L, e, m, j,
+                                                        keys, st);
+      if (e1 != hipSuccess) return e1;
+    } else {
+      k_recompute_round<<<grid, kWave, 0, st>>>(xs, A, invn, flat, list, nlist, N, L, e, m, j, keys);
+    }
+  }
   k_topm_best<<<blocks_for(max_listed, 256), 256, 0, st>>>(list, nlist, m, keys, best);
   k_mth_fill<<<blocks_for(max_listed, 128), 128, 0, st>>>(xs, A, invn, list, nlist, keys, m, N0, L, vals, nn);
   return hipGetLastError();
@@ -819,13 +826,20 @@ hipError_t launch_recompute_topm_keys(const double* xs, const double* A, const d
 hipError_t launch_recompute_topm(const double* xs, const double* A, const double* invn, const uint8_t* flat,
                                  const int32_t* fail, const unsigned long long* nfail, int64_t max_listed, int64_t N,
                                  int L, int64_t e, int m, int p, uint64_t* keys, int32_t* hc, double* hS, int32_t* hn,
-                                 uint64_t* best, hipStream_t st) {
+                                 uint64_t* best, bool mfma, hipStream_t st) {
   if (max_listed <= 0 || N <= 0) return hipSuccess;
   if (m < 1 || m > p) return hipErrorInvalidValue;
   k_clear_keys<<<blocks_for(max_listed, 256), 256, 0, st>>>(fail, nfail, m, keys);
   const dim3 grid(blocks_for(N, kWave * kRecK), (unsigned)(max_listed < 32 ? max_listed : 32));
-  for (int j = 0; j < m; ++j)
-    k_recompute_round<<<grid, kWave, 0, st>>>(xs, A, invn, flat, fail, nfail, N, L, e, m, j, keys);
+  for (int j = 0; j < m; ++j) {
+    if (mfma) {
+      const hipError_t e1 = launch_recompute_round_mfma(xs, A, invn, flat, fail, nfail, max_listed, N, L, e, m, j,
+                                                        keys, st);
+      if (e1 != hipSuccess) return e1;
+    } else {
+      k_recompute_round<<<grid, kWave, 0, st>>>(xs, A, invn, flat, fail, nfail, N, L, e, m, j, keys);
+    }
+  }
   k_topm_store<<<blocks_for(max_listed, 256), 256, 0, st>>>(xs, fail, nfail, L, m, p, keys, hc, hS, hn, best);
   return hipGetLastError();
 }

@@ -181,7 +181,7 @@ hipError_t launch_recompute(const double* xs, const double* A, const double* inv
 hipError_t launch_recompute_topm(const double* xs, const double* A, const double* invn, const uint8_t* flat,
                                  const int32_t* fail, const unsigned long long* nfail, int64_t max_listed, int64_t N,
                                  int L, int64_t e, int m, int p, uint64_t* keys, int32_t* hc, double* hS, int32_t* hn,
-                                 uint64_t* best, hipStream_t st);
+                                 uint64_t* best, bool mfma, hipStream_t st);
 hipError_t launch_mth_values(const double* A, const double* invn, const uint8_t* flat, const int32_t* hc,
                              const double* hS, const int32_t* hn, int p, int m, int64_t N, int64_t N0, int L,
                              double* vals, int32_t* nn, hipStream_t st);
@@ -227,7 +227,7 @@ hipError_t launch_mth_prune(const uint8_t* mstate, const double* ub, const doubl
 hipError_t launch_recompute_topm_keys(const double* xs, const double* A, const double* invn, const uint8_t* flat,
                                       const int32_t* list, const unsigned long long* nlist, int64_t max_listed,
                                       int64_t N, int64_t N0, int L, int64_t e, int m, uint64_t* keys, uint64_t* best,
-                                      double* vals, int32_t* nn, hipStream_t st);
+                                      double* vals, int32_t* nn, bool mfma, hipStream_t st);
 hipError_t launch_mth_global(const int32_t* on, const double* d, int nlen, int l_min, int m, int kd,
                              int32_t* g_onl, double* g_d, hipStream_t st);
 // motif sets grown from the global top-k motif pairs of one series (valmod_sets.hip)
@@ -262,6 +262,11 @@ hipError_t launch_anchor_mfma(const double* xs, int64_t n, int L, int64_t H, int
 hipError_t launch_recompute_mfma(const double* xs, const double* A, const double* invn, const uint8_t* flat,
                                  const int32_t* list, const unsigned long long* nlist, int64_t max_listed, int64_t N,
                                  int L, int64_t e, uint64_t* best, hipStream_t st);
+// round jr of the top-m recompute on matrix cores: out[o * m + jr] = the smallest
+// key above out[o * m + jr - 1] (must be empty before the round)
+hipError_t launch_recompute_round_mfma(const double* xs, const double* A, const double* invn, const uint8_t* flat,
+                                       const int32_t* list, const unsigned long long* nlist, int64_t max_listed,
+                                       int64_t N, int L, int64_t e, int m, int jr, uint64_t* out, hipStream_t st);
 // copies best keys into an int32 index array (-1 for empty keys)
 hipError_t launch_keys_to_idx(const uint64_t* best, int64_t N, int32_t* idx, hipStream_t st);
 

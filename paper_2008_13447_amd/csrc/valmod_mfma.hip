@@ -112,12 +112,17 @@ __global__ __launch_bounds__(kWave) void k_anchor_mfma(const double* __restrict_
 // walk too, so that the grid stays small when the list is short or empty), the
 // best key (correlation, candidate) over the eligible candidates, merged into
 // the owner's key by a 64-bit atomic min (the listing kernel set it to empty).
+//
+// The same kernel serves the rounds of the top-m recompute: with m > 1 the
+// owner's result goes to out[o * m + j] and only keys strictly above its key of
+// round j - 1 (out[o * m + j - 1]) take part; an owner whose previous round found
+// nothing is skipped.
 __global__ __launch_bounds__(kWave) void k_recompute_mfma(const double* __restrict__ xs, const double* __restrict__ A,
                                                           const double* __restrict__ invn,
                                                           const uint8_t* __restrict__ flat,
                                                           const int32_t* __restrict__ list,
                                                           const unsigned long long* __restrict__ nlist, int64_t N,
-                                                          int L, int64_t e, uint64_t* __restrict__ best) {
+                                                          int L, int64_t e, int m, int jr, uint64_t* __restrict__ out) {
   const int64_t count = (int64_t)*nlist;
   const int l = threadIdx.x & (kWave - 1);
   for (int64_t j0 = (int64_t)blockIdx.x * kTileCols; j0 < N; j0 += (int64_t)gridDim.x * kTileCols)
@@ -134,7 +139,8 @@ __global__ __launch_bounds__(kWave) void k_recompute_mfma(const double* __restri
       const int64_t rr = rb + 4 * v + (l >> 4);
       const bool live = rr < count;
       const int64_t o = live ? list[rr] : 0;
-      const bool own = live && !flat[o];
+      const uint64_t floor_key = (live && jr > 0) ? out[o * m + jr - 1] : 0;
+      const bool own = live && !flat[o] && (jr == 0 || floor_key != kEmptyKey);
       const double Ao = own ? A[o] : 0.0, io = own ? invn[o] : 0.0;
       uint64_t kb = kEmptyKey;
 #pragma unroll
@@ -143,7 +149,7 @@ __global__ __launch_bounds__(kWave) void k_recompute_mfma(const double* __restri
         if (own && j < N && iabs64(j - o) > e && !flat[j]) {
           const double rho = (acc[c][v] - Ao * A[j] / (double)L) * io * invn[j];
           const uint64_t key = make_key(rho, j);
-          kb = key < kb ? key : kb;
+          if (jr == 0 || key > floor_key) kb = key < kb ? key : kb;
         }
       }
       // min over the 16 lanes that share this row (same l / 16)
@@ -152,7 +158,8 @@ __global__ __launch_bounds__(kWave) void k_recompute_mfma(const double* __restri
         const uint64_t other = shfl_xor_u64(kb, m);
         kb = other < kb ? other : kb;
       }
-      if ((l & 15) == 0 && live && kb != kEmptyKey) atomicMin((unsigned long long*)&best[o], (unsigned long long)kb);
+      if ((l & 15) == 0 && live && kb != kEmptyKey)
+        atomicMin((unsigned long long*)&out[o * m + jr], (unsigned long long)kb);
     }
   }
 }
@@ -171,11 +178,18 @@ hipError_t launch_anchor_mfma(const double* xs, int64_t n, int L, int64_t H, int
 hipError_t launch_recompute_mfma(const double* xs, const double* A, const double* invn, const uint8_t* flat,
                                  const int32_t* list, const unsigned long long* nlist, int64_t max_listed, int64_t N,
                                  int L, int64_t e, uint64_t* best, hipStream_t st) {
+  return launch_recompute_round_mfma(xs, A, invn, flat, list, nlist, max_listed, N, L, e, 1, 0, best, st);
+}
+
+hipError_t launch_recompute_round_mfma(const double* xs, const double* A, const double* invn, const uint8_t* flat,
+                                       const int32_t* list, const unsigned long long* nlist, int64_t max_listed,
+                                       int64_t N, int L, int64_t e, int m, int jr, uint64_t* out, hipStream_t st) {
   if (max_listed <= 0 || N <= 0) return hipSuccess;
+  if (m < 1 || jr < 0 || jr >= m) return hipErrorInvalidValue;
   const int64_t groups = (max_listed + 15) / 16;
   const unsigned chunks = blocks_for(N, kTileCols);
   const dim3 grid(chunks < 2048 ? chunks : 2048, (unsigned)(groups < 16 ? groups : 16));
-  k_recompute_mfma<<<grid, kWave, 0, st>>>(xs, A, invn, flat, list, nlist, N, L, e, best);
+  k_recompute_mfma<<<grid, kWave, 0, st>>>(xs, A, invn, flat, list, nlist, N, L, e, m, jr, out);
   return hipGetLastError();
 }
 

@@ -607,6 +607,21 @@ def test_mth_discords_parity(oracle_mod, precision, path):
         assert st["certified"] > 0
 
 
+@pytest.mark.parametrize("mfma", ["1", "0"])
+def test_mth_discords_topm_rounds_on_matrix_cores(oracle_mod, monkeypatch, mfma):
+    """The rounds of the top-m row recompute on FP64 matrix cores (each the best
+    key above the previous round's) and on VALU give rankings equal to the
+    oracle's, on the path that recomputes every uncertified owner."""
+    monkeypatch.setenv("VALMOD_MFMA", mfma)
+    x = gen.small_random_walk(1900, 99, np.float32)
+    lo, hi, k, m = 26, 31, 3, 4
+    g = run_gpu(x, lo, hi, p=6, k_motifs=2, k_discords=k, m_discords=m, precision="fp32", path="recompute")
+    _check_mth(oracle_mod, x, lo, hi, g, k, m)
+    st = _mth_stats(g)
+    _say(f"top-m rounds mfma={mfma}: {st}")
+    assert st["m_recomputed"] > 0
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_mth_discords_pruned_on_planted_discord(oracle_mod, precision):
     """A noisy sine with one planted anomaly: the periodic windows have close
