@@ -118,7 +118,7 @@ typedef struct {
                                rounding bound grows linearly with R */
   int32_t path;             /* valmod_path */
   int32_t device;           /* HIP device ordinal the plan runs on */
-  int32_t lanes;            /* series processed concurrently (streams), 0 = default min(num_series, 4),
+  int32_t lanes;            /* series processed concurrently (streams), 0 = default min(num_series, 16),
                                at most 64; each lane has its own workspace slice */
   int32_t graph;            /* 1: capture the whole run in a HIP graph on the first call and replay it on
                                later calls with the same buffers and stream; implies VALMOD_PATH_FULL

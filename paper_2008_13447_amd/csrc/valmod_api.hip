@@ -433,7 +433,9 @@ extern "C" valmod_status valmod_plan(const valmod_config* cfg, valmod_plan_t* ou
   if (cap_env > 0) P->cap = cap_env < 512 ? cap_env : 512;
 
   // lanes: longest-processing-time assignment of the series by sum over lengths of N_L^2
-  const int nl = std::min(S, P->cfg.lanes > 0 ? (int)P->cfg.lanes : 4);
+  // default 16 lanes: more streams than hardware queues still overlap the short
+  // per-length kernels of one series with the passes of others
+  const int nl = std::min(S, P->cfg.lanes > 0 ? (int)P->cfg.lanes : 16);
   try {
     P->lanes.resize(nl);
     std::vector<int> order(S);
