@@ -28,7 +28,7 @@ struct WsLayout {
   size_t xs, A, B, A2, B2, mu, sig, invn, flat, df, dg, sw32, thr, thr32, best, counters, anc;
   size_t hc, hS, hn, hbound, hsig, hflat, acnt, abuf, fail, big, lbm, rec, part, mvals, mnn, mkeys;
   size_t mstate, mub, mlist, tau_on, tau_d;
-  size_t df32, dg32, inv32, bsw_max, bsw_min, bdf_max, bdg_max, bmu_max, delta64, delta, hard, fext, fthr;
+  size_t df32, dg32, inv32, bsw_max, bsw_min, bdf_max, bdg_max, bmu_max, delta64, delta, hard;
   size_t ms_keys0, ms_keys1, ms_vals0, ms_vals1, ms_hist, ms_meta, ms_count, ms_taken, ms_bucket;
   // the last ring_rows profile rows (distance, index; stride N0 of the series):
   // seeds of the next length and input of the per-length rankings
@@ -270,8 +270,6 @@ static size_t layout_lane(const valmod_plan_s* P, Lane& ln) {
     w.inv32 = take(wp * 4);
     w.delta = take((size_t)ln.itemmax * 4);
     w.hard = take((size_t)ln.itemmax * 4);
-    w.fext = take(wp * 8);  // block-filter inputs of the FP32 collecting pass
-    w.fthr = take(wp * 4);
   }
   w.ring_rows = std::min<int64_t>(ln.nlenmax, kRingRows);
   w.ring_d = take((size_t)(w.ring_rows * ln.n0max + kPad) * 8);
@@ -565,8 +563,6 @@ struct LaneRun {
   double *xs, *A, *B, *A2, *B2, *mu, *sig, *invn, *df, *dg, *thr, *anc, *hS, *hbound, *hsig, *lbm;
   uint8_t* flat;
   float *sw32, *thr32, *df32, *dg32, *inv32, *bsw_max, *bsw_min, *bdf_max, *bdg_max, *bmu_max, *delta64, *delta;
-  float2* fext;
-  float* fthr;
   uint8_t* hflat;
   uint64_t* best;
   unsigned long long* cnt;
@@ -668,8 +664,6 @@ struct LaneRun {
     sub_gdd = (double*)(b + w.sub_gdd);
     delta = fp32 ? (float*)(b + w.delta) : nullptr;
     hard = fp32 ? (int32_t*)(b + w.hard) : nullptr;
-    fext = fp32 ? (float2*)(b + w.fext) : nullptr;
-    fthr = fp32 ? (float*)(b + w.fthr) : nullptr;
     if (P->cfg.mset_radius > 0.0) {
       ms.meta = (double*)(b + w.ms_meta);
       ms.count = (uint32_t*)(b + w.ms_count);
@@ -747,8 +741,6 @@ LaneRun::Status LaneRun::advance() {
   // dense dot-product blocks (anchor table, row recompute) on FP64 matrix cores;
   // VALMOD_MFMA=0 selects the VALU kernels
   const bool use_mfma = env_int("VALMOD_MFMA", 1) != 0;
-  // FP32 collecting passes: block filter (k_collect32) or the per-cell filter of k_pass
-  const bool block_filter = env_int("VALMOD_BLOCK_FILTER", 0) != 0;
   // exact rows of the listed owners (every eligible candidate), reduced into `best`
   auto recompute_rows = [&](const int32_t* list, const unsigned long long* nlist) -> hipError_t {
     return use_mfma ? launch_recompute_mfma(xs, A, invn, flat, list, nlist, N, N, L, e, best, st)
@@ -949,11 +941,6 @@ LaneRun::Status LaneRun::advance() {
       q.fp32 = true;
       q.delta = delta;
       q.delta_max = delta_max;
-      if (block_filter) {
-        q.ext = fext;
-        q.thrf = fthr;
-        if (e1 == hipSuccess) e1 = launch_filter_window(thr32, inv32, N, G.K, fext, fthr, st);
-      }
       if (e1 == hipSuccess) e1 = timed_pass(q);
       // then the listed items in FP64 (a small grid that walks the device-side
       // list; on the same stream: a second stream's fork and join cost more

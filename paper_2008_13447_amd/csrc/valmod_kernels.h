@@ -61,11 +61,6 @@ struct PassLaunch {
   // optional: events recorded by the full-grid launch itself (start and end of
   // the kernel), so timing it adds no marker between it and its neighbours
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;
-  // FP32 collecting pass with the block filter (k_collect32): window extrema of
-  // the column thresholds and inverse norms, and the owners' filter thresholds
-  // (launch_filter_window); null: the per-cell filter of k_pass
-  const float2* ext = nullptr;
-  const float* thrf = nullptr;
 };
 
 struct PassGrid {
@@ -74,11 +69,7 @@ struct PassGrid {
 
 // Work decomposition of the diagonal pass over the upper triangle j - i > e.
 PassGrid pass_grid(int64_t N, int64_t e, int64_t dstart, int K, int64_t H);
-// inputs of the FP32 block filter at length L (after the thresholds are set):
-// ext and thrf hold at least N + kFilterWindowAhead entries
-constexpr int64_t kFilterWindowAhead = 1024;
-hipError_t launch_filter_window(const float* thr32, const float* inv32, int64_t N, int K, float2* ext, float* thrf,
-                                hipStream_t st);
+
 hipError_t launch_anchor(const double* xs, int64_t n, int L, bool init, int64_t H, int64_t dstart, int64_t segs,
                          int64_t stride, int64_t ncols, double* anc, hipStream_t st);
 

@@ -494,226 +494,6 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
 }
 
 // --------------------------------------------------------------------------
-// FP32 collecting pass with a block filter (the diagonal pass of the collecting
-// mode when FP32 items run under their rounding bound).
-//
-// Same work items, recurrence, anchors, queue entries and per-cell rule as
-// k_pass<float, K, MODE_APPEND>; the step filter and the column data differ.
-// A lane's K cells at a step all lie in the 2K - 1 columns of its block (rows ib
-// .. ib + K - 1, columns ib + dl .. ib + dl + 2K - 2), so one upper bound per
-// step covers them: with Cmax = max_q C_q and inv^ the largest inverse norm of
-// those columns (window extrema, one load per block),
-//   fl(Cmax inv^) >= fl(C_q invn_j)   for every cell with C_q >= 0,
-// and the test fma(fl(Cmax inv^), invn_i, delta) >= min(thr^, thr_i) keeps every
-// step that the per-cell filter keeps, where thr^ is the smallest threshold of
-// the block's columns. Cells with C_q < 0 have a negative correlation, which
-// can reach only a threshold at or below the bound delta; thresholds at or below
-// kLowThr (> any delta the FP32 pass accepts) enter the filter as -inf, so such
-// owners pass every step and the per-cell rule decides. Only the recurrence
-// inputs of the columns sit in registers; the slow path loads the inverse norms
-// and thresholds of its cells, so the kernel needs about half the registers of
-// k_pass (twice the resident wavefronts) and a third fewer VALU instructions per
-// step.
-constexpr float kLowThr = 0.0625f;
-
-// ext[j] = (min over columns j .. j + W - 1 of thrf, max of their inverse
-// norms, NaN skipped, 0 if none), thrf[j] = the filter threshold of owner j (its
-// FP32 threshold, or -inf at or below kLowThr), for j < nout. Reads up to
-// nout + W - 1 entries of the padded arrays.
-template <int W>
-__global__ void k_filter_window(const float* __restrict__ thr32, const float* __restrict__ inv32, int64_t nout,
-                                float2* __restrict__ ext, float* __restrict__ thrf) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nout) return;
-  float tm = INFINITY, im = 0.0f;
-#pragma unroll
-  for (int c = 0; c < W; ++c) {
-    const float t = thr32[j + c];
-    tm = fminf(tm, t > kLowThr ? t : -INFINITY);
-    const float v = inv32[j + c];
-    im = v > im ? v : im;  // NaN (flat or padding) never wins
-  }
-  ext[j] = make_float2(tm, im);
-  const float t0 = thr32[j];
-  thrf[j] = t0 > kLowThr ? t0 : -INFINITY;
-}
-
-template <int K>
-__global__ __launch_bounds__(kWave) void k_collect32(const float* __restrict__ g_df, const float* __restrict__ g_dg,
-                                                     const float* __restrict__ g_invn, const float* __restrict__ g_thr,
-                                                     const float2* __restrict__ g_ext,
-                                                     const float* __restrict__ g_thrf,
-                                                     const double* __restrict__ g_xs,
-                                                     const double* __restrict__ g_anc,
-                                                     const double* __restrict__ g_A, PassArgs a) {
-  static_assert(K % 4 == 0, "run loads need K multiple of 4");
-  constexpr int64_t BW = (int64_t)kWave * K;
-  constexpr int HK = K / 2;
-  constexpr int kQueue = 4 * kWave;  // four steps of entries (at most one per lane and step)
-  __shared__ int32_t q_owner[kQueue];
-  __shared__ uint32_t q_val[kQueue];
-  const int t = threadIdx.x;
-  const int64_t N = a.N;
-  const int64_t seg = blockIdx.x, band = blockIdx.y;
-  const int64_t d0 = a.dstart + band * BW;
-  if (d0 > N - 1) return;
-  const int64_t i0 = seg * a.H;
-  const int64_t rowEnd = N - d0;
-  if (i0 >= rowEnd) return;
-  float delta = 0.0f;
-  if (a.delta) {
-    const float dl_ = a.delta[seg * a.bands + band];
-    if (!(dl_ <= a.delta_max)) return;  // left to the FP64 kernel
-    delta = dl_;
-  }
-  const int rows = (int)((i0 + a.H < rowEnd ? i0 + a.H : rowEnd) - i0);
-  const int64_t dl = d0 + (int64_t)K * t;
-
-  float C[K];
-  {
-    double S[K], Aj[K];
-    if (g_anc)
-      load_run<K>(g_anc + seg * a.anc_stride + (dl - a.dstart), S);
-    else
-      direct_sums_ahead<K>(g_xs, i0, i0 + dl, a.L, S);
-    load_run<K>(g_A + i0 + dl, Aj);
-    const double Ai = g_A[i0] / (double)a.L;
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-      const int64_t j = i0 + dl + q;
-      C[q] = (dl + q > a.e && j < N) ? (float)(S[q] - Ai * Aj[q]) : -INFINITY;
-    }
-  }
-  // column window of the recurrence inputs (two register sets, as in k_pass)
-  float Xdf[K], Xdg[K], Ydf[K], Ydg[K];
-  {
-    const int64_t c0 = i0 + dl;
-    load_run<K>(g_df + c0, Xdf);
-    load_run<K>(g_dg + c0, Xdg);
-    load_run<K>(g_df + c0 + K, Ydf);
-    load_run<K>(g_dg + c0 + K, Ydg);
-  }
-  float2 ext = g_ext[i0 + dl];
-  int qn = 0;
-  unsigned long long ev_steps = 0;
-
-  auto flush = [&]() {
-    __syncthreads();
-    unsigned long long hits = 0;
-    for (int b = 0; b < qn; b += kWave) {
-      if (b + t < qn) {
-        const int32_t own = q_owner[b + t];
-        const uint32_t v = q_val[b + t];
-        const int64_t j0 = (int64_t)own + d0 + (int64_t)K * (int64_t)(v & 63u);
-        uint32_t m = v >> 6;
-        while (m) {
-          const int q = __ffs(m) - 1;
-          m &= m - 1;
-          const bool col = q < K;
-          const int64_t j = j0 + (col ? q : q - K);
-          const int64_t o = col ? j : (int64_t)own;
-          const uint32_t pos = atomicAdd(&a.cnt[o], 1u);
-          if ((int64_t)pos < a.cap) a.buf[o * a.cap + pos] = (int32_t)(col ? (int64_t)own : j);
-          hits += 1;
-        }
-      }
-    }
-    if (a.events) {
-#pragma unroll
-      for (int m = kWave / 2; m >= 1; m >>= 1) hits += shfl_xor_u64(hits, m);
-      if (t == 0 && hits) atomicAdd(&a.events[1], hits);
-    }
-    __syncthreads();
-    qn = 0;
-  };
-
-  auto block = [&](int64_t ib, float* Pdf, float* Pdg, float* Qdf, float* Qdg) {
-    float rdf[K], rdg[K], rinv[K], rthf[K];
-#pragma unroll
-    for (int u = 0; u < K; ++u) {
-      rdf[u] = g_df[ib + u];
-      rdg[u] = g_dg[ib + u];
-      rinv[u] = g_invn[ib + u];
-      rthf[u] = g_thrf[ib + u];
-    }
-    const float2 ext_next = g_ext[ib + K + dl];  // the next block's window extrema
-    const int64_t cn = ib + dl + 2 * K;
-#pragma unroll
-    for (int u = 0; u < K; ++u) {
-      const int64_t i = ib + u;
-      // co-moments are never NaN (finite, or -inf on trivial and past-the-end
-      // diagonals), so the NaN-propagating maximum is exact and needs no quieting
-      float m[K];
-#pragma unroll
-      for (int q = 0; q < K; ++q) m[q] = C[q];
-#pragma unroll
-      for (int w = 1; w < K; w *= 2)
-#pragma unroll
-        for (int q = 0; q + w < K; q += 2 * w) m[q] = __builtin_elementwise_maximum(m[q], m[q + w]);
-      const bool any_pass = __builtin_expect(
-          __any(fma(m[0] * ext.y, rinv[u], delta) >= __builtin_elementwise_minimum(ext.x, rthf[u])), 0);
-      if (any_pass) {
-        ++ev_steps;
-        // the per-cell rule of the collecting mode (thresholds lowered by the
-        // bound; flat and padded windows have a NaN inverse norm and fail), four
-        // cells at a time
-        const float rlow = g_thr[i] - delta;
-        uint32_t cm = 0, rm = 0;
-#pragma unroll
-        for (int h = 0; h < K; h += 4) {
-          float inv[4], thc[4];
-          load_run<4>(g_invn + i + dl + h, inv);
-          load_run<4>(g_thr + i + dl + h, thc);
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const float rho = (C[h + k] * inv[k]) * rinv[u];
-            cm |= (uint32_t)(rho >= thc[k] - delta) << (h + k);
-            rm |= (uint32_t)(rho >= rlow) << (h + k);
-          }
-          // one half's loads in flight at a time: the half's values are consumed
-          // here, and no later load moves above this point
-          asm volatile("" ::"v"(cm), "v"(rm) : "memory");
-        }
-        const uint32_t mask = cm | (rm << K);
-        if (qn + kWave > kQueue) flush();
-        const bool want = mask != 0;
-        const uint64_t bm = __ballot(want);
-        if (want) {
-          const int pos = qn + __popcll(bm & ((uint64_t(1) << t) - 1));
-          q_owner[pos] = (int32_t)i;
-          q_val[pos] = (uint32_t)t | (mask << 6);
-        }
-        qn += __popcll(bm);
-      }
-#pragma unroll
-      for (int q = 0; q < K; ++q) {
-        const int s = (q + u) % K;
-        const float cdf = s < u ? Qdf[s] : Pdf[s];
-        const float cdg = s < u ? Qdg[s] : Pdg[s];
-        C[q] = fma(rdf[u], cdg, C[q]);
-        C[q] = fma(cdf, rdg[u], C[q]);
-      }
-      if (u == HK - 1) {
-        load_run<HK>(g_df + cn, Pdf);
-        load_run<HK>(g_dg + cn, Pdg);
-      } else if (u == K - 1) {
-        load_run<HK>(g_df + cn + HK, Pdf + HK);
-        load_run<HK>(g_dg + cn + HK, Pdg + HK);
-      }
-    }
-    ext = ext_next;
-  };
-
-  for (int sb = 0; sb < rows; sb += 2 * K) {
-    block(i0 + sb, Xdf, Xdg, Ydf, Ydg);
-    if (sb + K < rows) block(i0 + sb + K, Ydf, Ydg, Xdf, Xdg);
-  }
-  if (qn > 0) flush();
-  if (a.events && t == 0 && ev_steps) atomicAdd(&a.events[0], ev_steps);
-  if (a.anc_next) grow_anchors<K>(g_xs, a.anc_next + seg * a.anc_stride - a.dstart, i0, d0, N, a.L);
-}
-
-// --------------------------------------------------------------------------
 // Rounding bounds of the recurrence per work item (recurrence_bound: H = the
 // segment height, Phi and Psi from the per-64-window extrema of sigma sqrt(L),
 // |df| and |dg| of the item's rows and columns, flat windows excluded). The
@@ -878,18 +658,6 @@ static hipError_t launch_pass_k(const PassLaunch& p, hipStream_t st) {
     }
   }
   const dim3 grid((unsigned)g.segs, (unsigned)g.bands);
-  if constexpr (sizeof(T) == 4) {
-    if (p.append && p.ext && p.thrf) {
-      const float2* ext = p.ext;
-      const float* thrf = p.thrf;
-      if (p.ev_start || p.ev_stop)
-        hipExtLaunchKernelGGL(k_collect32<K>, grid, dim3(kWave), 0, st, p.ev_start, p.ev_stop, 0, df, dg, inv, thr,
-                              ext, thrf, p.xs, p.anc, p.A, a);
-      else
-        k_collect32<K><<<grid, kWave, 0, st>>>(df, dg, inv, thr, ext, thrf, p.xs, p.anc, p.A, a);
-      return hipGetLastError();
-    }
-  }
   if (p.ev_start || p.ev_stop) {
     if (p.append)
       hipExtLaunchKernelGGL(k_pass<T, K, MODE_APPEND, false>, grid, dim3(kWave), 0, st, p.ev_start, p.ev_stop, 0, df,
@@ -914,20 +682,6 @@ hipError_t launch_pass(const PassLaunch& p, hipStream_t st) {
   if (p.K == 8) return launch_pass_k<double, 8>(p, st);
   if (p.K == 4) return launch_pass_k<double, 4>(p, st);
   return hipErrorInvalidValue;
-}
-
-hipError_t launch_filter_window(const float* thr32, const float* inv32, int64_t N, int K, float2* ext, float* thrf,
-                                hipStream_t st) {
-  // the pass reads ext up to N + 64 K - 1 (K <= 8) and thrf below N + K
-  static_assert(kFilterWindowAhead >= (int64_t)kWave * 8, "window extrema must cover the pass's reads");
-  const int64_t nout = N + kFilterWindowAhead;
-  if (K == 8)
-    k_filter_window<15><<<blocks_for(nout, 256), 256, 0, st>>>(thr32, inv32, nout, ext, thrf);
-  else if (K == 4)
-    k_filter_window<7><<<blocks_for(nout, 256), 256, 0, st>>>(thr32, inv32, nout, ext, thrf);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
 }
 
 hipError_t launch_item_bounds(const float* bsw_max, const float* bsw_min, const float* bdf_max, const float* bdg_max,

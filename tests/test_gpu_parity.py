@@ -283,51 +283,6 @@ def test_fp32_refresh_equals_fp64():
         assert np.array_equal(a[key], b[key], equal_nan=True), key
 
 
-def _block_filter_inputs():
-    rw = gen.small_random_walk(6000, 74, np.float32)
-    flats = gen.small_random_walk(5000, 75) + 1.0e4
-    flats[900:1500] = flats[900]
-    flats[3000:3100] = flats[3000]
-    return {
-        "random walk p=10": (rw, 40, 48, 10),
-        "offset 1e4 with flats p=5": (flats.astype(np.float32), 30, 38, 5),
-        # p >= N - 1: every owner collects every candidate (thresholds below
-        # -1), the case that enters the block filter as -inf
-        "collect all": (gen.small_random_walk(260, 76, np.float32), 20, 24, 300),
-        # white noise: low correlations and many candidates per owner
-        "white noise p=40": (np.random.default_rng(20080077).standard_normal(3000).astype(np.float32), 16, 20, 40),
-    }
-
-
-@pytest.mark.parametrize("case", list(_block_filter_inputs()))
-def test_block_filter_matches_cell_filter(oracle_mod, monkeypatch, case):
-    """The FP32 collecting pass with the block filter (one bound per lane and
-    step from the block's window extrema) and with the per-cell filter give
-    bitwise equal outputs, which match the oracle. Both filters keep every cell
-    whose exact correlation reaches its threshold, and both passes apply the
-    same per-cell rule; the rule's threshold is lowered by the rounding bound, so
-    it also accepts some cells within an ulp below, which one filter may keep
-    and the other drop: the append counts may differ by such cells only."""
-    from oracle import compare
-
-    x, lo, hi, p = _block_filter_inputs()[case]
-    outs = []
-    for bf in ("1", "0"):
-        monkeypatch.setenv("VALMOD_BLOCK_FILTER", bf)
-        _say(f"block filter {bf}: {case}")
-        outs.append(run_gpu(x, lo, hi, p=p, k_motifs=3, k_discords=3, path="full", precision="fp32"))
-    a, b = outs
-    appends = 5  # stats column: candidates appended by the collecting passes
-    na, nb = a["stats"][:, appends], b["stats"][:, appends]
-    assert (np.abs(na - nb) <= np.maximum(8, nb // 100000)).all(), (na, nb)
-    for key in ("prof_dist", "prof_idx", "valmp_norm", "valmp_dist", "valmp_len", "valmp_idx", "motif_ab",
-                "motif_d", "discord_on", "discord_d", "g_motif_abl", "g_motif_d", "g_discord_onl", "g_discord_d"):
-        assert np.array_equal(a[key], b[key], equal_nan=True), key
-    _say(f"{case}: slow-path steps {a['stats'][:, 6].sum()} (block) vs {b['stats'][:, 6].sum()} (cell)")
-    r = oracle_mod.valmod(x, lo, hi, k_motifs=3, k_discords=3)
-    compare.check_full(x, lo, a, r, TOL64)
-
-
 def test_config2_fp32_sampled_parity(oracle_mod):
     from oracle import compare
 
