@@ -155,7 +155,9 @@ enum {
   VALMOD_STAT_MTH_RECOMPUTED = 12, /* windows whose m best matches a top-m row scan recomputes */
   VALMOD_STAT_MTH_PRUNED = 13,     /* uncertified windows the top-k cutoff leaves out of the
                                       m-th discord rankings (their best match stays exact) */
-  VALMOD_NSTATS = 14
+  VALMOD_STAT_OVERFLOWED = 14,     /* at a length that rebuilds the partial profiles: windows whose
+                                      candidate list of the pass with p thresholds overflowed */
+  VALMOD_NSTATS = 15
 };
 
 /*

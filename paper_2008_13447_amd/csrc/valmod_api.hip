@@ -19,8 +19,11 @@ using namespace valmod;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int64_t kRingRows = 32;
-constexpr int kErrSlot = 7;  // slot of a lane's pinned host words that receives its device error flag  // profile rows kept in the workspace (rankings run per group of rows)
+constexpr int64_t kRingRows = 32;  // profile rows kept in the workspace (rankings run per group of rows)
+// a lane's pinned host words: 0-5 NFAIL .. MINLB and 6 MOPEN after a sweep, then
+constexpr int kErrSlot = 7;   // the device error flag
+constexpr int kOverSlot = 8;  // the last rebuild's overflowing lists (CNT_OVER)
+constexpr int kHostWords = 16;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -28,6 +31,7 @@ struct WsLayout {
   size_t xs, A, B, A2, B2, mu, sig, invn, flat, df, dg, sw32, thr, thr32, best, counters, anc;
   size_t hc, hS, hn, hbound, hsig, hflat, acnt, abuf, fail, big, lbm, rec, part, mvals, mnn, mkeys;
   size_t mstate, mub, mlist, tau_on, tau_d;
+  size_t thrp;  // thresholds of a rebuild from the partial profiles it replaces
   size_t df32, dg32, inv32, bsw_max, bsw_min, bdf_max, bdg_max, bmu_max, delta64, delta, hard;
   size_t ms_keys0, ms_keys1, ms_vals0, ms_vals1, ms_hist, ms_meta, ms_count, ms_taken, ms_bucket;
   // the last ring_rows profile rows (distance, index; stride N0 of the series):
@@ -223,6 +227,7 @@ static size_t layout_lane(const valmod_plan_s* P, Lane& ln) {
   w.hbound = take(wp * 8);
   w.hsig = take(wp * 8);
   w.hflat = take(wp);
+  w.thrp = take(wp * 8);
   w.acnt = take(wp * 4);
   w.abuf = take((size_t)ln.n0max * (size_t)P->cap * 4);
   w.fail = take(wp * 4);
@@ -532,7 +537,7 @@ static hipError_t ensure_resources(valmod_plan_s* P) {
   for (Lane& ln : P->lanes) {
     ok(hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking));
     for (hipEvent_t* ev : {&ln.ready, &ln.done}) ok(hipEventCreateWithFlags(ev, hipEventDisableTiming));
-    ok(hipHostMalloc((void**)&ln.hcnt, 8 * sizeof(unsigned long long), hipHostMallocDefault));
+    ok(hipHostMalloc((void**)&ln.hcnt, kHostWords * sizeof(unsigned long long), hipHostMallocDefault));
     for (int64_t i = 0; e == hipSuccess && i < 4 * ln.total_lengths; ++i) {
       hipEvent_t ev;
       if (ok(hipEventCreate(&ev))) ln.ev.push_back(ev);
@@ -564,6 +569,7 @@ struct LaneRun {
   uint8_t* flat;
   float *sw32, *thr32, *df32, *dg32, *inv32, *bsw_max, *bsw_min, *bdf_max, *bdg_max, *bmu_max, *delta64, *delta;
   uint8_t* hflat;
+  double* thrp;
   uint64_t* best;
   unsigned long long* cnt;
   int32_t *hc, *hn, *abuf, *fail, *big, *hard, *rec, *part, *mnn;
@@ -647,6 +653,7 @@ struct LaneRun {
     bmu_max = (float*)(b + w.bmu_max);
     delta64 = (float*)(b + w.delta64);
     hflat = (uint8_t*)(b + w.hflat);
+    thrp = (double*)(b + w.thrp);
     ring_d = (double*)(b + w.ring_d);
     ring_i = (int32_t*)(b + w.ring_i);
     ring_rows = w.ring_rows;
@@ -761,10 +768,6 @@ LaneRun::Status LaneRun::advance() {
     ms_.hbound = hbound;
     ms_.hsig = hsig;
     ms_.rflat = &cnt[CNT_RFLAT];
-    ms_.thr = thr;
-    ms_.acnt = acnt;
-    ms_.cap = P->cap;
-    ms_.dmax = &cnt[CNT_DMAX];
     ms_.fresh = fresh ? 1 : 0;
     ms_.p = p;
     ms_.m = md;
@@ -858,6 +861,8 @@ LaneRun::Status LaneRun::advance() {
       // NFAIL, VALID, HARD, BIG, MINDIST, MINLB (and MOPEN)
       LCHECK(hipMemcpyAsync(ln->hcnt, &cnt[CNT_NFAIL], 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
       if (md > 1) LCHECK(hipMemcpyAsync(ln->hcnt + 6, &cnt[CNT_MOPEN], sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+      LCHECK(hipMemcpyAsync(ln->hcnt + kOverSlot, &cnt[CNT_OVER], sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            st));
       LCHECK(hipEventRecord(ln->ready, st));
       phase = 1;
       return BLOCKED;
@@ -923,6 +928,8 @@ LaneRun::Status LaneRun::advance() {
   // collecting pass above per-owner thresholds from the candidates of `src`,
   // then the exact merge (top-`keep` partial profiles and best keys)
   bool fail_reset = sweep;  // the sweep's recompute list, replaced by the first collecting pass
+  bool tighten = false;     // the collecting pass with p thresholds takes the replaced profiles' thresholds too
+  bool count_over = false;  // that pass counts the owners whose list overflows (CNT_OVER)
   auto collect = [&](const int32_t* src, int p_eff, int keep, int best_exact) -> hipError_t {
     // the wavefront-per-owner merge list is rebuilt by every collecting pass (a
     // length may run two); the recompute list keeps the owners listed so far at
@@ -933,6 +940,8 @@ LaneRun::Status LaneRun::advance() {
     if (e1 == hipSuccess)
       e1 = launch_seed_append(xs, A, invn, flat, src, N, L, e, p_eff, p_eff == 1 ? 0 : D, margin, best_exact, thr,
                               fp32 ? thr32 : nullptr, acnt, fail, &cnt[CNT_NFAIL], st);
+    if (e1 == hipSuccess && tighten && p_eff == p)
+      e1 = launch_tighten_threshold(thrp, N, thr, fp32 ? thr32 : nullptr, st);
     PassLaunch q = pl;
     q.append = true;
     q.grow = grow_collect;
@@ -963,7 +972,7 @@ LaneRun::Status LaneRun::advance() {
     if (e1 == hipSuccess)
       e1 = launch_merge(xs, A, invn, sig, flat, thr, acnt, abuf, P->cap, N, L, p, keep, margin, best_exact, hc, hS,
                         hn, hbound, hsig, hflat, best, fail, &cnt[CNT_NFAIL], big, &cnt[CNT_BIG], &cnt[CNT_APPENDS],
-                        st);
+                        count_over && p_eff == p ? &cnt[CNT_OVER] : nullptr, st);
     recompute = true;
     return e1;
   };
@@ -1040,18 +1049,37 @@ LaneRun::Status LaneRun::advance() {
       src = ri;
     }
     if (rebuild) {
-      // exact neighbours first (a list of one threshold rarely overflows), so that
-      // the owners whose partial-profile list overflows keep them: on periodic
-      // series the p-th best seed is far below the p-th best candidate, and the
-      // lists of nearly all owners overflow
-      grow_collect = false;
-      LCHECK(collect(src, 1, 0, 0));
-      LCHECK(launch_keys_to_idx(best, N, ri, st));
-      src = ri;
+      // thresholds from the partial profiles being replaced (the sweep grew their
+      // sums to L; an overflowed list left the best p of its first candidates),
+      // taken before a collecting pass overwrites the profiles. Once a rebuild has
+      // run with them, few lists of the pass with p thresholds overflow: that pass
+      // alone then gives the exact neighbours (the owners whose list overflows go
+      // to the row recompute) when the previous rebuild's overflowing lists would
+      // cost less to recompute than a full pass
+      bool one = false;
+      if (sweep) {
+        LCHECK(launch_profile_threshold(A, invn, flat, hc, hS, hn, p, N, L, e, margin, thrp, st));
+        tighten = true;
+        const double over_rows = (double)ln->hcnt[kOverSlot];
+        one = md == 1 && over_rows * (double)N * (double)L <= rec_factor * 0.5 * (double)N * (double)N;
+      }
+      LCHECK(launch_zero_counters(&cnt[CNT_OVER], 1, st));
+      count_over = true;
+      if (!one) {
+        // exact neighbours first (a list of one threshold rarely overflows), so
+        // that the owners whose partial-profile list overflows keep them: on
+        // periodic series the p-th best seed is far below the p-th best
+        // candidate, and without the replaced profiles' thresholds the lists of
+        // nearly all owners overflow
+        grow_collect = false;
+        LCHECK(collect(src, 1, 0, 0));
+        LCHECK(launch_keys_to_idx(best, N, ri, st));
+        src = ri;
+      }
       grow_collect = grow;
-      // new partial profiles at base L (Alg. ComputeMatrixProfile); `best` already
-      // holds the exact neighbours
-      LCHECK(collect(src, p, p, 1));
+      // new partial profiles at base L (Alg. ComputeMatrixProfile); with two
+      // passes `best` already holds the exact neighbours
+      LCHECK(collect(src, p, p, one ? 0 : 1));
       base = L;
       probe_next = true;
       if (md > 1) mth = 2;
@@ -1078,12 +1106,7 @@ LaneRun::Status LaneRun::advance() {
     // match the sweep did not certify.
     const int kd = P->cfg.k_discords;
     const bool fresh = mth == 2;
-    if (fresh) {
-      LCHECK(bounds_setup());
-      LCHECK(launch_max_delta(delta64, fp32 ? delta : nullptr, N, e, G.dstart, G.K, G.H, delta_max, &cnt[CNT_DMAX],
-                              st));
-      LCHECK(mth_select(true));
-    }
+    if (fresh) LCHECK(mth_select(true));
     LCHECK(launch_mth_rankings(mvals, mnn, N0, n, L, md, excl_den, kd, tau_on, tau_d, st, 2));
     if (!fresh) LCHECK(launch_zero_counters(&cnt[CNT_NFAIL], 1, st));
     LCHECK(launch_mth_prune(mstate, mub, tau_d, N, N0, md, kd, fresh ? 1 : 0, mlist, &cnt[CNT_MREC], fail,
@@ -1119,7 +1142,8 @@ LaneRun::Status LaneRun::advance() {
                            mot_ab + 2 * t0 * km, mot_d + t0 * km, dis_on + 2 * t0 * kd, dis_d + t0 * kd, st));
   }
   LCHECK(launch_record_stats(cnt, o->stats ? o->stats + Ls.stats + t * VALMOD_NSTATS : nullptr, full ? 1 : 0,
-                             nvalid, nswept_fail, paper_split == 1 ? 2 : (recompute ? 1 : 0), passes, st));
+                             nvalid, nswept_fail, paper_split == 1 ? 2 : (recompute ? 1 : 0), passes,
+                             rebuild ? 1 : 0, st));
   // VALMOD_PROGRESS=k: one line on stderr every k lengths, once the length has run
   const int progress = capture || noalloc ? 0 : env_int("VALMOD_PROGRESS", 0);
   if (progress > 0 && (t % progress == 0 || L == Ls.l_max)) {

@@ -214,7 +214,7 @@ __global__ __launch_bounds__(kWave) void k_merge_small(
     int keep, double margin, int best_exact, int32_t* __restrict__ hc, double* __restrict__ hS, int32_t* __restrict__ hn,
     double* __restrict__ hbound, double* __restrict__ hsig, uint8_t* __restrict__ hflat, uint64_t* __restrict__ best,
     int32_t* __restrict__ fail, unsigned long long* __restrict__ nfail, int32_t* __restrict__ big,
-    unsigned long long* __restrict__ nbig) {
+    unsigned long long* __restrict__ nbig, unsigned long long* __restrict__ nover) {
   const int t = threadIdx.x, l = t % kSmallG, gb = t - l;
   const int64_t o = (int64_t)blockIdx.x * (kWave / kSmallG) + t / kSmallG;
   const bool live = o < N;
@@ -260,8 +260,9 @@ __global__ __launch_bounds__(kWave) void k_merge_small(
   double nb = (ok && rank == keep) ? rho : -4.0;  // the best collected candidate not kept
 #pragma unroll
   for (int msk = kSmallG / 2; msk >= 1; msk >>= 1) nb = fmax(nb, __shfl_xor(nb, msk, kWave));
+  if (nover) count_wave(live && !skip && m > cap && keep > 0 && l == 0, nover);
   if (!live) return;
-  if (skip || m == 0 || m > cap || m > kMergeCap) {
+  if (skip || m == 0 || (m > cap && keep == 0)) {
     // no partial profile: an empty one whose bound is 0 (bound correlation 1),
     // so that the sweep of a later length never certifies from stale data
     if (l == 0) {
@@ -275,6 +276,23 @@ __global__ __launch_bounds__(kWave) void k_merge_small(
         best[o] = kEmptyKey;
         push_fail(fail, nfail, o);
       }
+    }
+    return;
+  }
+  if (m > cap) {
+    // overflow: the list holds the first cap candidates collected, not the best
+    // ones. The exact neighbour comes from elsewhere (best_exact) or the recompute
+    // list; k_merge_big keeps the best p of the cap as a profile that no sweep
+    // certifies (bound correlation 1) but whose candidates give a later rebuild
+    // its thresholds (any p real candidates bound the p-th best from below)
+    if (l == 0) {
+      hflat[o] = 0;
+      if (!best_exact) {
+        best[o] = kEmptyKey;
+        push_fail(fail, nfail, o);
+      }
+      const unsigned long long pos = atomicAdd(nbig, 1ull);
+      if ((int64_t)pos < N) big[pos] = (int32_t)o;
     }
     return;
   }
@@ -320,7 +338,9 @@ __global__ __launch_bounds__(kWave) void k_merge_big(
   const int64_t count = listed < N ? listed : N;  // the list has N entries
   for (int64_t w = blockIdx.x; w < count; w += gridDim.x) {
     const int64_t o = big[w];
-    const int64_t m = cnt[o];  // kSmallG < m <= cap
+    const int64_t mc = cnt[o];        // kSmallG < mc <= cap, or an overflowed list (mc > cap)
+    const bool over = mc > cap;       // the list holds its first cap candidates
+    const int64_t m = over ? cap : mc;
     const double Ao = A[o], io = invn[o];
     const int32_t* list = buf + o * cap;
     for (int64_t r = t; r < m; r += kWave) {
@@ -341,13 +361,13 @@ __global__ __launch_bounds__(kWave) void k_merge_big(
         hc[o * p + rank] = (int32_t)key_cand(k);
         hS[o * p + rank] = ssum[r];
       }
-      if (rank == 0) best[o] = k;
+      if (rank == 0 && !over) best[o] = k;
       if (rank == keep && srho[r] + margin > sbound) sbound = srho[r] + margin;  // a single lane has this rank
     }
     __syncthreads();
     if (t == 0) {
       hn[o] = (int32_t)(m < keep ? m : keep);
-      hbound[o] = sbound;
+      hbound[o] = over ? 2.0 : sbound;  // overflowed: candidates outside the list are unbounded
       hsig[o] = sig[o];
     }
     __syncthreads();  // the LDS lists are reused by the next owner
@@ -650,8 +670,7 @@ __global__ void k_mth_select(const double* __restrict__ A, const double* __restr
                              const int32_t* __restrict__ hc, const double* __restrict__ hS,
                              const int32_t* __restrict__ hn, const double* __restrict__ hbound,
                              const double* __restrict__ hsig, const unsigned long long* __restrict__ rflat,
-                             const double* __restrict__ thr, const uint32_t* __restrict__ acnt, int64_t cap,
-                             const unsigned long long* __restrict__ dmax, int fresh, int p, int m, int64_t N,
+                             int fresh, int p, int m, int64_t N,
                              int64_t N0, int L, int64_t e, int base, double margin, double* __restrict__ vals,
                              int32_t* __restrict__ nn, double* __restrict__ ub, uint8_t* __restrict__ mstate,
                              unsigned long long* __restrict__ n_open) {
@@ -694,15 +713,10 @@ __global__ void k_mth_select(const double* __restrict__ A, const double* __restr
       if (j == m - 1) cert_m = ok;
     }
     if (cnt < m) cert_m = lb == INFINITY;  // a complete profile: the owner has no more candidates
-    double uo = INFINITY;                    // bound of the missing entries
-    if (fresh && nh == 0 && cap >= m && (int64_t)acnt[o] > cap && thr[o] >= -1.0) {
-      const double dm = (double)__uint_as_float((uint32_t)*dmax);
-      uo = dist(1.0 - thr[o] + 2.0 * dm + 0x1p-21 + margin);
-    }
     for (int j = cnt; j < m; ++j) {
       vals[(int64_t)j * N0 + o] = INFINITY;
       nn[(int64_t)j * N0 + o] = -1;
-      ub[(int64_t)j * N0 + o] = uo;
+      ub[(int64_t)j * N0 + o] = INFINITY;
     }
     if (!cert_m)
       for (int j = 0; j < cnt; ++j) {  // no entry until the owner is resolved
@@ -786,7 +800,7 @@ hipError_t launch_mth_select(const MthSelect& a, hipStream_t st) {
   if (a.N <= 0) return hipSuccess;
   if (a.m < 1 || a.m > a.p) return hipErrorInvalidValue;
   k_mth_select<<<blocks_for(a.N, 128), 128, 0, st>>>(a.A, a.invn, a.sig, a.flat, a.hc, a.hS, a.hn, a.hbound, a.hsig,
-                                                     a.rflat, a.thr, a.acnt, a.cap, a.dmax, a.fresh, a.p, a.m, a.N,
+                                                     a.rflat, a.fresh, a.p, a.m, a.N,
                                                      a.N0, a.L, a.e, a.base, a.margin, a.vals, a.nn, a.ub, a.mstate,
                                                      a.n_open);
   return hipGetLastError();
@@ -852,6 +866,65 @@ hipError_t launch_mth_values(const double* A, const double* invn, const uint8_t*
   return hipGetLastError();
 }
 
+// --------------------------------------------------------------------------
+// Thresholds of a rebuild from the partial profiles it replaces. After the sweep
+// at L, an owner whose profile holds p candidates all still eligible at L has p
+// real candidates with correlations evaluated from their sums (error <= margin):
+// the smallest of them, lowered by the margin, is at most the owner's true p-th
+// largest correlation, so it is a valid threshold for the collecting pass with p
+// thresholds, and on periodic series a far tighter one than the p-th best seed.
+// thrp[o] = that value, or -inf when the profile cannot give one.
+__global__ void k_profile_threshold(const double* __restrict__ A, const double* __restrict__ invn,
+                                    const uint8_t* __restrict__ flat, const int32_t* __restrict__ hc,
+                                    const double* __restrict__ hS, const int32_t* __restrict__ hn, int p, int64_t N,
+                                    int L, int64_t e, double margin, double* __restrict__ thrp) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= N) return;
+  double t = -INFINITY;
+  if (!flat[o] && hn[o] == p) {
+    const double Ao = A[o], io = invn[o];
+    double lo = INFINITY;
+    bool all = true;
+    for (int r = 0; r < p && all; ++r) {
+      const int64_t c = hc[o * p + r];
+      all = c < N && iabs64(c - o) > e && !flat[c];
+      if (all) lo = fmin(lo, rho_from_sum(hS[o * p + r], Ao, A[c], L, io, invn[c]));
+    }
+    if (all) t = lo - margin;
+  }
+  thrp[o] = t;
+}
+
+// the collecting thresholds raised to the profile thresholds (both are at most
+// the true p-th largest correlation, so their maximum is as well); an owner that
+// the seeding left without a threshold (no eligible seed) takes the profile's
+__global__ void k_tighten_threshold(const double* __restrict__ thrp, int64_t N, double* __restrict__ thr,
+                                    float* __restrict__ thr32) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= N) return;
+  const double tp = thrp[o];
+  if (!(tp > -INFINITY)) return;
+  const double t = thr[o];
+  if (t >= 2.0 || tp > t) {
+    thr[o] = tp;
+    if (thr32) thr32[o] = __double2float_rd(tp);
+  }
+}
+
+hipError_t launch_profile_threshold(const double* A, const double* invn, const uint8_t* flat, const int32_t* hc,
+                                    const double* hS, const int32_t* hn, int p, int64_t N, int L, int64_t e,
+                                    double margin, double* thrp, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  k_profile_threshold<<<blocks_for(N, 256), 256, 0, st>>>(A, invn, flat, hc, hS, hn, p, N, L, e, margin, thrp);
+  return hipGetLastError();
+}
+
+hipError_t launch_tighten_threshold(const double* thrp, int64_t N, double* thr, float* thr32, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  k_tighten_threshold<<<blocks_for(N, 256), 256, 0, st>>>(thrp, N, thr, thr32);
+  return hipGetLastError();
+}
+
 hipError_t launch_seed_append(const double* xs, const double* A, const double* invn, const uint8_t* flat,
                               const int32_t* src, int64_t N, int L, int64_t e, int p, int D, double margin,
                               int best_exact, double* thr, float* thr32, uint32_t* cnt, int32_t* fail,
@@ -881,12 +954,12 @@ hipError_t launch_merge(const double* xs, const double* A, const double* invn, c
                         int p, int keep, double margin, int best_exact, int32_t* hc, double* hS, int32_t* hn,
                         double* hbound, double* hsig, uint8_t* hflat, uint64_t* best, int32_t* fail,
                         unsigned long long* nfail, int32_t* big, unsigned long long* nbig, unsigned long long* nappend,
-                        hipStream_t st) {
+                        unsigned long long* nover, hipStream_t st) {
   if (N <= 0) return hipSuccess;
   if (cap <= 0 || cap > kMergeCap || keep < 0 || keep > p) return hipErrorInvalidValue;
   k_merge_small<<<blocks_for(N, kWave / kSmallG), kWave, 0, st>>>(xs, A, invn, sig, flat, thr, cnt, buf, cap, N, L, p,
                                                                    keep, margin, best_exact, hc, hS, hn, hbound, hsig,
-                                                                   hflat, best, fail, nfail, big, nbig);
+                                                                   hflat, best, fail, nfail, big, nbig, nover);
   // a wavefront per listed owner; 4,096 workgroups fill the chip (the list is
   // walked in a grid-stride loop, so a short list costs little to dispatch)
   k_merge_big<<<(unsigned)(N < 4096 ? N : 4096), kWave, (size_t)cap * 3 * sizeof(double), st>>>(

@@ -26,7 +26,7 @@ enum CounterSlot {
   CNT_NPART = 12,    // paper mode: owners left partial
   CNT_RFLAT = 13,    // largest sigma_b / sigma_L of the windows flat at the base length but not at L (bits of a double)
   CNT_MOPEN = 14,    // m-th discords: owners whose m-list the partial profiles do not certify
-  CNT_DMAX = 15,     // largest rounding bound of the work items of the length's collecting passes (float bits)
+  CNT_OVER = 15,     // owners whose list overflowed in the last rebuild's collecting pass with p thresholds
   CNT_MREC = 16,     // m-th discords: owners listed for the top-m row recompute
   CNT_MCERT = 17,    // m-th discords: owners whose m-list the partial profiles certify
   CNT_MPRUNED = 18,  // m-th discords: uncertified owners left out by the top-k cutoff
@@ -122,7 +122,7 @@ hipError_t launch_finalize(const double* xs, const double* mu, const double* sig
 // `recomputed`: 0 none, 1 the recompute list (CNT_NFAIL), 2 the paper-mode list
 // (CNT_NREC)) and clears the per-length counters.
 hipError_t launch_record_stats(unsigned long long* cnt, int64_t* row, int full_pass, int64_t valid,
-                               int64_t failed, int recomputed, int64_t passes, hipStream_t st);
+                               int64_t failed, int recomputed, int64_t passes, int rebuilt, hipStream_t st);
 // sets n consecutive counters to v (a kernel, so that the sequence stays capturable)
 hipError_t launch_fill_counters(unsigned long long* p, int n, unsigned long long v, hipStream_t st);
 inline hipError_t launch_zero_counters(unsigned long long* p, int n, hipStream_t st) {
@@ -141,6 +141,12 @@ hipError_t launch_global_rank(const double* valmp_norm, const double* valmp_dist
 
 // partial distance profiles (valmod_heap.hip)
 // thr32 (optional): FP32 copy of each written threshold, rounded down
+// thresholds of a rebuild from the partial profiles it replaces (after the sweep):
+// thrp per owner, then the collecting thresholds raised to them
+hipError_t launch_profile_threshold(const double* A, const double* invn, const uint8_t* flat, const int32_t* hc,
+                                    const double* hS, const int32_t* hn, int p, int64_t N, int L, int64_t e,
+                                    double margin, double* thrp, hipStream_t st);
+hipError_t launch_tighten_threshold(const double* thrp, int64_t N, double* thr, float* thr32, hipStream_t st);
 hipError_t launch_seed_append(const double* xs, const double* A, const double* invn, const uint8_t* flat,
                               const int32_t* src, int64_t N, int L, int64_t e, int p, int D, double margin,
                               int best_exact, double* thr, float* thr32, uint32_t* cnt, int32_t* fail,
@@ -150,7 +156,7 @@ hipError_t launch_merge(const double* xs, const double* A, const double* invn, c
                         int p, int keep, double margin, int best_exact, int32_t* hc, double* hS, int32_t* hn,
                         double* hbound, double* hsig, uint8_t* hflat, uint64_t* best, int32_t* fail,
                         unsigned long long* nfail, int32_t* big, unsigned long long* nbig, unsigned long long* nappend,
-                        hipStream_t st);
+                        unsigned long long* nover, hipStream_t st);
 // lbm, min_dist, min_lb: optional (paper mode)
 hipError_t launch_sweep(const double* xs, const double* A, const double* invn, const double* sig, const uint8_t* flat,
                         int64_t N, int L, int64_t e, int p, int base, const int32_t* hc, double* hS, const int32_t* hn,
@@ -189,10 +195,6 @@ struct MthSelect {
   const int32_t *hc, *hn;
   const double *hS, *hbound, *hsig;
   const unsigned long long* rflat;  // CNT_RFLAT (read unless fresh)
-  const double* thr;                // collecting thresholds (read when fresh)
-  const uint32_t* acnt;             // collected candidates per owner (read when fresh)
-  int64_t cap;
-  const unsigned long long* dmax;   // CNT_DMAX (read when fresh)
   int fresh;                        // the partial profiles were rebuilt at this length
   int p, m;
   int64_t N, N0;
@@ -207,10 +209,6 @@ struct MthSelect {
   unsigned long long* n_open;
 };
 hipError_t launch_mth_select(const MthSelect& a, hipStream_t st);
-// largest rounding bound of the work items of the length's collecting passes
-// (after launch_item_bounds), atomically maxed into `out` (float bits)
-hipError_t launch_max_delta(const float* delta64, const float* delta32, int64_t N, int64_t e, int64_t dstart, int K,
-                            int64_t H, float dlim, unsigned long long* out, hipStream_t st);
 hipError_t launch_mth_prune(const uint8_t* mstate, const double* ub, const double* tau_d, int64_t N, int64_t N0,
                             int m, int kd, int best_exact, int32_t* mlist, unsigned long long* nmlist, int32_t* fail,
                             unsigned long long* nfail, unsigned long long* ncert, unsigned long long* npruned,

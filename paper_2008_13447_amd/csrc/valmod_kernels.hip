@@ -286,7 +286,7 @@ __global__ __launch_bounds__(128) void k_finalize(const double* __restrict__ xs,
 // Per-length diagnostic counters: copies the running device counters into the
 // stats row of length t and clears them.
 __global__ void k_record_stats(unsigned long long* __restrict__ cnt, int64_t* __restrict__ row, int full_pass,
-                               int64_t valid, int64_t failed, int recomputed, int64_t passes) {
+                               int64_t valid, int64_t failed, int recomputed, int64_t passes, int rebuilt) {
   if (threadIdx.x != 0) return;
   if (row) {
     row[0] = valid;
@@ -303,11 +303,12 @@ __global__ void k_record_stats(unsigned long long* __restrict__ cnt, int64_t* __
     row[11] = (int64_t)cnt[CNT_MCERT];
     row[12] = (int64_t)cnt[CNT_MREC];
     row[13] = (int64_t)cnt[CNT_MPRUNED];
+    row[14] = rebuilt ? (int64_t)cnt[CNT_OVER] : 0;  // CNT_OVER is kept until the next rebuild
   }
   cnt[CNT_NFLAT] = cnt[CNT_EV_STEPS] = cnt[CNT_EV_HITS] = cnt[CNT_APPENDS] = 0;
   cnt[CNT_NFAIL] = cnt[CNT_VALID] = cnt[CNT_HARD] = cnt[CNT_BIG] = 0;
   cnt[CNT_NREC] = cnt[CNT_NPART] = cnt[CNT_RFLAT] = 0;
-  cnt[CNT_MOPEN] = cnt[CNT_DMAX] = cnt[CNT_MREC] = cnt[CNT_MCERT] = cnt[CNT_MPRUNED] = 0;
+  cnt[CNT_MOPEN] = cnt[CNT_MREC] = cnt[CNT_MCERT] = cnt[CNT_MPRUNED] = 0;
 }
 
 __global__ void k_fill_counters(unsigned long long* __restrict__ p, int n, unsigned long long v) {
@@ -644,8 +645,8 @@ hipError_t launch_finalize(const double* xs, const double* mu, const double* sig
 }
 
 hipError_t launch_record_stats(unsigned long long* cnt, int64_t* row, int full_pass, int64_t valid,
-                               int64_t failed, int recomputed, int64_t passes, hipStream_t st) {
-  k_record_stats<<<1, 64, 0, st>>>(cnt, row, full_pass, valid, failed, recomputed, passes);
+                               int64_t failed, int recomputed, int64_t passes, int rebuilt, hipStream_t st) {
+  k_record_stats<<<1, 64, 0, st>>>(cnt, row, full_pass, valid, failed, recomputed, passes, rebuilt);
   return hipGetLastError();
 }
 

@@ -556,37 +556,6 @@ __global__ void k_item_bounds(const float* __restrict__ bsw_max, const float* __
   }
 }
 
-// Largest rounding bound any work item of the length's collecting passes ran
-// with: the FP32 bound of the items the FP32 pass takes (delta32 <= dlim), else
-// the FP64 bound. Written as the bits of a non-negative float (atomic max).
-__global__ __launch_bounds__(256) void k_max_delta(const float* __restrict__ d64, const float* __restrict__ d32,
-                                                   int64_t n, float dlim, unsigned long long* __restrict__ out) {
-  __shared__ float part[256 / kWave];
-  float m = 0.0f;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float v = (d32 && d32[i] <= dlim) ? d32[i] : d64[i];
-    m = fmaxf(m, v);
-  }
-#pragma unroll
-  for (int s = kWave / 2; s >= 1; s >>= 1) m = fmaxf(m, __shfl_xor(m, s, kWave));
-  if ((threadIdx.x % kWave) == 0) part[threadIdx.x / kWave] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < 256 / kWave; ++w) m = fmaxf(m, part[w]);
-    if (m > 0.0f) atomicMax(out, (unsigned long long)__float_as_uint(m));
-  }
-}
-
-hipError_t launch_max_delta(const float* delta64, const float* delta32, int64_t N, int64_t e, int64_t dstart, int K,
-                            int64_t H, float dlim, unsigned long long* out, hipStream_t st) {
-  const PassGrid g = pass_grid(N, e, dstart, K, H);
-  const int64_t n = g.segs * g.bands;
-  if (n <= 0) return hipSuccess;
-  const int64_t blocks = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
-  k_max_delta<<<(unsigned)blocks, 256, 0, st>>>(delta64, delta32, n, dlim, out);
-  return hipGetLastError();
-}
-
 PassGrid pass_grid(int64_t N, int64_t e, int64_t dstart, int K, int64_t H) {
   PassGrid g;
   const int64_t ndiag = N - 1 - e;    // non-trivial diagonals e+1 .. N-1

@@ -26,9 +26,9 @@ DTYPE = {"f32": 0, "f64": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 MODE = {"exact": 0, "paper": 1}
 PATH = {"auto": 0, "full": 1, "recompute": 2}
-NSTATS = 14
+NSTATS = 15
 STAT_NAMES = ["valid", "failed", "recomputed", "full_pass", "flat", "appends", "pass_events", "pass_hits",
-              "fp64_items", "passes", "partial", "mth_certified", "mth_recomputed", "mth_pruned"]
+              "fp64_items", "passes", "partial", "mth_certified", "mth_recomputed", "mth_pruned", "overflowed"]
 
 # (name, C type) of every function declared in include/valmod.h
 EXPORTS = ["valmod_plan", "valmod_workspace_bytes", "valmod_output_sizes", "valmod_series_layout",

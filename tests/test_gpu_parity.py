@@ -513,6 +513,41 @@ def test_paper_mode_motif_per_length_exact(oracle_mod, precision, p):
     assert rep["partial_entries"] == int(st[:, 10].sum())
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("cap", [0, 12])
+def test_paper_mode_rebuilds_from_profile_thresholds(oracle_mod, monkeypatch, precision, cap):
+    """A periodic series where the bound fails at every length, so that paper mode
+    rebuilds the partial profiles at every length. A rebuild takes its thresholds
+    from the profiles it replaces (an overflowed list keeps the best p of its
+    candidates for that); once a rebuild has run with them, one collecting pass
+    rebuilds the profiles when the last rebuild's overflowing lists are cheap to
+    recompute, and those owners are recomputed. cap 12 (test hook) makes hundreds
+    of lists overflow at every rebuild. The motif of every length stays exact, and
+    so does every computed entry."""
+    from oracle import compare
+
+    if cap:
+        monkeypatch.setenv("VALMOD_COLLECT_CAP", str(cap))
+    x = gen.sensor_like(5000, 97).astype(np.float32)
+    lo, hi = 40, 52
+    g = run_gpu(x, lo, hi, p=5, k_motifs=3, k_discords=3, precision=precision, mode="paper")
+    r = oracle_mod.valmod(x, lo, hi, k_motifs=3, k_discords=3)
+    rep = compare.check_paper_mode(x, lo, g, r, TOL64)
+    st = g["stats"]
+    _say(f"paper rebuilds {precision} cap {cap}: {dict(rep)}; full {st[:, 3].tolist()}, passes "
+         f"{st[:, 9].tolist()}, overflowed {st[:, 14].tolist()}, recomputed {st[:, 2].tolist()}")
+    assert rep["partial_entries"] == int(st[:, 10].sum())
+    rebuilt = [t for t in range(1, hi - lo + 1) if st[t, 3] == 1]
+    assert rebuilt, "the bound certified every length"
+    per_pass = 2 if precision == "fp32" else 1  # launches of one collecting pass (FP32: + the listed FP64 items)
+    if cap:
+        # hundreds of lists overflow at every rebuild: recomputing them would cost
+        # more than the pass for the exact neighbours, which every rebuild runs
+        assert all(st[t, 14] > 0 and st[t, 9] == 2 * per_pass for t in rebuilt)
+    else:
+        assert any(st[t, 9] == per_pass for t in rebuilt), "no rebuild ran a single collecting pass"
+
+
 def _check_mth(oracle_mod, x, lo, hi, g, k, m):
     """Top-k m-th discords per length and across lengths against the oracle:
     offsets equal except between ties, distances to the FP64 tolerance; the
@@ -596,9 +631,9 @@ def test_mth_discords_pruned_on_planted_discord(oracle_mod, precision):
 @pytest.mark.parametrize("cap", [3, 2])
 def test_mth_discords_overflowing_lists(oracle_mod, monkeypatch, cap):
     """Collecting lists of `cap` entries (test hook): at a rebuild most owners
-    overflow; with cap >= m their threshold bounds their m-th best matches and
-    they can be pruned, with cap < m they are recomputed. Rankings equal the
-    oracle's either way."""
+    overflow; with cap >= m the best m of their listed candidates bound their
+    m-th best matches and they can be pruned, with cap < m they are recomputed.
+    Rankings equal the oracle's either way."""
     monkeypatch.setenv("VALMOD_COLLECT_CAP", str(cap))
     x = gen.small_random_walk(1800, 98, np.float32)
     lo, hi, k, m = 28, 33, 3, 3
