@@ -426,17 +426,19 @@ __global__ void k_sweep(const double* __restrict__ xs, const double* __restrict_
   bool valid = false;
   double min_d = INFINITY, max_lb = 0.0;
   uint64_t kb = kEmptyKey;
-  if (owner) {
+  double rb = -2.0;
+  if (live) {
+    // every stored sum grows to L, also those of an owner flat at this length
+    // (one that is not flat at a later length reads them again)
     const int nh = hn[o];
     const double xo = xs[o], dx = xs[o + L - 1] - xo;
     const double Ao = A[o], io = invn[o];
-    double rb = -2.0;
     for (int r = 0; r < nh; ++r) {
       const int64_t c = hc[o * p + r];
       if (c >= N) continue;  // no window of length L at c (nor at any longer length)
       const double S = fma(dx, xs[c + L - 1] - xs[c], hS[o * p + r]);
       hS[o * p + r] = S;
-      if (iabs64(c - o) <= e || flat[c]) continue;
+      if (!owner || iabs64(c - o) <= e || flat[c]) continue;
       const double rho = rho_from_sum(S, Ao, A[c], L, io, invn[c]);
       const uint64_t k = make_key(rho, c);
       if (k < kb) {
@@ -444,6 +446,8 @@ __global__ void k_sweep(const double* __restrict__ xs, const double* __restrict_
         rb = rho;
       }
     }
+  }
+  if (owner) {
     max_lb = unstored_bound(o, base, sig, hbound, hsig, __longlong_as_double((long long)*rflat));
     if (kb != kEmptyKey) {
       // the stored minimum from a correlation evaluated directly (error <= margin):

@@ -228,4 +228,21 @@ def flat_at_base_copy(n: int, seed: int, b: int, L: int, flat_eps: float = 2.0 *
     return x, o, c, m
 
 
+def flat_between(n: int, seed: int, hold: int = 42, h: float = 5.68e-6,
+                 level: float = 0.5) -> Tuple[np.ndarray, int]:
+    """Sensor-like series with one owner window o that is not flat at the
+    shortest lengths, flat at intermediate ones and not flat again once it
+    reaches past a constant stretch: x[o] = level + h, x[o+1 .. o+hold-1] = level
+    (deviation h sqrt(L - 1) / L against the flat threshold 2^-20 max(1, |mean|)),
+    then the series resumes from `level`. With the defaults o is not flat for
+    L <= 34, flat for 35 <= L <= hold and not flat beyond. Returns (x, o)."""
+    x = sensor_like(n, SEED_BASE + 500 + seed)
+    o = n // 2
+    tail = x[o + hold:] - x[o + hold] + level + 0.3
+    x[o:o + hold] = level
+    x[o] = level + h
+    x[o + hold:] = tail
+    return x, o
+
+
 WORKLOADS = {1: config1, 2: config2, 3: config3, 5: config5}

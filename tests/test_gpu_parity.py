@@ -212,6 +212,33 @@ def test_partial_profiles_on_flat_segments(oracle_mod):
     compare.check_full(x, 20, g, r, TOL64)
 
 
+@pytest.mark.parametrize("mode,path", [("exact", "auto"), ("exact", "recompute"), ("paper", "auto")])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_owner_flat_at_intermediate_lengths(oracle_mod, mode, path, precision):
+    """An owner not flat at the base length, flat at the lengths after it and not
+    flat again once its window reaches past a constant stretch: the sweep grows its
+    stored sums at every length, so the later lengths (their sweeps, the m-lists
+    and the thresholds of a rebuild) read sums of the right length."""
+    from oracle import compare
+
+    x, o = gen.flat_between(4000, 0)
+    x = x.astype(np.float32)
+    lo, hi = 30, 50
+    flat_at = []
+    for L in range(lo, hi + 1):
+        w = x[o:o + L].astype(np.float64)
+        flat_at.append(bool(np.sqrt(((w - w.mean()) ** 2).mean()) <= 2.0 ** -20 * max(1.0, abs(w.mean()))))
+    assert not flat_at[0] and flat_at[40 - lo] and not flat_at[-1]  # the input is what the test is about
+    g = run_gpu(x, lo, hi, p=5, k_motifs=3, k_discords=3, precision=precision, mode=mode, path=path)
+    r = oracle_mod.valmod(x, lo, hi, k_motifs=3, k_discords=3)
+    if mode == "paper":
+        compare.check_paper_mode(x, lo, g, r, TOL64)
+    else:
+        compare.check_full(x, lo, g, r, TOL64)
+    st = g["stats"]
+    _say(f"flat in between {mode}/{path}/{precision}: full {st[:, 3].tolist()}, recomputed {st[:, 2].tolist()}")
+
+
 # --------------------------------------------------------------------------
 # FP32 recurrence with FP64 refresh: the FP32 pass only selects candidates
 # (threshold widened by its per-item rounding bound) and every reported value
