@@ -185,9 +185,11 @@ __global__ __launch_bounds__(kWave) void k_seed_append(const double* __restrict_
 // Merge of the collected candidates into the partial profile of each owner at
 // the new base length L: exact correlation of every candidate the pass
 // appended, top-`keep` by (correlation desc, index asc), the bound correlation
-// of the ones not kept, and the owner's best key. Owners whose list overflowed
-// (incomplete) or that collected nothing go to the recompute list with an empty
-// profile.
+// of the ones not kept, and the owner's best key. Owners that collected nothing
+// go to the recompute list with an empty profile; so do owners whose list
+// overflowed (incomplete), which keep the best `keep` of their listed
+// candidates as a profile whose bound certifies nothing (k_merge_big), or an
+// empty one when keep = 0.
 //
 // best_exact: `best` already holds every owner's exact neighbour (a
 // matrix-profile pass ran at this length), so an owner whose profile cannot be
