@@ -118,6 +118,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"],
                     help="headline path (the other one is timed beside it unless --no-compare)")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper-mode run beside an exact-mode headline")
     ap.add_argument("--compare-steps", type=int, default=1,
                     help="timed steps of the other precision (after its autotuning, no warm-up)")
     ap.add_argument("--k-motifs", type=int, default=0, help="top-k motif pairs (0: the workload's)")
@@ -171,11 +172,11 @@ def main():
 
     km = args.k_motifs or w.k_motifs
 
-    def timed(precision, steps, warmup):
+    def timed(precision, steps, warmup, mode=args.mode):
         graph = args.graph and precision == "fp64"
         v = native.Valmod(x, lo, hi, p=w.p, k_motifs=km, k_discords=w.k_discords,
                           excl_den=w.excl_den, precision=precision, path="full" if graph else args.path,
-                          lanes=args.lanes, graph=graph, mode=args.mode, mset_radius=args.mset,
+                          lanes=args.lanes, graph=graph, mode=mode, mset_radius=args.mset,
                           mset_cap=args.mset_cap, m_discords=args.m_discords)
         tune = None
         if not args.no_autotune:
@@ -237,6 +238,21 @@ def main():
             "speedup_of_headline": ms2 / ms,
             "max_abs_dn_diff": float(np.max(np.abs(a[fin] - b[fin]))) if fin.any() else 0.0,
             "idx_diff": int(np.sum(res["prof_idx"] != res2["prof_idx"])),
+        }
+    if not args.no_paper and args.mode == "exact" and batch is None and args.m_discords <= 1:
+        # Alg. ComputeSubMP as published on the same input: its time, how much of
+        # the profile it recomputes by row scans, and its per-length motifs (exact
+        # by the method's guarantee) against the exact run's
+        ms3, _, res3, tune3 = timed(args.precision, 1, 0, mode="paper")
+        st3 = res3["stats"].sum(axis=0)
+        nwin = sum(w.n - L + 1 for L in range(w.l_min, w.l_max + 1))
+        Ls = np.arange(w.l_min, w.l_max + 1)
+        out["paper_mode"] = {
+            "ms_per_step": ms3, "steps": 1, "warmup": 0, "autotune": tune3,
+            "full_passes": int(st3[3]), "recomputed_rows": int(st3[2]),
+            "recomputed_fraction": float(st3[2]) / nwin, "certified_fraction": float(st3[0]) / nwin,
+            "partial_entries": int(st3[10]),
+            "max_motif_dn_diff": float(np.nanmax(np.abs(res3["motif_d"][:, 0] - res["motif_d"][:, 0]) / np.sqrt(Ls))),
         }
     if not args.no_cpu and batch is None:
         lengths = sorted({w.l_min, (w.l_min + w.l_max) // 2, w.l_max})
