@@ -575,11 +575,11 @@ def test_paper_mode_rebuilds_from_profile_thresholds(oracle_mod, monkeypatch, pr
         assert any(st[t, 9] == per_pass for t in rebuilt), "no rebuild ran a single collecting pass"
 
 
-def _check_mth(oracle_mod, x, lo, hi, g, k, m):
+def _check_mth(oracle_mod, x, lo, hi, g, k, m, excl_den=4):
     """Top-k m-th discords per length and across lengths against the oracle:
     offsets equal except between ties, distances to the FP64 tolerance; the
     1st-discord column equals the plain discords."""
-    r = oracle_mod.mth_discords(x, lo, hi, k, m)
+    r = oracle_mod.mth_discords(x, lo, hi, k, m, excl_den=excl_den)
     for t in range(hi - lo + 1):
         L = lo + t
         for j in range(m):
@@ -592,9 +592,9 @@ def _check_mth(oracle_mod, x, lo, hi, g, k, m):
                     continue
                 assert abs(gd - rd) <= TOL64 * np.sqrt(L), (L, j, q, gd, rd)
                 if go != ro:  # a tie: the reported owner's (j+1)-th distance equals the oracle's
-                    d_own, _ = oracle_mod.mth_rows(x, L, m, rows=[go])
+                    d_own, _ = oracle_mod.mth_rows(x, L, m, rows=[go], excl_den=excl_den)
                     assert abs(d_own[0, j] - rd) <= TOL64 * np.sqrt(L), (L, j, q)
-                dd, _ = oracle_mod.mth_rows(x, L, m, rows=[go])
+                dd, _ = oracle_mod.mth_rows(x, L, m, rows=[go], excl_den=excl_den)
                 assert abs(oracle_mod.pair_dist(x, L, go, gn) - dd[0, j]) <= TOL64 * np.sqrt(L)
         np.testing.assert_allclose(g["mdiscord_d"][t, 0], g["discord_d"][t], rtol=0, atol=TOL64 * np.sqrt(L))
     np.testing.assert_allclose(g["g_mdiscord_d"], r["g_d"], rtol=0, atol=TOL64)
@@ -667,6 +667,51 @@ def test_mth_discords_overflowing_lists(oracle_mod, monkeypatch, cap):
     g = run_gpu(x, lo, hi, p=5, k_motifs=2, k_discords=k, m_discords=m, precision="fp32")
     _check_mth(oracle_mod, x, lo, hi, g, k, m)
     _say(f"overflowing lists cap {cap}: {_mth_stats(g)}")
+
+
+def _random_case(i):
+    """Configuration i of the seeded sweep over sizes, exclusion rules, p, k, m,
+    precisions, dtypes, paths and modes (inputs from the seeded generators)."""
+    rng = np.random.default_rng(20081344 + i)
+    kind = ["walk", "sensor", "planted"][i % 3]
+    n = int(rng.integers(300, 3001))
+    lo = int(rng.integers(8, 61))
+    hi = lo + int(rng.integers(1, 8))
+    if kind == "walk":
+        x = gen.small_random_walk(n, 500 + i)
+    elif kind == "sensor":
+        x = gen.sensor_like(n, 600 + i)
+    else:
+        x, _ = gen.small_planted(n, 700 + i, lo + 2, base="walk")
+    dtype = [np.float32, np.float64][int(rng.integers(0, 2))]
+    mode, path = [("exact", "auto"), ("exact", "full"), ("exact", "recompute"), ("paper", "auto")][i % 4]
+    p = [1, 3, 5, 12][int(rng.integers(0, 4))]
+    m = 1 if mode == "paper" else min(p, [1, 1, 2, 3][int(rng.integers(0, 4))])
+    return dict(x=x.astype(dtype), lo=lo, hi=hi, den=[2, 4][int(rng.integers(0, 2))], p=p,
+                k=int(rng.integers(1, 5)), m=m, precision=["fp64", "fp32"][int(rng.integers(0, 2))],
+                mode=mode, path=path)
+
+
+@pytest.mark.parametrize("i", range(32))
+def test_seeded_configuration_sweep(oracle_mod, i):
+    """Thirty-two seeded configurations mixing every option the boundary offers for
+    one series, each against the oracle (paper mode: its guarantees; m > 1: the
+    Top-k m-th discords as well)."""
+    from oracle import compare
+
+    c = _random_case(i)
+    x, lo, hi = c["x"], c["lo"], c["hi"]
+    _say(f"sweep {i}: n={x.shape[0]} {x.dtype} L={lo}..{hi} den={c['den']} p={c['p']} k={c['k']} m={c['m']} "
+         f"{c['precision']} {c['mode']}/{c['path']}")
+    g = run_gpu(x, lo, hi, p=c["p"], k_motifs=c["k"], k_discords=c["k"], excl_den=c["den"],
+                precision=c["precision"], mode=c["mode"], path=c["path"], m_discords=c["m"])
+    r = oracle_mod.valmod(x, lo, hi, excl_den=c["den"], k_motifs=c["k"], k_discords=c["k"])
+    if c["mode"] == "paper":
+        compare.check_paper_mode(x, lo, g, r, TOL64, excl_den=c["den"])
+    else:
+        compare.check_full(x, lo, g, r, TOL64, excl_den=c["den"])
+    if c["m"] > 1:
+        _check_mth(oracle_mod, x, lo, hi, g, c["k"], c["m"], excl_den=c["den"])
 
 
 def _check_motif_sets(oracle_mod, x, lo, hi, g, D, cap, k):
