@@ -229,6 +229,10 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
     delta = (T)dl_;
   }
   const int rows = (int)((i0 + a.H < rowEnd ? i0 + a.H : rowEnd) - i0);
+  // the bound in a vector register: the filter's fma then reads one scalar (the
+  // row's inverse norm) instead of two, which would need a move at every step
+  T delta_v = delta;
+  if constexpr (sizeof(T) == 4) asm volatile("v_mov_b32 %0, %1" : "=v"(delta_v) : "s"(delta));
   const int64_t dl = d0 + (int64_t)K * t;
 
   // co-moments at row i0 from FP64 anchors: C = S - A_i A_j / L
@@ -372,12 +376,21 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
           const int s = (q + u) % K;
           dq[q] = C[q] * (s < u ? Qinv[s] : Pinv[s]);
         }
+        T mx;
+        if constexpr (K == 8) {  // three-input maxima: 4 instructions for 8 values, 3 deep
+          const T m0 = __builtin_fmaxf(__builtin_fmaxf(dq[0], dq[1]), dq[2]);
+          const T m1 = __builtin_fmaxf(__builtin_fmaxf(dq[3], dq[4]), dq[5]);
+          const T m2 = __builtin_fmaxf(__builtin_fmaxf(dq[6], dq[7]), m0);
+          mx = __builtin_fmaxf(m1, m2);
+        } else {
 #pragma unroll
-        for (int w = 1; w < K; w *= 2)  // pairwise, to keep the dependency chain short
+          for (int w = 1; w < K; w *= 2)  // pairwise, to keep the dependency chain short
 #pragma unroll
-          for (int q = 0; q + w < K; q += 2 * w) dq[q] = __builtin_fmaxf(dq[q], dq[q + w]);
+            for (int q = 0; q + w < K; q += 2 * w) dq[q] = __builtin_fmaxf(dq[q], dq[q + w]);
+          mx = dq[0];
+        }
         any_pass = __builtin_expect(
-            __any(fma(dq[0], rinv[u], delta) >= __builtin_elementwise_minimum(tcol, rthr[u])), 0);
+            __any(fma(mx, rinv[u], delta_v) >= __builtin_elementwise_minimum(tcol, rthr[u])), 0);
       } else {
         // FP64: per-cell comparisons (this form allocates registers better
         // there) of rho + delta, the correlation raised by the item's rounding
