@@ -665,12 +665,12 @@ __global__ void k_mth_values(const double* __restrict__ A, const double* __restr
 // (column j, stride N0). The others get no entry (nn = -1) and, in ub, upper
 // bounds of those distances: the j-th stored candidate's distance widened by two
 // correlation error margins (its stored sum, and a later direct evaluation), or
-// +inf. With `fresh` (the profiles were rebuilt at this length), an owner whose
-// collecting list overflowed has more than cap >= m candidates whose exact
-// correlation is at least its threshold lowered by twice the largest rounding
-// bound of the pass's work items (dmax) and one FP32 ulp, which bounds all its m
-// best-match distances. mstate: bit 0 the m-list is certified, bit 1 the best
-// match is (the rule of k_sweep), bit 2 an owner (a non-flat window).
+// +inf. Any m real candidates bound the m best matches from above, so this also
+// holds for an owner whose collecting list overflowed at a rebuild (`fresh`: the
+// profiles were rebuilt at this length; such an owner stores the best of its
+// listed candidates, and its bound certifies nothing). mstate: bit 0 the m-list
+// is certified, bit 1 the best match is (the rule of k_sweep), bit 2 an owner
+// (a non-flat window).
 __global__ void k_mth_select(const double* __restrict__ A, const double* __restrict__ invn,
                              const double* __restrict__ sig, const uint8_t* __restrict__ flat,
                              const int32_t* __restrict__ hc, const double* __restrict__ hS,
