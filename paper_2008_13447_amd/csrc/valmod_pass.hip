@@ -339,15 +339,20 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
     // FP32 filter threshold of the lane: the running minimum of the thresholds of
     // the column slots the block has used so far (the current set at its start,
     // then each column as it enters), taken with the step's row threshold
-    T tcol = (T)0;
-    if constexpr (sizeof(T) == 4) {
+    T tcol;
+    {
       T m[K];
 #pragma unroll
       for (int q = 0; q < K; ++q) m[q] = Pthr[q];
 #pragma unroll
       for (int w = 1; w < K; w *= 2)
 #pragma unroll
-        for (int q = 0; q + w < K; q += 2 * w) m[q] = __builtin_elementwise_minimum(m[q], m[q + w]);
+        for (int q = 0; q + w < K; q += 2 * w) {
+          if constexpr (sizeof(T) == 4)
+            m[q] = __builtin_elementwise_minimum(m[q], m[q + w]);
+          else
+            m[q] = vmin(m[q], m[q + w]);
+        }
       tcol = m[0];
     }
     // Every block runs all K steps: rows past the segment or the series only meet
@@ -392,19 +397,21 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
         any_pass = __builtin_expect(
             __any(fma(mx, rinv[u], delta_v) >= __builtin_elementwise_minimum(tcol, rthr[u])), 0);
       } else {
-        // FP64: per-cell comparisons (this form allocates registers better
-        // there) of rho + delta, the correlation raised by the item's rounding
-        // bound with one rounding (fma), so a cell whose exact correlation
-        // reaches a threshold always passes (delta = 0 in matrix-profile mode)
-        bool pass = false;
+        // FP64: the same superset test (delta = 0 in matrix-profile mode, where
+        // the slow path raises thresholds during the block: the running minimum
+        // taken before only loosens the test)
+        if (u > 0) tcol = vmin(tcol, Qthr[u - 1]);
+        T dq[K];
 #pragma unroll
         for (int q = 0; q < K; ++q) {
           const int s = (q + u) % K;
-          const T inv = s < u ? Qinv[s] : Pinv[s];
-          const T th = s < u ? Qthr[s] : Pthr[s];
-          pass |= fma(C[q] * inv, rinv[u], delta) >= vmin(th, rthr[u]);
+          dq[q] = C[q] * (s < u ? Qinv[s] : Pinv[s]);
         }
-        any_pass = __any(pass);
+#pragma unroll
+        for (int w = 1; w < K; w *= 2)
+#pragma unroll
+          for (int q = 0; q + w < K; q += 2 * w) dq[q] = __builtin_fmax(dq[q], dq[q + w]);
+        any_pass = __builtin_expect(__any(fma(dq[0], rinv[u], delta) >= vmin(tcol, rthr[u])), 0);
       }
       if (MODE == MODE_MP && any_pass) {
         ++ev_steps;
