@@ -66,8 +66,8 @@ __global__ void k_anchor_grow(const double* __restrict__ xs, int64_t n, int L, i
 // and compares it with the lane's threshold: the minimum of the row's threshold
 // and those of the column slots the block has used (a superset of the cells that
 // pass per cell, at K multiplies and a max tree per step instead of K
-// multiplies, K minimums, K fmas and the max tree). The FP64 pass compares per
-// cell. A step whose wavefront has a passing cell goes to a slow path that
+// multiplies, K minimums, K fmas and K compares). The FP64 pass takes the same
+// test. A step whose wavefront has a passing cell goes to a slow path that
 // evaluates rho per cell and applies the mode's action:
 //   MODE_MP     : running best of each owner as a packed (distance, index) key
 //                 updated by 64-bit atomic min; thr = the running best's bound.
@@ -361,13 +361,12 @@ __global__ __launch_bounds__(kWave) void k_pass(const T* __restrict__ g_df, cons
 #pragma unroll
     for (int u = 0; u < K; ++u) {
       const int64_t i = ib + u;
-      // correlation of every cell against both owners' thresholds. FP32: the
-      // difference rho - min(thr_j, thr_i) with one rounding (fma), reduced by a
-      // max over the lane's cells (no per-cell mask traffic) and compared with
-      // -delta: fl(x) >= -delta whenever x >= -delta, so the filter keeps every
-      // cell whose FP32 correlation reaches the threshold lowered by the bound.
-      // The thresholds are never NaN (NaN-propagating minimum is exact here);
-      // the max ignores the NaN of flat and padded windows.
+      // the cells of the step against both owners' thresholds, one test per lane
+      // (no per-cell mask traffic): the largest C invn_j, scaled by invn_i and
+      // raised by the rounding bound with one rounding, against the smallest
+      // threshold the lane's cells can have. The thresholds are never NaN (the
+      // NaN-propagating minimum is exact here); the max ignores the NaN inverse
+      // norms of flat and padded windows in the FP32 copies.
       bool any_pass;
       if constexpr (sizeof(T) == 4) {
         // the largest C invn_j over the lane's cells, scaled by the row's inverse
