@@ -480,3 +480,23 @@ def test_valid_heaps_exact_with_candidates_flat_at_base(oracle_mod):
                 order = np.lexsort((np.arange(r.shape[0]), -r))[:p]
                 order = order[order < DL.shape[0]]
                 assert np.isclose(DL[w, order].min(), dL[w], rtol=1e-9, atol=1e-12), (L, p, w)
+
+
+def test_flat_between_fixture_and_profile(oracle_mod):
+    """The fixture of an owner flat only at intermediate lengths (gen.flat_between)
+    is what it claims under the oracle's flat rule, and at a length past the
+    constant stretch the oracle's profile row of that owner equals a numpy brute
+    force (the owner is an ordinary window again)."""
+    x, o = gen.flat_between(900, 1)
+    x = x.astype(np.float32).astype(np.float64)
+    flags = {L: bool(oracle_mod.stats(x, L)[2][o]) for L in range(30, 48)}
+    assert not any(flags[L] for L in range(30, 35))
+    assert all(flags[L] for L in range(35, 43))
+    assert not any(flags[L] for L in range(43, 48))
+    for L in (45, 47):
+        dp, ip = oracle_mod.profile(x, L, rows=[o])
+        d, i, D = _brute_mp(x, L)
+        _, _, fl = oracle_mod.stats(x, L)
+        row = D[o].copy()
+        row[fl[:row.shape[0]]] = np.inf
+        assert ip[0] == int(np.argmin(row)) and np.isclose(dp[0], row.min(), rtol=1e-12, atol=1e-12)
