@@ -12,7 +12,7 @@ from typing import Dict, Optional, Sequence
 
 import numpy as np
 
-from . import FLAT_EPS, pair_dists, profile
+from . import pair_dists, profile
 
 
 def _excl(L: int, den: int) -> int:
